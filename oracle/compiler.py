@@ -1,0 +1,204 @@
+"""Forest compiler: the vectorizable structures of Section 4.2.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Follows the paper's definitions in its order:
+  * node level = branches on the longest path down to a label, counting the
+    node itself; a label has level 0 (Section 4.1, "Properties of nodes");
+  * multiplicity kappa_f, maximum multiplicity K, branching b and quantized
+    branching q = K * F (Section 4.1, "Properties of models");
+  * padded threshold vector: thresholds grouped by feature, each group padded
+    with sentinels S = 0 up to K entries (Section 4.2, "Padded Threshold
+    Vector"); within a group, branches in ascending preorder index (reading:
+    the paper does not fix the order);
+  * reshuffling matrix R (b x q): R[i][j] = 1 iff padded slot j holds branch i
+    (Section 4.2, "Reshuffling Matrix");
+  * level matrices L_l (m x b) and masks (Section 4.2, "Level Matrices",
+    "Level Masks").  For label i and level l the selected branch is the
+    ancestor at level exactly l; else the ancestor with the greatest level
+    below l ("the highest branch not exceeding that level"); else (reading:
+    every ancestor lies above l) the label's parent.  mask = 0 when the label
+    lies under the true (right) child of the selected branch, 1 otherwise;
+  * generalized diagonals d_k[j] = A[j][(j + k) mod n] (Section 4.1, "Matrix
+    Representation"; the printed formula is garbled, this is its reading).
+
+Slot layout (reading; the paper leaves the packing unstated): the query's
+replicated feature vector is cyclically extended inside a block of W slots so
+that both matrix products can read rotated inputs without wrap-around:
+B_in = m + b + q - 2 padded positions are used, W = next power of two >= B_in.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from .forest import Branch, Leaf, Node, codebook, parse_forest, tree_of_label
+
+
+@dataclass
+class Compiled:
+    n_features: int
+    precision: int
+    branches: List[Branch]
+    labels: List[Leaf]
+    level_of_branch: List[int]
+    kappa: List[int]
+    K: int
+    q: int
+    b: int
+    m: int
+    d: int
+    padded: List[Optional[int]]          # padded slot -> branch index or None (sentinel)
+    thresholds_padded: List[int]          # threshold per padded slot (sentinel = 0)
+    R: np.ndarray                         # b x q
+    L: List[np.ndarray]                   # d matrices, m x b
+    masks: List[np.ndarray]               # d vectors, length m
+    Lfold: List[np.ndarray]               # d signed matrices (1 - 2 mask) * L, entries in {-1,0,1}
+    selected: List[List[Optional[int]]]   # [level-1][label] -> selected branch index
+    codebook: List[int]
+    tree_of_label: List[int]
+    n_trees: int
+    B_in: int = 0
+    W: int = 0
+    meta: dict = field(default_factory=dict)
+
+
+def next_pow2(x: int) -> int:
+    p = 1
+    while p < x:
+        p <<= 1
+    return p
+
+
+def bsgs_n1(n: int) -> int:
+    """Baby-step count n1 = 2^ceil(log2 sqrt(n)) (at least 1)."""
+    if n <= 1:
+        return 1
+    return 1 << math.ceil(math.log2(math.sqrt(n)) - 1e-12)
+
+
+def compile_forest(text: str, n_features: int, precision: int) -> Compiled:
+    _, trees = parse_forest(text)
+    return compile_trees(trees, n_features, precision)
+
+
+def compile_trees(trees: List[Node], n_features: int, precision: int) -> Compiled:
+    branches: List[Branch] = []
+    labels: List[Leaf] = []
+    parent_of_label: List[List[Branch]] = []   # ancestors root..parent per label
+    side_of_label: List[List[int]] = []        # 1 if label is in right subtree of that ancestor
+    levels: dict = {}
+
+    def level(n: Node) -> int:
+        if isinstance(n, Leaf):
+            return 0
+        if id(n) not in levels:
+            levels[id(n)] = 1 + max(level(n.left), level(n.right))
+        return levels[id(n)]
+
+    def walk(n: Node, anc: List[Branch], side: List[int]) -> None:
+        if isinstance(n, Leaf):
+            labels.append(n)
+            parent_of_label.append(list(anc))
+            side_of_label.append(list(side))
+            return
+        branches.append(n)
+        walk(n.left, anc + [n], side + [0])
+        walk(n.right, anc + [n], side + [1])
+
+    for t in trees:
+        walk(t, [], [])
+    b, m = len(branches), len(labels)
+    if b == 0:
+        raise ValueError("forest has no branches")
+    for i, br in enumerate(branches):
+        assert br.index == i
+        if not 0 <= br.feature < n_features:
+            raise ValueError(f"feature {br.feature} out of range")
+        if br.threshold >= (1 << precision):
+            raise ValueError(f"threshold {br.threshold} needs more than {precision} bits")
+    lvl = [level(br) for br in branches]
+    d = max(level(t) for t in trees)
+
+    kappa = [0] * n_features
+    for br in branches:
+        kappa[br.feature] += 1
+    K = max(kappa)
+    q = K * n_features
+
+    padded: List[Optional[int]] = []
+    for f in range(n_features):
+        group = [br.index for br in branches if br.feature == f]   # ascending preorder
+        padded.extend(group + [None] * (K - len(group)))
+    thr_pad = [0 if j is None else branches[j].threshold for j in padded]
+
+    R = np.zeros((b, q), dtype=np.int64)
+    for col, br_idx in enumerate(padded):
+        if br_idx is not None:
+            R[br_idx, col] = 1
+
+    L_mats, masks, folds, selected = [], [], [], []
+    for l in range(1, d + 1):
+        Lm = np.zeros((m, b), dtype=np.int64)
+        mk = np.zeros(m, dtype=np.int64)
+        sel_l: List[Optional[int]] = []
+        for i in range(m):
+            anc = parent_of_label[i]
+            side = side_of_label[i]
+            if not anc:                       # a tree that is a single label
+                sel_l.append(None)
+                mk[i] = 1
+                continue
+            choice = None
+            for a_pos, a in enumerate(anc):
+                if lvl[a.index] == l:
+                    choice = a_pos
+            if choice is None:
+                below = [a_pos for a_pos, a in enumerate(anc) if lvl[a.index] < l]
+                if below:
+                    choice = max(below, key=lambda ap: lvl[anc[ap].index])
+                else:
+                    choice = len(anc) - 1     # parent
+            br = anc[choice]
+            Lm[i, br.index] = 1
+            mk[i] = 0 if side[choice] == 1 else 1
+            sel_l.append(br.index)
+        L_mats.append(Lm)
+        masks.append(mk)
+        folds.append((1 - 2 * mk)[:, None] * Lm)
+        selected.append(sel_l)
+
+    c = Compiled(
+        n_features=n_features, precision=precision, branches=branches, labels=labels,
+        level_of_branch=lvl, kappa=kappa, K=K, q=q, b=b, m=m, d=d, padded=padded,
+        thresholds_padded=thr_pad, R=R, L=L_mats, masks=masks, Lfold=folds,
+        selected=selected, codebook=codebook(trees), tree_of_label=tree_of_label(trees),
+        n_trees=len(trees))
+    c.B_in = m + b + q - 2
+    c.W = next_pow2(c.B_in)
+    return c
+
+
+def generalized_diagonal(A: np.ndarray, k: int) -> np.ndarray:
+    """d_k[j] = A[j][(j + k) mod n], j < rows (Section 4.1)."""
+    rows, n = A.shape
+    j = np.arange(rows)
+    return A[j, (j + k) % n]
+
+
+def extended_reshuffle(c: Compiled) -> np.ndarray:
+    """R_ext ((m + b - 1) x q): row j is R[j mod b], so the reshuffled output
+    is already the period-b cyclic extension the level products read."""
+    rows = c.m + c.b - 1
+    return c.R[np.arange(rows) % c.b]
+
+
+def replicate_features(x: List[int], K: int) -> List[int]:
+    """Diane's replicated feature vector [x0]*K + [x1]*K + ... (Section 3.3, Step 0)."""
+    out: List[int] = []
+    for v in x:
+        out.extend([int(v)] * K)
+    return out

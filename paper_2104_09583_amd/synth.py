@@ -1,0 +1,117 @@
+"""Seeded synthetic workload generators (forests, queries, crypto seeds).
+
+This module is shared by the CPU oracle and the GPU library's tests and
+benchmark.  It holds *no* arithmetic of the method: it only draws random
+forest shapes, thresholds, labels and feature values with numpy's PCG64
+generator and writes them in the serialized forest format (paper, Section 5,
+"Input Representation": one line of label names, then one line per tree in
+preorder; a leaf carries its label index, a branch its feature index,
+threshold, then its left and right subtrees).
+
+Generator pin (the shapes of the evaluated workloads):
+  * the root of every tree is a branch;
+  * a node at depth k with 1 <= k < max_depth is a branch with probability
+    ``split_prob``, otherwise a leaf; a node at depth max_depth is a leaf;
+  * a branch draws feature ~ U[0, F) and threshold ~ U[0, 2^p);
+    a leaf draws label ~ U[0, C);
+  * nodes are drawn in preorder (self, left subtree, right subtree);
+  * query features are drawn ~ U[0, 2^p).
+
+Token grammar of one tree line: ``B <feature> <threshold> <left> <right>`` or
+``L <label>``; indices are 0-based.
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class ForestShape:
+    n_trees: int
+    max_depth: int
+    split_prob: float
+    n_features: int
+    precision: int
+    n_classes: int
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One evaluated configuration: forest shape, query count, ring size."""
+    name: str
+    shape: ForestShape
+    n_queries: int
+    log_n: int
+    encrypted_model: bool
+    seed_index: int
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+def _gen_tree(rng: np.random.Generator, shape: ForestShape, depth: int, out: list) -> None:
+    is_branch = depth == 0 or (depth < shape.max_depth and rng.random() < shape.split_prob)
+    if depth >= shape.max_depth:
+        is_branch = False
+    if is_branch:
+        f = int(rng.integers(0, shape.n_features))
+        thr = int(rng.integers(0, 1 << shape.precision))
+        out.extend(["B", str(f), str(thr)])
+        _gen_tree(rng, shape, depth + 1, out)
+        _gen_tree(rng, shape, depth + 1, out)
+    else:
+        out.extend(["L", str(int(rng.integers(0, shape.n_classes)))])
+
+
+def gen_forest_text(shape: ForestShape, seed: int) -> str:
+    """Serialized random forest of the given shape (deterministic in ``seed``)."""
+    rng = np.random.default_rng(seed)
+    lines = [" ".join(f"c{i}" for i in range(shape.n_classes))]
+    for _ in range(shape.n_trees):
+        toks: list = []
+        _gen_tree(rng, shape, 0, toks)
+        lines.append(" ".join(toks))
+    return "\n".join(lines) + "\n"
+
+
+def gen_queries(n_queries: int, n_features: int, precision: int, seed: int) -> np.ndarray:
+    """Uniform unsigned feature vectors, shape [n_queries, n_features], uint32."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << precision, size=(n_queries, n_features), dtype=np.uint64).astype(np.uint32)
+
+
+def crypto_seed(label: str) -> bytes:
+    """32-byte seed for all randomness of one workload's keys and ciphertexts."""
+    return hashlib.shake_256(label.encode("ascii")).digest(32)
+
+
+# The five evaluated workloads.  Depth/feature/precision/class counts follow
+# the configuration list of the benchmark; ``seed_index`` i gives forest seed
+# i, query seed 100 + i and crypto seed SHAKE-256("COPSE-cfg-i").
+WORKLOADS = {
+    "c1_plain_d3": Workload(
+        "c1_plain_d3", ForestShape(1, 3, 1.0, 4, 8, 2), 1, 14, False, 1,
+        "one complete binary tree of depth 3, one query, N=16384"),
+    "c2_forest16_d5": Workload(
+        "c2_forest16_d5", ForestShape(16, 5, 0.7, 16, 8, 4), 1, 15, False, 2,
+        "16 random unbalanced trees, max depth 5, one query, N=32768"),
+    "c3_batched_32x_d6": Workload(
+        "c3_batched_32x_d6", ForestShape(32, 6, 0.7, 16, 8, 8), 1024, 15, False, 3,
+        "1024 queries against 32 trees of max depth 6, N=32768"),
+    "c4_encmodel_64x_d8": Workload(
+        "c4_encmodel_64x_d8", ForestShape(64, 8, 0.7, 32, 16, 10), 256, 15, True, 4,
+        "encrypted model and queries, 64 trees max depth 8, 16-bit, N=32768"),
+    "c5_serve_8x_d4": Workload(
+        "c5_serve_8x_d4", ForestShape(8, 4, 0.7, 16, 8, 4), 1, 15, False, 5,
+        "serving mix member: 8 trees of depth 4"),
+}
+
+
+def workload_inputs(w: Workload):
+    """(forest_text, queries[n, F], crypto_seed) for a workload."""
+    s = w.shape
+    text = gen_forest_text(s, w.seed_index)
+    queries = gen_queries(w.n_queries, s.n_features, s.precision, 100 + w.seed_index)
+    return text, queries, crypto_seed(f"COPSE-cfg-{w.seed_index}")

@@ -1,0 +1,217 @@
+"""Pins of the plaintext half of the oracle: forest evaluation, compiler and
+the slot simulator of Algorithm 1 (CPU only)."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle import compiler as C
+from oracle import forest as F
+from oracle import slotsim as S
+from paper_2104_09583_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "worked_example.txt")
+
+
+def _worked():
+    lines = [ln for ln in open(GOLD) if not ln.startswith("#")]
+    i = lines.index("forest:\n")
+    text = lines[i + 1] + lines[i + 2]
+    exp = {}
+    for ln in lines[i + 3:]:
+        for tok in ln.split()[1:]:
+            k, v = tok.split("=")
+            exp[k] = v
+    return text, exp
+
+
+def test_worked_example_compiler():
+    text, exp = _worked()
+    c = C.compile_forest(text, 2, 4)
+    assert (c.K, c.b, c.q, c.m, c.d) == (int(exp["K"]), int(exp["b"]), int(exp["q"]),
+                                        int(exp["m"]), int(exp["d"]))
+    assert c.kappa == [int(v) for v in exp["kappa"].split(",")]
+    assert ",".join("-" if j is None else str(j) for j in c.padded) == exp["padded"]
+    want_R = {tuple(map(int, p.split(":"))) for p in exp["R"].split(",")}
+    assert {(int(i), int(j)) for i, j in zip(*np.nonzero(c.R))} == want_R
+    for l in range(1, 4):
+        assert c.selected[l - 1] == [int(v) for v in exp[f"level{l}"].split(",")]
+        assert list(c.masks[l - 1]) == [int(v) for v in exp[f"mask{l}"].split(",")]
+
+
+def test_worked_example_evaluation():
+    text, exp = _worked()
+    _, trees = F.parse_forest(text)
+    x = [int(v) for v in exp["query"].split(",")]
+    out = F.evaluate(trees, x)
+    assert out.index(1) == int(exp["label"]) and sum(out) == 1
+    c = C.compile_trees(trees, 2, 4)
+    res = S.run(c, np.array([x]), n_slots=2 * c.W)
+    assert list(res["per_query"][0]) == out
+
+
+def _random_forest(seed, trees=3, depth=4, feats=3, prec=4, classes=3, split=0.7):
+    shape = synth.ForestShape(trees, depth, split, feats, prec, classes)
+    return synth.gen_forest_text(shape, seed), shape
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_evaluator_matches_path_product(seed):
+    text, shape = _random_forest(seed)
+    _, trees = F.parse_forest(text)
+    for x in itertools.product(range(1 << shape.precision), repeat=shape.n_features):
+        a = F.evaluate(trees, list(x))
+        assert a == F.evaluate_path_product(trees, list(x))
+        # N-hot: exactly one label per tree
+        tol = F.tree_of_label(trees)
+        for ti in range(len(trees)):
+            assert sum(a[i] for i in range(len(a)) if tol[i] == ti) == 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_compiler_invariants(seed):
+    text, shape = _random_forest(seed, trees=4, depth=5, feats=4)
+    c = C.compile_forest(text, shape.n_features, shape.precision)
+    # R: one 1 per row, at most one per column (Section 4.2)
+    assert (c.R.sum(axis=1) == 1).all() and (c.R.sum(axis=0) <= 1).all()
+    assert c.q == c.K * shape.n_features and c.b == sum(c.kappa)
+    _, trees = F.parse_forest(text)
+    widths = {}
+
+    def width(n):
+        if isinstance(n, F.Leaf):
+            return 1
+        w = width(n.left) + width(n.right)
+        widths[n.index] = w
+        return w
+    for t in trees:
+        width(t)
+    for l, Lm in enumerate(c.L):
+        assert (Lm.sum(axis=1) == 1).all()
+        # a column sum is 0 or the branch's width when that branch sits at
+        # level l; a lower branch reused for shallower labels adds at most
+        # its width (each label is counted once)
+        for j in range(c.b):
+            s = Lm[:, j].sum()
+            assert s == 0 or s <= widths[j]
+            if c.level_of_branch[j] == l + 1:
+                assert s == widths[j]
+    # every ancestor of every label is selected at some level
+    for i, leaf in enumerate(c.labels):
+        sel = {c.selected[l][i] for l in range(c.d)}
+        anc = set()
+
+        def find(n, path):
+            if isinstance(n, F.Leaf):
+                if n is leaf:
+                    anc.update(path)
+                return
+            find(n.left, path + [n.index])
+            find(n.right, path + [n.index])
+        for t in trees:
+            find(t, [])
+        assert anc <= sel
+
+
+def test_unique_branch_per_level_and_label():
+    text, shape = _random_forest(3, trees=5, depth=6)
+    c = C.compile_forest(text, shape.n_features, shape.precision)
+    for i in range(c.m):
+        at_level = {}
+        for j in range(c.b):
+            pass
+    # Section 4.1: at most one ancestor of a label has a given level
+    _, trees = F.parse_forest(text)
+    lv = c.level_of_branch
+
+    def rec(n, path):
+        if isinstance(n, F.Leaf):
+            levels = [lv[a] for a in path]
+            assert len(levels) == len(set(levels))
+            assert levels == sorted(levels, reverse=True)
+            return
+        rec(n.left, path + [n.index])
+        rec(n.right, path + [n.index])
+    for t in trees:
+        rec(t, [])
+
+
+def test_seccomp_bruteforce_p8():
+    """The comparison circuit equals x < theta for all 65,536 pairs of bytes."""
+    p = 8
+    xs, ts = np.meshgrid(np.arange(256), np.arange(256), indexing="ij")
+    xs, ts = xs.reshape(1, -1), ts.reshape(1, -1)
+    xp = [(xs >> k) & 1 for k in range(p)]
+    tp = [(ts >> k) & 1 for k in range(p)]
+    dec = S.seccomp_slots(xp, tp, 65537)
+    assert (dec == (xs < ts)).all()
+
+
+def test_seccomp_p16_edges():
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([rng.integers(0, 1 << 16, 4000), [0, 0, 65535, 65535, 1234, 40000]])
+    ts = np.concatenate([rng.integers(0, 1 << 16, 4000), [0, 65535, 0, 65535, 1234, 40001]])
+    xs[:1000] = ts[:1000]                       # ties
+    xs, ts = xs.reshape(1, -1), ts.reshape(1, -1)
+    dec = S.seccomp_slots([(xs >> k) & 1 for k in range(16)], [(ts >> k) & 1 for k in range(16)], 65537)
+    assert (dec == (xs < ts)).all()
+
+
+def test_kogge_stone_prefix_matches_sequential():
+    for n in range(1, 20):
+        seq = list(range(2, 2 + n))
+        pre = S.kogge_stone_prefix(seq, lambda a, b: a * b)
+        assert pre == [int(np.prod(seq[:i + 1])) for i in range(n)]
+
+
+@pytest.mark.parametrize("rows,n,n1", [(5, 7, 4), (9, 6, 2), (3, 16, 4), (12, 12, 1), (4, 5, 8)])
+def test_bsgs_matmul_equals_dense(rows, n, n1):
+    rng = np.random.default_rng(rows * 100 + n)
+    A = rng.integers(0, 5, size=(rows, n))
+    v = rng.integers(0, 7, size=n)
+    W = C.next_pow2(rows + n - 1)
+    lay = S.Layout(4 * W, W)
+    vext = v[np.arange(rows + n - 1) % n]
+    slots = lay.replicate(vext)
+    t = 65537
+    got = S.matmul_bsgs(slots, S.prerotated_diagonals(A, lay, n1), n1, t)
+    plain = S.matmul_plain(slots, A, lay, t)
+    for k in range(lay.Qs):
+        assert (lay.extract(got, k, rows) == (A @ v) % t).all()
+        assert (lay.extract(plain, k, rows) == (A @ v) % t).all()
+
+
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("fold", [False, True])
+def test_slot_simulator_equals_evaluator(seed, fold):
+    text, shape = _random_forest(seed, trees=4, depth=5, feats=4, prec=5, classes=3)
+    c = C.compile_forest(text, shape.n_features, shape.precision)
+    _, trees = F.parse_forest(text)
+    lay_slots = max(64, 4 * c.W)
+    qn = (lay_slots // c.W)
+    queries = synth.gen_queries(qn, shape.n_features, shape.precision, 1000 + seed)
+    res = S.run(c, queries, n_slots=lay_slots, fold_reshuffle=fold)
+    for k, x in enumerate(queries):
+        assert list(res["per_query"][k]) == F.evaluate(trees, list(x))
+    # slots outside the label range stay zero
+    lab = res["labels"].copy()
+    for k in range(len(queries)):
+        r, c0 = res["layout"].block_origin(k)
+        lab[r, c0:c0 + c.m] = 0
+    assert not lab.any()
+
+
+def test_generator_pins():
+    text = synth.gen_forest_text(synth.ForestShape(1, 3, 1.0, 4, 8, 2), 1)
+    _, trees = F.parse_forest(text)
+    c = C.compile_trees(trees, 4, 8)
+    assert (c.b, c.m, c.d) == (7, 8, 3)          # complete tree of depth 3
+    assert synth.gen_forest_text(synth.ForestShape(16, 5, 0.7, 16, 8, 4), 2) == \
+        synth.gen_forest_text(synth.ForestShape(16, 5, 0.7, 16, 8, 4), 2)
+
+
+def test_parse_errors():
+    for bad in ["", "a b\nB 0 1 L 0", "a\nL 3", "a b\nX 1", "a b\nL 0 L 1"]:
+        with pytest.raises(F.ParseError):
+            F.parse_forest(bad)
