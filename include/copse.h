@@ -1,0 +1,319 @@
+/*
+ * copse.h -- C ABI of the MI355X (gfx950) library for vectorized secure
+ * decision-forest inference (COPSE, Malik et al., PLDI'21).
+ *
+ * The operations follow the paper's statement of the problem (Section 3.1,
+ * "The Players"; Section 3.2, "The Workflow"; Section 5, "COPSE Runtime"):
+ * the model owner compiles a forest, the data owner generates keys and
+ * encrypts feature vectors, the server evaluates Algorithm 1 (Section 4.3)
+ * on ciphertexts, and the data owner decrypts the N-hot label vector
+ * (Section 4.1, "Classification Result").  The encryption scheme is BGV over
+ * Z_Q[X]/(X^N + 1) with an RNS prime chain (the paper uses HElib's BGV,
+ * Section 5); every choice that decides ciphertext bits is fixed in the
+ * comments below so an independent implementation reproduces them.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: COPSE_OK (0) or a negative COPSE_E* code; the message of
+ *     the calling thread's last failure is returned by copse_last_error().
+ *   - Handles are opaque, created by the library and released by the
+ *     matching copse_*_destroy (NULL is accepted and ignored).
+ *   - Array arguments are HOST pointers borrowed for the duration of the
+ *     call unless stated otherwise; caller-sized output buffers are filled
+ *     up to the stated size.
+ *   - Ciphertexts, keys and encoded models live in device (HBM) memory of the
+ *     context's GPU and stay resident until destroyed.
+ *   - Work is enqueued on the context's HIP stream; entry points that return
+ *     host data synchronize that stream before returning.
+ *   - Not thread-safe per context: calls on one context must not overlap.
+ *
+ * Ciphertext export format (copse_cts_export / copse_cts_import): per
+ * ciphertext, a header of 4 uint64 words {n_polys, level, N, reserved=0}
+ * followed by n_polys x (level+1) x N coefficients, each the residue in
+ * [0, q_i) of the coefficient-domain polynomial modulo prime q_i; polys
+ * outermost, then limbs q_0..q_level, then coefficients 0..N-1.
+ */
+#ifndef COPSE_H
+#define COPSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COPSE_OK 0
+#define COPSE_EINVAL (-1)     /* malformed input, bad size, out-of-range value  */
+#define COPSE_ECAPACITY (-2)  /* layout exceeds N/2 slots or circuit exceeds chain */
+#define COPSE_ENOMEM (-3)     /* device or host allocation failed / HBM budget    */
+#define COPSE_EDEVICE (-4)    /* HIP runtime error                               */
+#define COPSE_ENOISE (-5)     /* decryption noise check failed                   */
+#define COPSE_EKEY (-6)       /* a needed Galois or relinearization key is absent */
+#define COPSE_ETIMEOUT (-7)   /* copse_server_wait timed out                     */
+
+typedef struct copse_ctx copse_ctx;
+typedef struct copse_keys copse_keys;
+typedef struct copse_compiled copse_compiled;
+typedef struct copse_model copse_model;
+typedef struct copse_cts copse_cts;
+typedef struct copse_server copse_server;
+
+/*
+ * Ring and prime chain.  Ring dimension N = 2^log_n, plaintext modulus t
+ * (must satisfy t = 1 mod 2N so there are N slots).  Every prime q is
+ * q = k (2 N t) + 1 (so dropping q in a modulus switch keeps the plaintext:
+ * q^-1 = 1 mod t) and q < 2^50 (residues are held exactly in fp64).
+ * Candidates k(2Nt)+1 are scanned downward in k below exclusive bounds:
+ *   1. alpha special primes p_0 > p_1 > ... below special_max;
+ *   2. data primes q_1 > ... > q_L (L = n_data_primes - 1) below data_max,
+ *      skipping primes already taken;
+ *   3. q_0 below q0_max, skipping primes already taken.
+ * Primality: Miller-Rabin with witnesses 2..37 (exact for 64-bit inputs).
+ * A key-switching digit is alpha consecutive data primes (q_0..q_{alpha-1},
+ * ...); a modulus switch drops the highest-index data prime.
+ */
+typedef struct {
+  uint32_t log_n;
+  uint64_t t;
+  uint32_t n_data_primes;
+  uint64_t q0_max;
+  uint64_t data_max;
+  uint32_t alpha;
+  uint64_t special_max;
+  int device;            /* HIP device ordinal */
+} copse_params;
+
+/* Public facts about a compiled forest that the data owner and the server
+ * may learn (Section 7.1, Tables 3-4): K is revealed so the query can be
+ * laid out; q, b, m, d and the slot geometry fix the ciphertext shapes. */
+typedef struct {
+  uint32_t n_features;   /* F */
+  uint32_t precision;    /* p, bits per value */
+  uint32_t K;            /* maximum feature multiplicity */
+  uint32_t q;            /* quantized branching K*F */
+  uint32_t b;            /* branches */
+  uint32_t m;            /* labels (output slots per query) */
+  uint32_t d;            /* levels */
+  uint32_t n_trees;
+  uint32_t block_w;      /* W: slots per query block, next pow2 >= m+b+q-2 */
+  uint32_t queries_per_ct;/* N / W */
+  uint32_t n1_R;         /* baby steps of the reshuffle product */
+  uint32_t n1_L;         /* baby steps of the level products */
+  uint32_t fold;         /* 1: level matrices composed with R (one product less) */
+  uint32_t depth;        /* modulus switches the evaluation consumes */
+  uint32_t log_n;        /* ring the layout was made for */
+} copse_public_meta;
+
+/* ---------------------------------------------------------------- context */
+/* Creates the prime chain and device tables.  Errors: EINVAL (t not 1 mod
+ * 2N, bounds too small, alpha 0, more than 48 primes), EDEVICE. */
+int copse_ctx_create(const copse_params* params, copse_ctx** out);
+void copse_ctx_destroy(copse_ctx* ctx);
+/* Writes the primes (q_0..q_L then p_0..p_{alpha-1}) to out[0..cap); *n gets
+ * the total count.  EINVAL if cap is too small. */
+int copse_ctx_primes(const copse_ctx* ctx, uint64_t* out, size_t cap, size_t* n);
+/* The HIP stream (hipStream_t) the context enqueues on. */
+void* copse_ctx_stream(copse_ctx* ctx);
+/* Makes the context enqueue on `stream` (a hipStream_t, or NULL for the
+ * context's own stream).  The caller keeps ownership of the stream. */
+int copse_ctx_set_stream(copse_ctx* ctx, void* stream);
+/* Blocks until all work enqueued on the context's stream has finished. */
+int copse_ctx_sync(copse_ctx* ctx);
+/* Device bytes currently held by the context's pool (in use + cached). */
+size_t copse_ctx_device_bytes(const copse_ctx* ctx);
+
+/* ---------------------------------------------------------------- compile */
+/*
+ * Forest compiler (model owner; Section 4.2 and Section 5, "Input
+ * Representation").  text: first line label names, then one line per tree in
+ * preorder tokens "B <feature> <threshold> <left> <right>" or "L <label>",
+ * 0-based.  Branch i decides x[f_i] < t_i (true = right child).  Produces the
+ * padded threshold vector (features in order, each group of K slots in
+ * ascending branch preorder, sentinel 0), the reshuffle matrix R, the level
+ * matrices and masks (label i, level l selects the ancestor at level l,
+ * else the ancestor of greatest level below l, else the parent; mask 0 iff
+ * the label lies under the selected branch's true child).
+ * log_n fixes the slot geometry; n1_R / n1_L = 0 choose 2^ceil(log2 sqrt n).
+ * Errors: EINVAL (grammar, feature >= n_features, threshold >= 2^precision,
+ * no branches), ECAPACITY (W > N/2).
+ */
+int copse_forest_compile(const char* text, size_t len, uint32_t n_features, uint32_t precision,
+                         uint32_t log_n, int fold, uint32_t n1_R, uint32_t n1_L,
+                         copse_compiled** out, copse_public_meta* meta);
+void copse_compiled_destroy(copse_compiled* c);
+/* Left rotations (slot offsets) whose Galois keys evaluation needs. */
+int copse_compiled_rotations(const copse_public_meta* meta, int32_t* out, size_t cap, size_t* n);
+
+/* ---------------------------------------------------------------- keys */
+/*
+ * Key generation (data owner).  All randomness comes from SHAKE-256 streams
+ * SHAKE256(seed[32] || domain || le64(object) || le32(limb)) read from the
+ * start: uniform mod q = 8 bytes LE masked to bitlen(q), accepted if < q;
+ * ternary = one byte, 255 rejected, b mod 3 -> {0, 1, -1}; error = centered
+ * binomial eta=21 from 6 bytes LE (popcount of bits 0..20 minus bits
+ * 21..41).  s: ternary, domain "sk.s".  pk = (-a s + t e, a) over Q_L with
+ * a per limb "pk.a", e "pk.e".  A key-switching key from s' has, per digit
+ * j, a_j uniform over P Q_L ("ksk.a", object key_id*256+j, limb = global
+ * prime index), e_j ("ksk.e"), b_j = -a_j s + t e_j + g_j s' with
+ * g_j = P mod q_i on the limbs of digit j, 0 elsewhere.  key_id 0 is the
+ * relinearization key (s' = s^2); a rotation key has key_id = its Galois
+ * element 5^r mod 2N (s' = s(X^g)).
+ * rots: left rotations r (0 < r < N/2) that need keys; relin: nonzero to make
+ * the relinearization key.
+ */
+int copse_keygen(copse_ctx* ctx, const uint8_t seed[32], const int32_t* rots, size_t n_rots,
+                 int relin, copse_keys** out);
+void copse_keys_destroy(copse_keys* k);
+/* Copy without the secret key (what the server receives). */
+int copse_keys_export_eval(copse_ctx* ctx, const copse_keys* k, copse_keys** out);
+/* Device bytes held by the keys. */
+size_t copse_keys_bytes(const copse_keys* k);
+
+/* ---------------------------------------------------------------- model */
+/*
+ * Encodes the compiled model (server-held plaintext model, encrypt_model=0)
+ * or encrypts it under `keys` (encrypt_model=1, seed for its randomness).
+ * Plaintext slot vectors are encoded as m(X) with slot (r, j) = m(zeta^e),
+ * e = 5^j (row 0) or -5^j (row 1) mod 2N, zeta = 3^((t-1)/2N) mod t, and
+ * coefficients lifted centered into [-(t-1)/2, (t-1)/2].  The model stays
+ * resident on the device.  Errors: ECAPACITY (circuit deeper than the
+ * chain), EINVAL (layout made for another ring), EKEY.
+ */
+int copse_model_encode(copse_ctx* ctx, const copse_compiled* c, const copse_keys* keys,
+                       int encrypt_model, const uint8_t seed[32], copse_model** out);
+void copse_model_destroy(copse_model* m);
+size_t copse_model_bytes(const copse_model* m);
+
+/* ---------------------------------------------------------------- queries */
+/*
+ * Data owner: replicates each feature K times (feature-major), slices the p
+ * bit-planes (plane k = bit k), extends each block cyclically (slot s of a
+ * block holds padded position s mod q for s < m+b+q-2, 0 beyond), puts
+ * query i of the group in block i (row i / (N/2W), offset (i mod N/2W) W),
+ * and encrypts each plane at the top level: (pk0 u + t e0 + m,
+ * pk1 u + t e1), u ternary "enc.u", e0 "enc.e0", e1 "enc.e1", object
+ * (1 << 56) | (group << 32) | plane.  features: [n_queries][n_features]
+ * values < 2^p; n_queries <= queries_per_ct.  Result: p ciphertexts.
+ */
+int copse_query_encrypt(copse_ctx* ctx, const copse_keys* keys, const copse_public_meta* meta,
+                        const uint32_t* features, size_t n_queries, const uint8_t seed[32],
+                        uint32_t group, copse_cts** out);
+void copse_cts_destroy(copse_cts* c);
+size_t copse_cts_count(const copse_cts* c);
+int copse_cts_level(const copse_cts* c, size_t i);
+
+/* ---------------------------------------------------------------- evaluate */
+/*
+ * Server: Algorithm 1 on one query group: SecComp of the p planes with the
+ * thresholds, the reshuffle product, d level products with the masks, and
+ * the product tree; result switched to q_0 (one ciphertext).  Never takes
+ * the secret key: `keys` may be an evaluation-only copy.  Schedule (fixes
+ * every ciphertext bit): operands at different levels are switched down one
+ * prime at a time; sums switch every term to the lowest level first; a
+ * ciphertext product is tensor, relinearize, switch; a plaintext product
+ * layer is followed by one switch; MatMul = hoisted baby rotations, per
+ * giant group the sum of products with pre-rotated diagonals (relinearized
+ * once per group when the diagonals are encrypted), a giant rotation, the
+ * sum, one switch; the mask is added after that switch; MultAll pairs
+ * (0,1),(2,3),... carrying an odd last one up.  Every rotation is in hoisted
+ * form: ModUp(c1), the automorphism on each digit, inner product with the
+ * key, ModDown, plus the automorphism of c0.  Errors: EKEY, EINVAL.
+ */
+int copse_evaluate(copse_ctx* ctx, const copse_model* model, const copse_keys* keys,
+                   const copse_cts* query, copse_cts** result);
+/* Same for several query groups at once: the groups' ciphertexts travel
+ * through every step together (one launch per step for all of them).
+ * queries[i] and results[i] belong to group i.  Each result is bit-identical
+ * to copse_evaluate on that group alone. */
+int copse_evaluate_batch(copse_ctx* ctx, const copse_model* model, const copse_keys* keys,
+                         const copse_cts* const* queries, size_t n_groups, copse_cts** results);
+
+/* ---------------------------------------------------------------- decrypt */
+/*
+ * Data owner: decrypts a level-0 result, checks the noise (the centered
+ * phase must stay below q_0 / 2^11, else ENOISE), decodes the slots and
+ * writes bits[i*m + j] = label j of query i (0/1; any other value -> ENOISE)
+ * for i < n_queries.  cap = size of bits.
+ */
+int copse_decrypt_labels(copse_ctx* ctx, const copse_keys* keys, const copse_public_meta* meta,
+                         const copse_cts* result, size_t n_queries, uint8_t* bits, size_t cap);
+
+/* ---------------------------------------------------------------- raw ciphertext ops
+ * Used by the parity tests and the benchmark to check each step alone. */
+/* Encrypts an arbitrary slot vector slots[2*(N/2)] (values mod t, row-major)
+ * at `level` with encryption object `obj`. */
+int copse_encrypt_slots(copse_ctx* ctx, const copse_keys* keys, const uint64_t* slots,
+                        int level, const uint8_t seed[32], uint64_t obj, copse_cts** out);
+/* Decrypts ciphertext i of c (any level) into slots[2*(N/2)] mod t. */
+int copse_decrypt_slots(copse_ctx* ctx, const copse_keys* keys, const copse_cts* c, size_t i,
+                        uint64_t* slots);
+/* Needed size in words for export (NULL buf) and the export itself. */
+int copse_cts_export(copse_ctx* ctx, const copse_cts* c, uint64_t* buf, size_t cap, size_t* need);
+int copse_cts_import(copse_ctx* ctx, const uint64_t* buf, size_t len, copse_cts** out);
+
+#define COPSE_OP_ADD 1        /* a + b */
+#define COPSE_OP_SUB 2        /* a - b */
+#define COPSE_OP_TENSOR 3     /* (a0 b0, a0 b1 + a1 b0, a1 b1) */
+#define COPSE_OP_RELIN 4      /* 3-poly a -> 2 polys */
+#define COPSE_OP_MODSWITCH 5  /* drop the highest prime */
+#define COPSE_OP_MUL 6        /* tensor, relinearize, modulus switch */
+#define COPSE_OP_ROTATE 7     /* left rotation by arg slots (hoisted form) */
+#define COPSE_OP_MUL_PLAIN 8  /* a * encode(slots) */
+#define COPSE_OP_ADD_PLAIN 9  /* a + encode(slots) */
+/* out = op(a[ia], b[ib]).  b may be NULL for unary ops; slots (2*(N/2)
+ * values mod t) is the plaintext operand of *_PLAIN ops. */
+int copse_ct_op(copse_ctx* ctx, const copse_keys* keys, int op, const copse_cts* a, size_t ia,
+                const copse_cts* b, size_t ib, int32_t arg, const uint64_t* slots, copse_cts** out);
+/* Hoisted rotations of a[ia] by rots[0..n) (one ModUp shared): n results. */
+int copse_ct_rotate_many(copse_ctx* ctx, const copse_keys* keys, const copse_cts* a, size_t ia,
+                         const int32_t* rots, size_t n, copse_cts** out);
+/* Negacyclic product of two coefficient vectors modulo the prime with global
+ * index `prime` through the device transform: out = a * b mod (X^N+1, q). */
+int copse_poly_mul(copse_ctx* ctx, int prime, const uint64_t* a, const uint64_t* b, uint64_t* out);
+
+/* ---------------------------------------------------------------- profiling */
+/* When on, the library brackets each launch of the named kernel class with
+ * HIP events on the launching stream and accumulates the durations.
+ * kind: 0 = forward NTT, 1 = inverse NTT, 2 = key-switch inner product,
+ * 3 = base conversion, 4 = elementwise.  reset clears the counters. */
+int copse_profile_enable(copse_ctx* ctx, int on);
+int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
+                       double* limbs, int reset);
+
+/* ---------------------------------------------------------------- serving */
+/*
+ * Request loop: resident models, encrypted queries admitted while device
+ * memory is under hbm_budget_bytes, batched as they arrive (continuous
+ * batching across query groups), results in arrival-independent bits.
+ */
+int copse_server_create(copse_ctx* ctx, size_t hbm_budget_bytes, int max_batch, copse_server** out);
+void copse_server_destroy(copse_server* s);
+/* Registers a model with the evaluation keys it needs (borrowed; both must
+ * outlive the server). */
+int copse_server_add_model(copse_server* s, const copse_model* m, const copse_keys* eval_keys,
+                           int* model_id);
+/* Takes ownership of q.  ENOMEM when the request does not fit the budget. */
+int copse_server_submit(copse_server* s, int model_id, copse_cts* q, uint64_t* ticket);
+/* Waits up to timeout_ms (-1 = forever) for the ticket's result; ETIMEOUT. */
+int copse_server_wait(copse_server* s, uint64_t ticket, int timeout_ms, copse_cts** result);
+/* Submission-to-completion latency of a finished ticket, in ms. */
+int copse_server_latency(copse_server* s, uint64_t ticket, double* ms);
+
+/* ---------------------------------------------------------------- self-test hooks
+ * Expose the host samplers so their streams can be checked against an
+ * independent SHAKE-256.  kind: 0 uniform mod q (limb = global prime
+ * index), 1 ternary, 2 centered binomial. */
+int copse_test_shake256(const uint8_t* msg, size_t len, uint8_t* out, size_t outlen);
+/* Prime chain of the parameters, computed on the host (no device needed). */
+int copse_chain_primes(const copse_params* params, uint64_t* out, size_t cap, size_t* n);
+/* Host encoder: slots[2*(N/2)] mod t -> centered coefficients[N]. */
+int copse_test_encode(uint32_t log_n, uint64_t t, const uint64_t* slots, int64_t* coeffs);
+int copse_test_sample(const uint8_t seed[32], const char* domain, uint64_t obj, uint32_t limb, int kind,
+                      uint64_t q, size_t n, int64_t* out);
+
+const char* copse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COPSE_H */

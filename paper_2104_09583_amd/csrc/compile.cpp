@@ -1,0 +1,259 @@
+// Forest compiler (model owner): serialized forest -> padded thresholds,
+// reshuffle matrix, level matrices and masks, slot layout and baby-step
+// counts.  Definitions follow Section 4.1 ("Properties of nodes", "Properties
+// of models", generalized diagonals) and Section 4.2 (padded threshold
+// vector, reshuffling matrix, level matrices, level masks).
+#include <algorithm>
+#include <cmath>
+#include <sstream>
+
+#include "compiled.hpp"
+
+namespace copse {
+
+namespace {
+struct Parser {
+  std::vector<std::string> toks;
+  size_t pos = 0;
+  int n_labels_names = 0;
+  int parse(std::vector<Node>& nodes) {
+    if (pos >= toks.size()) fail(COPSE_EINVAL, "truncated tree");
+    const std::string& tag = toks[pos];
+    if (tag == "L") {
+      if (pos + 1 >= toks.size()) fail(COPSE_EINVAL, "truncated leaf");
+      long lab = std::stol(toks[pos + 1]);
+      pos += 2;
+      if (lab < 0 || lab >= n_labels_names) fail(COPSE_EINVAL, "label index out of range");
+      nodes.push_back(Node{true, 0, 0, (int)lab, -1, -1, -1});
+      return (int)nodes.size() - 1;
+    }
+    if (tag == "B") {
+      if (pos + 2 >= toks.size()) fail(COPSE_EINVAL, "truncated branch");
+      long f = std::stol(toks[pos + 1]);
+      long long thr = std::stoll(toks[pos + 2]);
+      if (f < 0 || thr < 0) fail(COPSE_EINVAL, "negative feature or threshold");
+      pos += 3;
+      int me = (int)nodes.size();
+      nodes.push_back(Node{false, (int)f, (uint64_t)thr, 0, -1, -1, -1});
+      int l = parse(nodes);
+      int r = parse(nodes);
+      nodes[me].left = l;
+      nodes[me].right = r;
+      return me;
+    }
+    fail(COPSE_EINVAL, "bad token '" + tag + "'");
+  }
+};
+
+int level_of(std::vector<Node>& nodes, int n) {
+  Node& x = nodes[n];
+  if (x.leaf) return 0;
+  if (x.level >= 0) return x.level;
+  x.level = 1 + std::max(level_of(nodes, x.left), level_of(nodes, x.right));
+  return x.level;
+}
+}  // namespace
+
+uint32_t pow2_ceil(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+uint32_t baby_steps(uint32_t n) {
+  if (n <= 1) return 1;
+  // 2^ceil(log2 sqrt(n)): smallest power of two p with p*p >= n
+  uint32_t p = 1;
+  while ((uint64_t)p * p < n) p <<= 1;
+  return p;
+}
+
+std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t F, uint32_t prec, uint32_t log_n,
+                                         int fold, uint32_t n1R, uint32_t n1L) {
+  if (!text) fail(COPSE_EINVAL, "null forest text");
+  if (F == 0 || prec == 0 || prec > 32) fail(COPSE_EINVAL, "bad feature count or precision");
+  std::string s(text, len);
+  std::istringstream in(s);
+  std::string line;
+  std::vector<std::string> lines;
+  while (std::getline(in, line)) {
+    bool blank = line.find_first_not_of(" \t\r") == std::string::npos;
+    if (!blank) lines.push_back(line);
+  }
+  if (lines.empty()) fail(COPSE_EINVAL, "empty forest text");
+  auto C = std::make_unique<Compiled>();
+  {
+    std::istringstream ls(lines[0]);
+    std::string nm;
+    while (ls >> nm) C->label_names.push_back(nm);
+  }
+  if (lines.size() < 2) fail(COPSE_EINVAL, "forest has no trees");
+  for (size_t li = 1; li < lines.size(); ++li) {
+    Parser p;
+    std::istringstream ls(lines[li]);
+    std::string tk;
+    while (ls >> tk) p.toks.push_back(tk);
+    p.n_labels_names = (int)C->label_names.size();
+    int root;
+    try {
+      root = p.parse(C->nodes);
+    } catch (const std::invalid_argument&) {
+      fail(COPSE_EINVAL, "non-numeric token");
+    } catch (const std::out_of_range&) {
+      fail(COPSE_EINVAL, "numeric token out of range");
+    }
+    if (p.pos != p.toks.size()) fail(COPSE_EINVAL, "trailing tokens on a tree line");
+    C->roots.push_back(root);
+  }
+  auto& nodes = C->nodes;
+  // preorder indices, ancestors and sides of labels
+  struct Frame { int n; std::vector<int> anc; std::vector<int> side; };
+  for (int root : C->roots) {
+    std::vector<Frame> st;
+    st.push_back({root, {}, {}});
+    while (!st.empty()) {
+      Frame f = std::move(st.back());
+      st.pop_back();
+      Node& x = nodes[f.n];
+      if (x.leaf) {
+        x.index = (int)C->label_nodes.size();
+        C->label_nodes.push_back(f.n);
+        C->anc.push_back(f.anc);
+        C->side.push_back(f.side);
+        continue;
+      }
+      x.index = (int)C->branch_nodes.size();
+      C->branch_nodes.push_back(f.n);
+      auto al = f.anc, ar = f.anc;
+      al.push_back(f.n); ar.push_back(f.n);
+      auto sl = f.side, sr = f.side;
+      sl.push_back(0); sr.push_back(1);
+      st.push_back({x.right, ar, sr});   // pushed first, visited second
+      st.push_back({x.left, al, sl});
+    }
+  }
+  const uint32_t b = (uint32_t)C->branch_nodes.size();
+  const uint32_t m = (uint32_t)C->label_nodes.size();
+  if (b == 0) fail(COPSE_EINVAL, "forest has no branches");
+  for (int bn : C->branch_nodes) {
+    if ((uint32_t)nodes[bn].feature >= F) fail(COPSE_EINVAL, "feature index out of range");
+    if (prec < 64 && nodes[bn].threshold >= (1ULL << prec)) fail(COPSE_EINVAL, "threshold exceeds precision");
+  }
+  uint32_t d = 0;
+  for (int r : C->roots) d = std::max<uint32_t>(d, (uint32_t)level_of(nodes, r));
+  std::vector<uint32_t> kappa(F, 0);
+  for (int bn : C->branch_nodes) kappa[nodes[bn].feature]++;
+  uint32_t K = *std::max_element(kappa.begin(), kappa.end());
+  uint32_t q = K * F;
+  // padded threshold vector: per feature, its branches in ascending preorder, then sentinels
+  C->padded.assign(q, -1);
+  for (uint32_t f = 0; f < F; ++f) {
+    uint32_t k = 0;
+    for (uint32_t bi = 0; bi < b; ++bi)
+      if ((uint32_t)nodes[C->branch_nodes[bi]].feature == f) C->padded[f * K + k++] = (int)bi;
+  }
+  // level selections and masks
+  C->sel.assign(d, std::vector<int>(m, -1));
+  C->mask.assign(d, std::vector<int>(m, 1));
+  for (uint32_t l = 1; l <= d; ++l) {
+    for (uint32_t i = 0; i < m; ++i) {
+      const auto& A = C->anc[i];
+      if (A.empty()) { C->sel[l - 1][i] = -1; C->mask[l - 1][i] = 1; continue; }
+      int choice = -1;
+      for (size_t a = 0; a < A.size(); ++a)
+        if ((uint32_t)nodes[A[a]].level == l) choice = (int)a;
+      if (choice < 0) {
+        int best = -1;
+        for (size_t a = 0; a < A.size(); ++a)
+          if ((uint32_t)nodes[A[a]].level < l && (best < 0 || nodes[A[a]].level > nodes[A[best]].level))
+            best = (int)a;
+        choice = best >= 0 ? best : (int)A.size() - 1;
+      }
+      C->sel[l - 1][i] = nodes[A[choice]].index;
+      C->mask[l - 1][i] = C->side[i][choice] == 1 ? 0 : 1;
+    }
+  }
+  auto& M = C->meta;
+  std::memset(&M, 0, sizeof(M));
+  M.n_features = F; M.precision = prec; M.K = K; M.q = q; M.b = b; M.m = m; M.d = d;
+  M.n_trees = (uint32_t)C->roots.size();
+  uint32_t B_in = m + b + q - 2;
+  M.block_w = pow2_ceil(std::max<uint32_t>(B_in, 1));
+  M.log_n = log_n;
+  uint64_t N = 1ULL << log_n;
+  if (M.block_w > N / 2) fail(COPSE_ECAPACITY, "query block of " + std::to_string(M.block_w) +
+                                                  " slots exceeds a slot row of " + std::to_string(N / 2));
+  M.queries_per_ct = (uint32_t)(N / M.block_w);
+  M.fold = fold ? 1 : 0;
+  M.n1_R = n1R ? n1R : baby_steps(q);
+  M.n1_L = n1L ? n1L : baby_steps(fold ? q : b);
+  // depth: comparison, reshuffle (unless folded), level product, product tree
+  uint32_t seccomp = prec > 2 ? 2 + (uint32_t)std::ceil(std::log2((double)(prec - 1))) : prec;
+  uint32_t tree = 0;
+  while ((1u << tree) < d) ++tree;
+  M.depth = seccomp + (fold ? 1 : 2) + tree;
+  C->B_in = B_in;
+  return C;
+}
+
+std::vector<int32_t> needed_rotations(const copse_public_meta& M) {
+  std::vector<int32_t> r;
+  auto add = [&](uint32_t n, uint32_t n1) {
+    for (uint32_t j = 1; j < n1; ++j) r.push_back((int32_t)j);
+    for (uint32_t g = 1; g * n1 < n; ++g) r.push_back((int32_t)(g * n1));
+  };
+  if (!M.fold) add(M.q, M.n1_R);
+  add(M.fold ? M.q : M.b, M.n1_L);
+  std::sort(r.begin(), r.end());
+  r.erase(std::unique(r.begin(), r.end()), r.end());
+  return r;
+}
+
+// ---------------------------------------------------------------- slot vectors of the layout
+// slot index of block k, offset s: row k / bpr, column (k % bpr) * W + s; rows of N/2 slots.
+static size_t slot_index(const copse_public_meta& M, size_t N, uint32_t k, uint32_t s) {
+  size_t bpr = (N / 2) / M.block_w;
+  size_t row = k / bpr, col = (k % bpr) * M.block_w + s;
+  return row * (N / 2) + col;
+}
+
+void replicate_blocks(const copse_public_meta& M, size_t N, const std::vector<int64_t>& vec,
+                      std::vector<uint64_t>& slots, uint64_t t) {
+  slots.assign(N, 0);
+  for (uint32_t k = 0; k < M.queries_per_ct; ++k)
+    for (size_t s = 0; s < vec.size(); ++s) {
+      int64_t v = vec[s] % (int64_t)t;
+      if (v < 0) v += (int64_t)t;
+      slots[slot_index(M, N, k, (uint32_t)s)] = (uint64_t)v;
+    }
+}
+
+void query_plane_slots(const copse_public_meta& M, size_t N, const uint32_t* feats, size_t nq, uint32_t plane,
+                       std::vector<uint64_t>& slots) {
+  slots.assign(N, 0);
+  uint32_t B_in = M.m + M.b + M.q - 2;
+  for (size_t k = 0; k < nq; ++k)
+    for (uint32_t s = 0; s < B_in; ++s) {
+      uint32_t pos = s % M.q;
+      uint32_t f = pos / M.K;
+      slots[slot_index(M, N, (uint32_t)k, s)] = (feats[k * M.n_features + f] >> plane) & 1u;
+    }
+}
+
+// Generalized diagonal k of A (rows x n), pre-rotated to block offset g*n1, replicated per block.
+void diagonal_slots(const copse_public_meta& M, size_t N, const std::vector<std::vector<int64_t>>& A, uint32_t k,
+                    uint32_t n1, std::vector<uint64_t>& slots, uint64_t t, bool* nonzero) {
+  const size_t rows = A.size(), n = A[0].size();
+  const uint32_t g = k / n1;
+  std::vector<int64_t> vec((size_t)g * n1 + rows, 0);
+  bool nz = false;
+  for (size_t j = 0; j < rows; ++j) {
+    int64_t v = A[j][(j + k) % n];
+    vec[(size_t)g * n1 + j] = v;
+    if (v % (int64_t)t) nz = true;
+  }
+  *nonzero = nz;
+  replicate_blocks(M, N, vec, slots, t);
+}
+
+}  // namespace copse

@@ -1,0 +1,88 @@
+// Compiled forest, model and evaluation structures (host side).
+#pragma once
+
+#include "internal.hpp"
+
+namespace copse {
+
+struct Node {
+  bool leaf;
+  int feature;
+  uint64_t threshold;
+  int label;
+  int left, right;
+  int level;   // -1 until computed; branch level (leaf 0)
+  int index = -1;   // preorder index among branches or among labels
+};
+
+struct Compiled {
+  copse_public_meta meta;
+  std::vector<std::string> label_names;
+  std::vector<Node> nodes;
+  std::vector<int> roots;
+  std::vector<int> branch_nodes;            // node id by branch preorder index
+  std::vector<int> label_nodes;             // node id by label preorder index
+  std::vector<std::vector<int>> anc;        // per label: ancestor node ids, root..parent
+  std::vector<std::vector<int>> side;       // per label: 1 if in the right (true) subtree
+  std::vector<int> padded;                  // padded slot -> branch index or -1
+  std::vector<std::vector<int>> sel;        // [level-1][label] -> branch index or -1
+  std::vector<std::vector<int>> mask;       // [level-1][label]
+  uint32_t B_in = 0;
+};
+
+uint32_t pow2_ceil(uint32_t x);
+uint32_t baby_steps(uint32_t n);
+std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t F, uint32_t prec, uint32_t log_n,
+                                         int fold, uint32_t n1R, uint32_t n1L);
+std::vector<int32_t> needed_rotations(const copse_public_meta& M);
+void replicate_blocks(const copse_public_meta& M, size_t N, const std::vector<int64_t>& vec,
+                      std::vector<uint64_t>& slots, uint64_t t);
+void query_plane_slots(const copse_public_meta& M, size_t N, const uint32_t* feats, size_t nq, uint32_t plane,
+                       std::vector<uint64_t>& slots);
+void diagonal_slots(const copse_public_meta& M, size_t N, const std::vector<std::vector<int64_t>>& A, uint32_t k,
+                    uint32_t n1, std::vector<uint64_t>& slots, uint64_t t, bool* nonzero);
+
+// Either a plaintext (NTT form) or a ciphertext operand of the model.
+struct Operand {
+  std::unique_ptr<Plain> pt;
+  CtPtr ct;
+  bool zero() const { return !pt && !ct; }
+};
+
+struct Model {
+  copse_public_meta meta;
+  bool encrypted = false;
+  int dec_level = 0, br_level = 0, lvl_level = 0;
+  // comparison operands: plaintext thresholds -> E, C, G, TH plaintexts; encrypted -> TH ciphertexts
+  std::vector<Operand> E, C, G, TH;
+  std::vector<Operand> rdiag;                   // q diagonals of R_ext (empty when folded)
+  std::vector<std::vector<Operand>> ldiag;      // d x (b or q) diagonals of the level matrices
+  std::vector<Operand> masks;
+  size_t bytes = 0;
+};
+
+std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k, bool encrypt_model,
+                                   const uint8_t seed[32]);
+// query group (p ciphertexts) -> result ciphertext at level 0
+CtPtr evaluate_group(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes);
+std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
+                                   const std::vector<std::vector<const Ct*>>& groups);
+
+}  // namespace copse
+
+// Opaque handles of the C ABI.
+struct copse_ctx {
+  std::unique_ptr<copse::Context> c;
+};
+struct copse_keys {
+  std::unique_ptr<copse::Keys> k;
+};
+struct copse_compiled {
+  std::unique_ptr<copse::Compiled> c;
+};
+struct copse_model {
+  std::unique_ptr<copse::Model> m;
+};
+struct copse_cts {
+  std::vector<copse::CtPtr> v;
+};

@@ -1,0 +1,299 @@
+// Internal declarations of the COPSE gfx950 library.
+//
+// Residues modulo every prime are held as IEEE doubles with exact integer
+// values in [0, q), q < 2^50.  A product a*b mod q is computed exactly with
+// the fused multiply-add: h = a*b (rounded), l = fma(a, b, -h) (the exact
+// rounding error, so a*b = h + l), k = floor(h * (1/q)) is the quotient up
+// to +-1 (|error| < 0.4 because a*b/q < 2^50 and three roundings of 2^-53),
+// r = fma(-k, q, h) + l is then an exact integer in [-q, 2q) and one
+// conditional add or subtract brings it to [0, q).  On CDNA the fp64 FMA
+// issues at full rate while 32-bit integer multiplies do not, which makes
+// this the fastest exact 50-bit modular product on the chip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/copse.h"
+
+namespace copse {
+
+constexpr int kMaxPrimes = 48;
+
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define COPSE_HIP(x)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      ::copse::fail(COPSE_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ------------------------------------------------------------------ host number theory
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m);
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t m);
+uint64_t invmod(uint64_t a, uint64_t m);
+bool is_prime(uint64_t n);
+uint64_t root_of_unity(uint64_t order, uint64_t q);
+uint32_t bitrev(uint32_t x, int bits);
+
+// ------------------------------------------------------------------ SHAKE-256 samplers
+void shake256(const uint8_t* msg, size_t len, uint8_t* out, size_t outlen);
+class ShakeStream {
+ public:
+  ShakeStream(const uint8_t seed[32], const char* domain, uint64_t obj, uint32_t limb);
+  void read(uint8_t* out, size_t n);
+
+ private:
+  void permute_block();
+  uint64_t st_[25];
+  uint8_t buf_[136];
+  size_t pos_;
+};
+void sample_uniform(const uint8_t seed[32], const char* dom, uint64_t obj, uint32_t limb, uint64_t q,
+                    size_t n, double* out);
+void sample_ternary(const uint8_t seed[32], const char* dom, uint64_t obj, size_t n, int64_t* out);
+void sample_cbd21(const uint8_t seed[32], const char* dom, uint64_t obj, size_t n, int64_t* out);
+
+// ------------------------------------------------------------------ device-side descriptors
+struct DevPrime {
+  double q;
+  double qinv;         // fl(1/q)
+  const double* fwd;   // psi^bitrev(k), k < N
+  const double* inv;   // psi^-bitrev(k), k < N
+  double ninv;         // N^-1 mod q
+};
+
+// A batched launch works on rows of N values; row r lives at base + rows[r].x * N and is
+// reduced modulo prime rows[r].y.
+using RowDesc = int2;
+
+// ------------------------------------------------------------------ memory pool
+class Pool {
+ public:
+  explicit Pool(int device) : device_(device) {}
+  ~Pool();
+  void* alloc(size_t bytes);
+  void free(void* p);
+  size_t held() const { return held_; }
+  void trim();
+
+ private:
+  int device_;
+  std::map<size_t, std::vector<void*>> cache_;
+  std::map<void*, size_t> live_;
+  size_t held_ = 0;
+  std::mutex mu_;
+};
+
+struct Context;
+
+// Device buffer owned through the context pool.
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(Context* c, size_t doubles);
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept;
+  ~DBuf() { reset(); }
+  void reset();
+  double* get() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  Context* c_ = nullptr;
+  double* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// A ciphertext (or a 3-component tensor) in NTT form: [npolys][level+1][N].
+struct Ct {
+  int level = 0;
+  int npolys = 0;
+  DBuf buf;
+  double* poly(int k, size_t N) const { return buf.get() + (size_t)k * (level + 1) * N; }
+  size_t limbs() const { return (size_t)level + 1; }
+};
+using CtPtr = std::unique_ptr<Ct>;
+
+// Profiling counters per kernel class.
+struct ProfSlot {
+  uint64_t launches = 0;
+  double ms = 0;
+  double limbs = 0;
+};
+
+struct KSTables;  // per-level base-conversion constants (device)
+
+struct Context {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  uint32_t log_n = 0;
+  size_t N = 0;
+  uint64_t t = 0;
+  int L = 0;          // top data level (L+1 data primes)
+  int alpha = 0;      // special primes = digit size
+  std::vector<uint64_t> primes;   // q_0..q_L, p_0..p_{alpha-1}
+  std::vector<uint64_t> psi;      // the device transform's 2N-th roots
+  DevPrime* d_primes = nullptr;
+  std::vector<double*> tables;
+  std::unique_ptr<Pool> pool;
+  uint64_t zeta = 0;              // slot root mod t
+  std::vector<uint32_t> slot_pos; // slot (r,j) -> natural evaluation index (host encode)
+  std::map<int, std::unique_ptr<KSTables>> ks;   // by level
+  std::map<std::string, int2*> row_tables;       // cached device row lists
+  bool profiling = false;
+  ProfSlot prof[5];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[5];
+  std::vector<hipEvent_t> event_cache;
+
+  int n_primes() const { return (int)primes.size(); }
+  int special(int r) const { return L + 1 + r; }
+  int n_digits(int level) const { return (level + 1 + alpha - 1) / alpha; }
+  const int2* rows(const std::string& key, const std::vector<int2>& host);
+  KSTables& kstab(int level);
+  ~Context();
+};
+
+struct KSTables {
+  // ModUp: per digit j, bconv from the digit's primes to all other primes of P Q_l.
+  struct Digit {
+    int first, count;                  // data prime range of the digit
+    std::vector<int> targets;          // ext-row index (0..nl-1 data, nl.. special) of outputs
+    double* d_mult = nullptr;          // [count]  (Q_j/q_i)^-1 mod q_i
+    double* d_mat = nullptr;           // [count][targets] (Q_j/q_i) mod p_o
+    int2* d_out_rows = nullptr;        // output row descriptors in the ext buffer
+    int2* d_in_rows = nullptr;
+  };
+  std::vector<Digit> digits;
+  // ModDown: special primes -> data primes 0..level
+  double* d_md_mult = nullptr;   // [alpha] t^-1 (P/p_r)^-1 mod p_r
+  double* d_md_mat = nullptr;    // [alpha][nl] (P/p_r) mod q_i
+  double* d_md_pinv = nullptr;   // [nl] P^-1 mod q_i
+  double* d_md_tpinv = nullptr;  // [nl] t P^-1 mod q_i
+  // Modulus switch from this level to level-1
+  double* d_ms = nullptr;        // [4 + 2*level]: q_l, t^-1 mod q_l, then per i<l: q_l^-1, t q_l^-1
+  std::vector<double*> owned;
+};
+
+// ------------------------------------------------------------------ kernel launchers (kernels.hip)
+void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows);
+void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows);
+// out = a op b over rows (same row layout for out, a, b)
+void launch_add(Context& c, double* out, const double* a, const double* b, const int2* rows, int nrows);
+void launch_sub(Context& c, double* out, const double* a, const double* b, const int2* rows, int nrows);
+void launch_neg(Context& c, double* out, const double* a, const int2* rows, int nrows);
+void launch_mul(Context& c, double* out, const double* a, const double* b, const int2* rows, int nrows);
+void launch_mac(Context& c, double* acc, const double* a, const double* b, const int2* rows, int nrows);
+// out[r] = a[r] * s where s = scal[prime of r]
+void launch_mul_scalar(Context& c, double* out, const double* a, const double* scal_by_prime,
+                       const int2* rows, int nrows);
+// ciphertext x plaintext: out_k = a_k * pt for k < npolys (pt rows = limbs), nl limbs
+void launch_mul_plain(Context& c, double* out, const double* a, const double* pt, int npolys, int nl);
+// acc_k += a_k * pt
+void launch_mac_plain(Context& c, double* acc, const double* a, const double* pt, int npolys, int nl);
+void launch_tensor(Context& c, double* d, const double* a, const double* b, int nl, bool accumulate);
+// out[r] = in[r] after sigma_g in the transform's bit-reversed evaluation order
+void launch_automorphism(Context& c, double* out, const double* in, uint64_t g, int nl, int npolys);
+// signed small integers (as doubles) -> residues for each prime row
+void launch_lift(Context& c, double* out, const double* v, const int2* rows, int nrows);
+// base conversion: out rows o < n_out (row desc out_rows) from in rows i < n_in
+void launch_bconv(Context& c, double* out_base, const int2* out_rows, int n_out, const double* in_base,
+                  const int2* in_rows, int n_in, const double* mult, const double* mat, int batch,
+                  size_t in_batch_stride, size_t out_batch_stride);
+// key-switch inner product with optional automorphism of the digits
+struct KsJob {
+  const double* ext;     // [D][nE][N]
+  const double* kb;      // key b rows base [D][Ltot][N]
+  const double* ka;
+  double* acc;           // [2][nE][N]
+  uint64_t g;            // Galois element (1 = none)
+};
+struct KsJobs {
+  static constexpr int kMax = 24;
+  KsJob j[kMax];
+};
+void launch_ks_inner(Context& c, const KsJob* jobs, int njobs, int D, int nE, int level,
+                     size_t key_digit_stride);
+// modulus switch helpers
+void launch_ms_prep(Context& c, double* out, const double* top_coef, int npolys, int level,
+                    const double* ms_tab);
+void launch_ms_finish(Context& c, double* out, const double* in, const double* w, int npolys, int level,
+                      const double* ms_tab);
+// ModDown finish: out_k[i] = y_k[i] * pinv_i - w_k[i] * tpinv_i (+ an addend, see add_mode)
+void launch_moddown_finish(Context& c, double* out, const double* y, size_t y_poly_stride, const double* w,
+                           int npolys, int nl, const double* pinv, const double* tpinv,
+                           const double* add, size_t add_poly_stride, int add_mode);
+void launch_add_const(Context& c, double* a, int nl, double v);
+
+// profiling hooks
+void prof_begin(Context& c, int kind, hipEvent_t* ev);
+void prof_end(Context& c, int kind, hipEvent_t ev, double limbs);
+void prof_collect(Context& c);
+
+// ------------------------------------------------------------------ BGV operations (bgv.cpp)
+struct Keys {
+  bool has_secret = false;
+  DBuf s;          // NTT form over all primes [Ltot][N]
+  std::vector<int64_t> s_host;   // ternary coefficients
+  DBuf pk_b, pk_a; // NTT form over data primes [L+1][N]
+  struct KSK {
+    DBuf b, a;     // [D][Ltot][N]
+  };
+  std::unique_ptr<KSK> relin;
+  std::map<uint64_t, std::unique_ptr<KSK>> rot;   // by Galois element
+  size_t bytes = 0;
+};
+
+struct Plain {
+  int level = 0;
+  DBuf buf;        // NTT form [level+1][N]
+};
+
+uint64_t galois_of(const Context& c, int64_t r);
+
+CtPtr ct_alloc(Context& c, int level, int npolys);
+CtPtr ct_copy(Context& c, const Ct& a);
+void encode_slots(const Context& c, const uint64_t* slots, std::vector<int64_t>& coeffs_centered);
+void decode_poly(const Context& c, const std::vector<uint64_t>& coeffs_mod_t, uint64_t* slots);
+std::unique_ptr<Plain> make_plain(Context& c, const std::vector<int64_t>& centered, int level);
+std::unique_ptr<Plain> make_plain_slots(Context& c, const uint64_t* slots, int level);
+
+std::unique_ptr<Keys> keygen(Context& c, const uint8_t seed[32], const std::vector<int32_t>& rots, bool relin);
+CtPtr encrypt(Context& c, const Keys& k, const std::vector<int64_t>& centered, int level,
+              const uint8_t seed[32], uint64_t obj);
+void phase_coef(Context& c, const Keys& k, const Ct& a, std::vector<uint64_t>& out);  // [level+1][N] u64
+
+CtPtr op_add(Context& c, const Ct& a, const Ct& b);
+CtPtr op_sub(Context& c, const Ct& a, const Ct& b);
+CtPtr op_neg(Context& c, const Ct& a);
+CtPtr op_mul_int(Context& c, const Ct& a, uint64_t k);
+CtPtr op_add_plain(Context& c, const Ct& a, const Plain& p);
+CtPtr op_mul_plain(Context& c, const Ct& a, const Plain& p);
+CtPtr op_add_const(Context& c, const Ct& a, uint64_t v);
+CtPtr op_tensor(Context& c, const Ct& a, const Ct& b);
+CtPtr op_modswitch(Context& c, const Ct& a);
+CtPtr op_modswitch_to(Context& c, const Ct& a, int level);
+CtPtr op_relin(Context& c, const Keys& k, const Ct& a);
+CtPtr op_mul(Context& c, const Keys& k, const Ct& a, const Ct& b);
+std::vector<CtPtr> op_rotate_hoisted(Context& c, const Keys& k, const Ct& a, const std::vector<int32_t>& rs);
+CtPtr op_rotate(Context& c, const Keys& k, const Ct& a, int32_t r);
+
+void to_coef_u64(Context& c, const Ct& a, std::vector<uint64_t>& out);
+CtPtr from_coef_u64(Context& c, const uint64_t* data, int level, int npolys);
+
+}  // namespace copse

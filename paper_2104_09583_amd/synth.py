@@ -48,7 +48,8 @@ class Workload:
     encrypted_model: bool
     seed_index: int
     notes: str = ""
-    extra: dict = field(default_factory=dict)
+    chain: dict = field(default_factory=dict)
+    fold: bool = False
 
 
 def _gen_tree(rng: np.random.Generator, shape: ForestShape, depth: int, out: list) -> None:
@@ -90,22 +91,42 @@ def crypto_seed(label: str) -> bytes:
 # The five evaluated workloads.  Depth/feature/precision/class counts follow
 # the configuration list of the benchmark; ``seed_index`` i gives forest seed
 # i, query seed 100 + i and crypto seed SHAKE-256("COPSE-cfg-i").
+# Prime-chain parameters (see the library's copse_params): number of data
+# primes, exclusive bounds for q_0, the other data primes and the special
+# primes, and alpha = special primes = primes per key-switching digit.
+#   N=16384: 9 data primes, total log2(PQ) ~ 433 <= 438 (HE-standard bound
+#            for 128-bit security); the reshuffle is folded into the level
+#            products to fit the circuit in that chain.
+#   N=32768: 11 (p = 8) or 12 (p = 16) data primes, log2(PQ) ~ 660-700 <= 881.
+CHAIN_16K = dict(log_n=14, n_data_primes=9, q0_max=1 << 42, data_max=388736063996,   # 2^38.5
+                 alpha=2, special_max=1 << 44)
+CHAIN_32K_P8 = dict(log_n=15, n_data_primes=11, q0_max=1 << 48, data_max=1 << 42, alpha=4,
+                    special_max=1 << 48)
+CHAIN_32K_P16 = dict(log_n=15, n_data_primes=12, q0_max=1 << 48, data_max=1 << 42, alpha=4,
+                     special_max=1 << 48)
+
 WORKLOADS = {
     "c1_plain_d3": Workload(
         "c1_plain_d3", ForestShape(1, 3, 1.0, 4, 8, 2), 1, 14, False, 1,
-        "one complete binary tree of depth 3, one query, N=16384"),
+        "one complete binary tree of depth 3, one query, N=16384", CHAIN_16K, True),
     "c2_forest16_d5": Workload(
         "c2_forest16_d5", ForestShape(16, 5, 0.7, 16, 8, 4), 1, 15, False, 2,
-        "16 random unbalanced trees, max depth 5, one query, N=32768"),
+        "16 random unbalanced trees, max depth 5, one query, N=32768", CHAIN_32K_P8),
     "c3_batched_32x_d6": Workload(
         "c3_batched_32x_d6", ForestShape(32, 6, 0.7, 16, 8, 8), 1024, 15, False, 3,
-        "1024 queries against 32 trees of max depth 6, N=32768"),
+        "1024 queries against 32 trees of max depth 6, N=32768", CHAIN_32K_P8),
     "c4_encmodel_64x_d8": Workload(
         "c4_encmodel_64x_d8", ForestShape(64, 8, 0.7, 32, 16, 10), 256, 15, True, 4,
-        "encrypted model and queries, 64 trees max depth 8, 16-bit, N=32768"),
+        "encrypted model and queries, 64 trees max depth 8, 16-bit, N=32768", CHAIN_32K_P16),
     "c5_serve_8x_d4": Workload(
         "c5_serve_8x_d4", ForestShape(8, 4, 0.7, 16, 8, 4), 1, 15, False, 5,
-        "serving mix member: 8 trees of depth 4"),
+        "serving mix member: 8 trees of depth 4", CHAIN_32K_P16),
+    "c5_serve_32x_d6": Workload(
+        "c5_serve_32x_d6", ForestShape(32, 6, 0.7, 16, 8, 8), 1, 15, False, 6,
+        "serving mix member: 32 trees of depth 6", CHAIN_32K_P16),
+    "c5_serve_64x_d8": Workload(
+        "c5_serve_64x_d8", ForestShape(64, 8, 0.7, 32, 16, 10), 1, 15, False, 7,
+        "serving mix member: 64 trees of depth 8, plaintext model", CHAIN_32K_P16),
 }
 
 

@@ -1,0 +1,251 @@
+"""GPU parity: every device operation against the CPU oracle, bit for bit,
+through the C ABI.  Ciphertexts are compared in the coefficient domain
+(residues per prime), where the result is independent of the transform's
+internal order."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bgv as B
+from oracle import circuit as CI
+from oracle import compiler as OC
+from oracle import forest as F
+from oracle import nt
+from oracle import slotsim as S
+from paper_2104_09583_amd import synth
+
+pytestmark = pytest.mark.gpu
+T = 65537
+
+
+def say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_2104_09583_amd import copse
+    return copse
+
+
+SMALL = dict(log_n=10, n_data_primes=6, q0_max=1 << 49, data_max=1 << 40, alpha=2, special_max=1 << 49)
+
+
+@pytest.fixture(scope="module")
+def small(C):
+    say("small context", SMALL)
+    ctx = C.Context(**SMALL)
+    ch = nt.make_chain(SMALL["log_n"], T, SMALL["n_data_primes"], SMALL["q0_max"], SMALL["data_max"],
+                       SMALL["alpha"], SMALL["special_max"])
+    assert ctx.primes() == ch.all_primes()
+    sc = B.BGV(ch)
+    seed = b"\x31" * 32
+    rots = [1, 2, 3, 7, 64, 100, 511]
+    keys = ctx.keygen(seed, rots)
+    okeys = sc.keygen(seed, rotations=rots)
+    return ctx, sc, keys, okeys, seed
+
+
+def same(exported, oct_):
+    assert exported["level"] == oct_.level
+    assert len(exported["polys"]) == len(oct_.polys)
+    for a, b in zip(exported["polys"], oct_.polys):
+        assert a.shape == b.shape
+        assert (a == b).all()
+
+
+def test_polymul_against_schoolbook(C, small):
+    ctx, sc, *_ = small
+    rng = np.random.default_rng(1)
+    for i, q in enumerate(ctx.primes()):
+        say("poly_mul prime", i)
+        a = rng.integers(0, q, ctx.N, dtype=np.uint64)
+        b = rng.integers(0, q, ctx.N, dtype=np.uint64)
+        assert (ctx.poly_mul(i, a, b) == B.negacyclic_schoolbook(a, b, q)).all()
+
+
+@pytest.mark.parametrize("log_n", [12, 14, 15])
+def test_polymul_two_pass_transform(C, log_n):
+    say("poly_mul two-pass", log_n)
+    ctx = C.Context(log_n, 2, 1 << 48, 1 << 45, 1, 1 << 49)
+    rng = np.random.default_rng(log_n)
+    for i, q in enumerate(ctx.primes()):
+        psi = nt.root_of_unity(2 * ctx.N, q)
+        a = rng.integers(0, q, ctx.N, dtype=np.uint64)
+        b = rng.integers(0, q, ctx.N, dtype=np.uint64)
+        want = B.ntt_inv(B.mulmod_vec(B.ntt_fwd(a, q, psi), B.ntt_fwd(b, q, psi), q), q, psi)
+        assert (ctx.poly_mul(i, a, b) == want).all()
+        # edge values: zero and q-1 everywhere
+        z = np.zeros(ctx.N, dtype=np.uint64)
+        m1 = np.full(ctx.N, q - 1, dtype=np.uint64)
+        want2 = B.ntt_inv(B.mulmod_vec(B.ntt_fwd(m1, q, psi), B.ntt_fwd(m1, q, psi), q), q, psi)
+        assert (ctx.poly_mul(i, m1, m1) == want2).all()
+        assert (ctx.poly_mul(i, z, m1) == 0).all()
+
+
+def test_import_export_roundtrip(C, small):
+    ctx, sc, *_ = small
+    rng = np.random.default_rng(2)
+    qs = ctx.primes()[:4]
+    polys = [np.stack([rng.integers(0, q, ctx.N, dtype=np.uint64) for q in qs]) for _ in range(2)]
+    ct = ctx.import_(polys, 3)
+    ex = ctx.export(ct)[0]
+    assert ex["level"] == 3 and all((a == b).all() for a, b in zip(ex["polys"], polys))
+
+
+def test_encryption_bit_exact(C, small):
+    ctx, sc, keys, okeys, seed = small
+    rng = np.random.default_rng(3)
+    for level in [sc.L, 2, 0]:
+        v = rng.integers(0, T, size=(2, sc.N // 2))
+        say("encrypt level", level)
+        ct = ctx.encrypt_slots(keys, v, level, seed, 1000 + level)
+        oct_ = sc.encrypt_slots(okeys, v, seed, 1000 + level, level)
+        same(ctx.export(ct)[0], oct_)
+        assert (ctx.decrypt_slots(keys, ct) == v).all()
+
+
+def _pair(ctx, sc, keys, okeys, seed, level=None, obj=(11, 12), binary=False):
+    rng = np.random.default_rng(obj[0])
+    level = sc.L if level is None else level
+    hi = 2 if binary else T
+    va = rng.integers(0, hi, size=(2, sc.N // 2))
+    vb = rng.integers(0, hi, size=(2, sc.N // 2))
+    a = ctx.encrypt_slots(keys, va, level, seed, obj[0])
+    b = ctx.encrypt_slots(keys, vb, level, seed, obj[1])
+    oa = sc.encrypt_slots(okeys, va, seed, obj[0], level)
+    ob = sc.encrypt_slots(okeys, vb, seed, obj[1], level)
+    return a, b, oa, ob, va, vb
+
+
+@pytest.mark.parametrize("level", [5, 3, 1])
+def test_ops_bit_exact(C, small, level):
+    ctx, sc, keys, okeys, seed = small
+    a, b, oa, ob, va, vb = _pair(ctx, sc, keys, okeys, seed, level)
+    say("ops at level", level)
+    same(ctx.export(ctx.op(keys, C.OP_ADD, a, b))[0], sc.add(oa, ob))
+    same(ctx.export(ctx.op(keys, C.OP_SUB, a, b))[0], sc.sub(oa, ob))
+    ten = ctx.op(keys, C.OP_TENSOR, a, b)
+    oten = sc.tensor(oa, ob)
+    same(ctx.export(ten)[0], oten)
+    rel = ctx.op(keys, C.OP_RELIN, ten)
+    orel = sc.relinearize(oten, okeys)
+    same(ctx.export(rel)[0], orel)
+    if level >= 1:
+        same(ctx.export(ctx.op(keys, C.OP_MODSWITCH, rel))[0], sc.modswitch(orel))
+        same(ctx.export(ctx.op(keys, C.OP_MUL, a, b))[0], sc.mul(oa, ob, okeys))
+    slots = np.random.default_rng(level).integers(0, T, size=(2, sc.N // 2))
+    same(ctx.export(ctx.op(keys, C.OP_MUL_PLAIN, a, slots=slots))[0], sc.mul_plain(oa, sc.encode(slots)))
+    same(ctx.export(ctx.op(keys, C.OP_ADD_PLAIN, a, slots=slots))[0], sc.add_plain(oa, sc.encode(slots)))
+    for r in [1, 7, 100, 511]:
+        same(ctx.export(ctx.op(keys, C.OP_ROTATE, a, arg=r))[0], sc.rotate(oa, r, okeys))
+    assert (ctx.decrypt_slots(keys, ctx.op(keys, C.OP_MUL, a, b) if level >= 1 else ten) == (va * vb) % T).all()
+
+
+def test_mixed_level_add_equalizes(C, small):
+    ctx, sc, keys, okeys, seed = small
+    a, b, oa, ob, va, vb = _pair(ctx, sc, keys, okeys, seed, 5, obj=(21, 22))
+    a2 = ctx.op(keys, C.OP_MODSWITCH, a)
+    a3 = ctx.op(keys, C.OP_MODSWITCH, a2)
+    oa3 = sc.modswitch(sc.modswitch(oa))
+    same(ctx.export(ctx.op(keys, C.OP_ADD, a3, b))[0], sc.add(oa3, ob))
+    same(ctx.export(ctx.op(keys, C.OP_MUL, b, a3))[0], sc.mul(ob, oa3, okeys))
+
+
+def test_hoisted_rotations_bit_exact(C, small):
+    ctx, sc, keys, okeys, seed = small
+    a, b, oa, ob, va, vb = _pair(ctx, sc, keys, okeys, seed, 4, obj=(31, 32))
+    rs = [0, 1, 2, 3, 7, 64, 100, 511]
+    got = ctx.rotate_many(keys, a, rs)
+    ex = ctx.export(got)
+    want = sc.rotate_hoisted(oa, rs, okeys)
+    for i, r in enumerate(rs):
+        same(ex[i], want[r])
+    assert (ctx.decrypt_slots(keys, got, 3) == S.rot(va, 3)).all()
+
+
+def test_missing_key_and_exhausted_chain(C, small):
+    ctx, sc, keys, okeys, seed = small
+    a, *_ = _pair(ctx, sc, keys, okeys, seed, 0, obj=(41, 42))
+    with pytest.raises(C.CopseError) as e:
+        ctx.op(keys, C.OP_ROTATE, a, arg=5)
+    assert e.value.code == C.COPSE_EKEY
+    with pytest.raises(C.CopseError) as e:
+        ctx.op(keys, C.OP_MODSWITCH, a)
+    assert e.value.code == C.COPSE_ECAPACITY
+    ev = ctx.export_eval(keys)
+    with pytest.raises(C.CopseError) as e:
+        ctx.decrypt_slots(ev, a)
+    assert e.value.code == C.COPSE_EKEY
+
+
+# ---------------------------------------------------------------- end to end
+def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
+    text = synth.gen_forest_text(shape, seed)
+    oc = OC.compile_forest(text, shape.n_features, shape.precision)
+    need = CI.seccomp_depth(shape.precision) + (1 if fold else 2) + (math.ceil(math.log2(oc.d)) if oc.d > 1 else 0)
+    chain = dict(log_n=log_n, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=alpha,
+                 special_max=1 << 49)
+    ctx = C.Context(**chain)
+    sc = B.BGV(nt.make_chain(log_n, T, need + 1, 1 << 49, 1 << 42, alpha, 1 << 49))
+    comp, meta = C.forest_compile(text, shape.n_features, shape.precision, log_n, fold=fold)
+    pl = CI.make_plan(oc, sc.N, sc.L, fold=fold, encrypted_model=enc)
+    kseed = bytes([seed % 256]) * 32
+    say("e2e", shape, "log_n", log_n, "fold", fold, "enc", enc)
+    keys = ctx.keygen(kseed, C.compiled_rotations(meta))
+    okeys = sc.keygen(kseed, rotations=pl.rotations())
+    nq = meta.queries_per_ct if n_queries is None else n_queries
+    queries = synth.gen_queries(nq, shape.n_features, shape.precision, 500 + seed)
+    model = ctx.model_encode(comp, keys if enc else None, encrypt=enc, seed=kseed if enc else None)
+    qct = ctx.query_encrypt(keys, meta, queries, kseed, group=2)
+    X = CI.encrypt_queries(sc, okeys, pl, queries, kseed, 2)
+    for i in range(len(X)):
+        same(ctx.export(qct)[i], X[i])
+    evk = ctx.export_eval(keys)
+    res = ctx.evaluate(model, evk, qct)
+    omodel = CI.encrypt_model(sc, okeys, pl, kseed) if enc else CI.encode_model(sc, pl)
+    out = CI.Evaluator(sc, okeys, pl).run(X, omodel)
+    same(ctx.export(res)[0], out["result"])
+    bits = ctx.decrypt_labels(keys, meta, res, nq)
+    _, trees = F.parse_forest(text)
+    want = np.array([F.evaluate(trees, list(x)) for x in queries])
+    assert (bits == want).all()
+    return ctx
+
+
+@pytest.mark.parametrize("seed,fold,enc", [(1, False, False), (2, True, False), (3, False, True),
+                                           (4, True, True), (5, False, False)])
+def test_end_to_end_small(C, seed, fold, enc):
+    shape = synth.ForestShape(3, 4, 0.7, 3, 4, 3)
+    _e2e(C, shape, seed, 10, fold, enc)
+
+
+def test_end_to_end_partial_group_and_deeper(C):
+    shape = synth.ForestShape(5, 6, 0.8, 4, 6, 4)
+    _e2e(C, shape, 9, 12, False, False, alpha=4, n_queries=3)
+
+
+def test_workload_c1_full_size(C):
+    """c1 at N=16384 with its 433-bit chain: ciphertexts and labels bit-exact."""
+    w = synth.WORKLOADS["c1_plain_d3"]
+    text, queries, seed = synth.workload_inputs(w)
+    ch = w.chain
+    say("c1 full size")
+    ctx = C.Context(**ch)
+    sc = B.BGV(nt.make_chain(ch["log_n"], T, ch["n_data_primes"], ch["q0_max"], ch["data_max"], ch["alpha"],
+                             ch["special_max"]))
+    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold)
+    oc = OC.compile_forest(text, w.shape.n_features, w.shape.precision)
+    pl = CI.make_plan(oc, sc.N, sc.L, fold=w.fold)
+    keys = ctx.keygen(seed, C.compiled_rotations(meta))
+    okeys = sc.keygen(seed, rotations=pl.rotations())
+    model = ctx.model_encode(comp)
+    qct = ctx.query_encrypt(keys, meta, queries, seed, group=0)
+    res = ctx.evaluate(model, keys, qct)
+    X = CI.encrypt_queries(sc, okeys, pl, queries, seed, 0)
+    out = CI.Evaluator(sc, okeys, pl).run(X, CI.encode_model(sc, pl))
+    same(ctx.export(res)[0], out["result"])
+    _, trees = F.parse_forest(text)
+    assert (ctx.decrypt_labels(keys, meta, res, 1)[0] == np.array(F.evaluate(trees, list(queries[0])))).all()
