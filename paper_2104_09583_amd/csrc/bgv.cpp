@@ -204,13 +204,15 @@ CtPtr ct_alloc(Context& c, int level, int npolys) {
   auto ct = std::make_unique<Ct>();
   ct->level = level;
   ct->npolys = npolys;
-  ct->buf = DBuf(&c, (size_t)npolys * (level + 1) * c.N);
+  ct->n = c.N;
+  ct->store = std::make_shared<DBuf>(&c, (size_t)npolys * (level + 1) * c.N);
+  ct->ptr = ct->store->get();
   return ct;
 }
 
 CtPtr ct_copy(Context& c, const Ct& a) {
   auto o = ct_alloc(c, a.level, a.npolys);
-  COPSE_HIP(hipMemcpyAsync(o->buf.get(), a.buf.get(), a.buf.size() * sizeof(double), hipMemcpyDeviceToDevice,
+  COPSE_HIP(hipMemcpyAsync(o->data(), a.data(), a.words() * sizeof(double), hipMemcpyDeviceToDevice,
                            c.stream));
   return o;
 }
@@ -467,10 +469,10 @@ void phase_coef(Context& c, const Keys& k, const Ct& a, std::vector<uint64_t>& o
 void to_coef_u64(Context& c, const Ct& a, std::vector<uint64_t>& out) {
   const size_t N = c.N;
   const int nl = a.level + 1;
-  DBuf tmp(&c, a.buf.size());
-  COPSE_HIP(hipMemcpyAsync(tmp.get(), a.buf.get(), a.buf.size() * 8, hipMemcpyDeviceToDevice, c.stream));
+  DBuf tmp(&c, a.words());
+  COPSE_HIP(hipMemcpyAsync(tmp.get(), a.data(), a.words() * 8, hipMemcpyDeviceToDevice, c.stream));
   launch_ntt_inv(c, tmp.get(), ct_rows(c, a.npolys, nl), a.npolys * nl);
-  std::vector<double> h(a.buf.size());
+  std::vector<double> h(a.words());
   COPSE_HIP(hipMemcpyAsync(h.data(), tmp.get(), h.size() * 8, hipMemcpyDeviceToHost, c.stream));
   COPSE_HIP(hipStreamSynchronize(c.stream));
   out.resize(h.size());
@@ -490,8 +492,8 @@ CtPtr from_coef_u64(Context& c, const uint64_t* data, int level, int npolys) {
         if (v >= c.primes[i]) fail(COPSE_EINVAL, "residue out of range in import");
         h[((size_t)k * nl + i) * N + j] = (double)v;
       }
-  COPSE_HIP(hipMemcpyAsync(ct->buf.get(), h.data(), h.size() * 8, hipMemcpyHostToDevice, c.stream));
-  launch_ntt_fwd(c, ct->buf.get(), ct_rows(c, npolys, nl), npolys * nl);
+  COPSE_HIP(hipMemcpyAsync(ct->data(), h.data(), h.size() * 8, hipMemcpyHostToDevice, c.stream));
+  launch_ntt_fwd(c, ct->data(), ct_rows(c, npolys, nl), npolys * nl);
   COPSE_HIP(hipStreamSynchronize(c.stream));
   return ct;
 }
@@ -530,7 +532,7 @@ CtPtr op_add(Context& c, const Ct& a, const Ct& b) {
     int np = std::max(x.npolys, y.npolys), nl = x.level + 1;
     auto o = ct_alloc(c, x.level, np);
     int common = std::min(x.npolys, y.npolys);
-    launch_add(c, o->buf.get(), x.buf.get(), y.buf.get(), ct_rows(c, common, nl), common * nl);
+    launch_add(c, o->data(), x.data(), y.data(), ct_rows(c, common, nl), common * nl);
     const Ct& longer = x.npolys > y.npolys ? x : y;
     for (int k = common; k < np; ++k)
       COPSE_HIP(hipMemcpyAsync(o->poly(k, c.N), longer.poly(k, c.N), (size_t)nl * c.N * 8,
@@ -541,7 +543,7 @@ CtPtr op_add(Context& c, const Ct& a, const Ct& b) {
 
 CtPtr op_neg(Context& c, const Ct& a) {
   auto o = ct_alloc(c, a.level, a.npolys);
-  launch_neg(c, o->buf.get(), a.buf.get(), ct_rows(c, a.npolys, a.level + 1), a.npolys * (a.level + 1));
+  launch_neg(c, o->data(), a.data(), ct_rows(c, a.npolys, a.level + 1), a.npolys * (a.level + 1));
   return o;
 }
 
@@ -557,7 +559,7 @@ CtPtr op_mul_int(Context& c, const Ct& a, uint64_t k) {
   DBuf ds(&c, sc.size());
   COPSE_HIP(hipMemcpyAsync(ds.get(), sc.data(), sc.size() * 8, hipMemcpyHostToDevice, c.stream));
   auto o = ct_alloc(c, a.level, a.npolys);
-  launch_mul_scalar(c, o->buf.get(), a.buf.get(), ds.get(), ct_rows(c, a.npolys, nl), a.npolys * nl);
+  launch_mul_scalar(c, o->data(), a.data(), ds.get(), ct_rows(c, a.npolys, nl), a.npolys * nl);
   COPSE_HIP(hipStreamSynchronize(c.stream));
   return o;
 }
@@ -580,7 +582,7 @@ CtPtr op_add_const(Context& c, const Ct& a, uint64_t v) {
 CtPtr op_mul_plain(Context& c, const Ct& a, const Plain& p) {
   if (p.level < a.level) fail(COPSE_EINVAL, "plaintext encoded below the ciphertext level");
   auto o = ct_alloc(c, a.level, a.npolys);
-  launch_mul_plain(c, o->buf.get(), a.buf.get(), p.buf.get(), a.npolys, a.level + 1);
+  launch_mul_plain(c, o->data(), a.data(), p.buf.get(), a.npolys, a.level + 1);
   return o;
 }
 
@@ -588,7 +590,7 @@ CtPtr op_tensor(Context& c, const Ct& a, const Ct& b) {
   return equalized(c, a, b, [&](const Ct& x, const Ct& y) {
     if (x.npolys != 2 || y.npolys != 2) fail(COPSE_EINVAL, "tensor needs 2-component ciphertexts");
     auto o = ct_alloc(c, x.level, 3);
-    launch_tensor(c, o->buf.get(), x.buf.get(), y.buf.get(), x.level + 1, false);
+    launch_tensor(c, o->data(), x.data(), y.data(), x.level + 1, false);
     return o;
   });
 }
@@ -613,7 +615,7 @@ CtPtr op_modswitch(Context& c, const Ct& a) {
   launch_ms_prep(c, w.get(), top.get(), np, l, T.d_ms);
   launch_ntt_fwd(c, w.get(), ct_rows(c, np, l), np * l);
   auto o = ct_alloc(c, l - 1, np);
-  launch_ms_finish(c, o->buf.get(), a.buf.get(), w.get(), np, l, T.d_ms);
+  launch_ms_finish(c, o->data(), a.data(), w.get(), np, l, T.d_ms);
   return o;
 }
 
@@ -676,7 +678,7 @@ CtPtr op_relin(Context& c, const Keys& k, const Ct& a) {
   KsJob job{ext.get(), k.relin->b.get(), k.relin->a.get(), acc.get(), 1};
   launch_ks_inner(c, &job, 1, D, nE, l, (size_t)Lt * N);
   auto o = ct_alloc(c, l, 2);
-  moddown(c, acc.get(), 2, l, o->buf.get(), a.buf.get(), (size_t)nl * N, 1);
+  moddown(c, acc.get(), 2, l, o->data(), a.data(), (size_t)nl * N, 1);
   return o;
 }
 
@@ -720,7 +722,7 @@ std::vector<CtPtr> op_rotate_hoisted(Context& c, const Keys& k, const Ct& a, con
     moddown(c, acc.get(), (int)(2 * cnt), l, res.get(), c0r.get(), (size_t)nl * N, 2);
     for (size_t u = 0; u < cnt; ++u) {
       auto o = ct_alloc(c, l, 2);
-      COPSE_HIP(hipMemcpyAsync(o->buf.get(), res.get() + u * 2 * nl * N, 2 * (size_t)nl * N * 8,
+      COPSE_HIP(hipMemcpyAsync(o->data(), res.get() + u * 2 * nl * N, 2 * (size_t)nl * N * 8,
                                hipMemcpyDeviceToDevice, c.stream));
       out[todo[first + u]] = std::move(o);
     }

@@ -457,7 +457,7 @@ int copse_cts_export(copse_ctx* ctx, const copse_cts* cts, uint64_t* buf, size_t
     NEED(ctx && cts && need);
     Context& c = *ctx->c;
     size_t total = 0;
-    for (auto& ct : cts->v) total += 4 + ct->buf.size();
+    for (auto& ct : cts->v) total += 4 + ct->words();
     *need = total;
     if (!buf) return;
     if (cap < total) fail(COPSE_EINVAL, "export buffer too small");

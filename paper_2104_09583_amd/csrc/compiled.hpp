@@ -49,8 +49,23 @@ struct Operand {
   bool zero() const { return !pt && !ct; }
 };
 
+// Static description of one matrix product of the model: the baby-step offsets (slot order of the
+// baby buffer), the giant groups that have terms, and per group its terms (baby slot, diagonal).
+struct MatPlan {
+  uint32_t n1 = 1;
+  bool enc = false;
+  std::vector<int32_t> rots;
+  std::vector<uint32_t> groups;
+  DBuf terms_buf, off_buf;   // device MMTerm[] and int[groups + 1]
+  const MMTerm* d_terms = nullptr;
+  const int* d_off = nullptr;
+};
+
 struct Model {
   copse_public_meta meta;
+  MatPlan plan_R;
+  std::vector<MatPlan> plan_L;
+  std::vector<int32_t> lvl_rots;
   bool encrypted = false;
   int dec_level = 0, br_level = 0, lvl_level = 0;
   // comparison operands: plaintext thresholds -> E, C, G, TH plaintexts; encrypted -> TH ciphertexts
@@ -64,6 +79,8 @@ struct Model {
 std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k, bool encrypt_model,
                                    const uint8_t seed[32]);
 // query group (p ciphertexts) -> result ciphertext at level 0
+void build_plan(Context& c, MatPlan& P, const std::vector<Operand>& diags, uint32_t n1, bool enc,
+                const std::vector<int32_t>* shared_rots);
 CtPtr evaluate_group(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes);
 std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
                                    const std::vector<std::vector<const Ct*>>& groups);

@@ -1,0 +1,536 @@
+// Batched evaluation engine: the canonical schedule of Algorithm 1 run on
+// many ciphertexts at once.  Every operation below takes a list of
+// ciphertexts and issues one launch per step for all of them (per level
+// group), so the query groups of a batch, the bit planes of a comparison, the
+// products of a prefix-scan round and the baby/giant rotations of a matrix
+// product all travel through the same kernels together.  Each output is the
+// same deterministic function of its inputs as the one-at-a-time operations,
+// so results are bit-identical whatever the batch.
+#include <algorithm>
+#include <map>
+#include <set>
+
+#include "compiled.hpp"
+
+namespace copse {
+
+using SCt = std::shared_ptr<Ct>;
+
+static std::vector<SCt> alloc_batch(Context& c, int count, int level, int npolys) {
+  const size_t words = (size_t)npolys * (level + 1) * c.N;
+  auto store = std::make_shared<DBuf>(&c, words * count);
+  std::vector<SCt> out;
+  for (int i = 0; i < count; ++i) {
+    auto ct = std::make_shared<Ct>();
+    ct->level = level;
+    ct->npolys = npolys;
+    ct->n = c.N;
+    ct->store = store;
+    ct->ptr = store->get() + words * i;
+    out.push_back(ct);
+  }
+  return out;
+}
+
+static const int2* rows_cached(Context& c, const std::string& key, const std::vector<int2>& h) { return c.rows(key, h); }
+
+static const int2* block_rows(Context& c, int np, int nl) {
+  std::string key = "ct:" + std::to_string(np) + ":" + std::to_string(nl);
+  auto it = c.row_tables.find(key);
+  if (it != c.row_tables.end()) return it->second;
+  std::vector<int2> h;
+  for (int k = 0; k < np; ++k)
+    for (int i = 0; i < nl; ++i) h.push_back(make_int2(k * nl + i, i));
+  return c.rows(key, h);
+}
+
+// ------------------------------------------------------------------ modulus switch (batched)
+std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in) {
+  std::vector<SCt> out(in.size());
+  std::map<std::pair<int, int>, std::vector<size_t>> groups;
+  for (size_t i = 0; i < in.size(); ++i) groups[{in[i]->level, in[i]->npolys}].push_back(i);
+  const size_t N = c.N;
+  for (auto& kv : groups) {
+    const int l = kv.first.first, np = kv.first.second;
+    if (l == 0) fail(COPSE_ECAPACITY, "modulus chain exhausted");
+    const auto& idx = kv.second;
+    const int J = (int)idx.size();
+    KSTables& T = c.kstab(l);
+    DBuf top(&c, (size_t)J * np * N);
+    std::vector<const double*> src;
+    for (size_t j : idx)
+      for (int k = 0; k < np; ++k) src.push_back(in[j]->poly(k, N) + (size_t)l * N);
+    launch_gather(c, top.get(), src, 1);
+    std::vector<int2> tr;
+    for (int z = 0; z < J * np; ++z) tr.push_back(make_int2(z, l));
+    launch_ntt_inv(c, top.get(), rows_cached(c, "top:" + std::to_string(J * np) + ":" + std::to_string(l), tr), J * np);
+    DBuf w(&c, (size_t)J * np * l * N);
+    launch_ms_prep(c, w.get(), top.get(), J * np, l, T.d_ms);
+    launch_ntt_fwd(c, w.get(), block_rows(c, J * np, l), J * np * l);
+    auto outs = alloc_batch(c, J, l - 1, np);
+    std::vector<double*> po;
+    std::vector<const double*> pi;
+    for (int j = 0; j < J; ++j) {
+      po.push_back(outs[j]->data());
+      pi.push_back(in[idx[j]]->data());
+      out[idx[j]] = outs[j];
+    }
+    launch_ms_finish_multi(c, po, pi, w.get(), np, l, T.d_ms);
+  }
+  return out;
+}
+
+// switch each ciphertext down to its target level (one prime at a time, batched per step)
+static std::vector<SCt> b_down(Context& c, std::vector<SCt> v, const std::vector<int>& target) {
+  while (true) {
+    std::vector<size_t> todo;
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i]->level > target[i]) todo.push_back(i);
+    if (todo.empty()) return v;
+    std::vector<const Ct*> in;
+    for (size_t i : todo) in.push_back(v[i].get());
+    auto r = b_modswitch(c, in);
+    for (size_t k = 0; k < todo.size(); ++k) v[todo[k]] = r[k];
+  }
+}
+
+// ------------------------------------------------------------------ key switching (batched)
+struct KsReq {
+  int input;
+  const Keys::KSK* key;
+  uint64_t g;
+  double* out;          // 2 polys at the level
+  const double* add;    // mode 1: (d0, d1) to add; mode 2: c0 to permute and add
+};
+
+static void ks_batch(Context& c, int level, const std::vector<const double*>& inputs, const std::vector<KsReq>& reqs,
+                     int add_mode) {
+  if (reqs.empty()) return;
+  const size_t N = c.N;
+  const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
+  const int I = (int)inputs.size(), R = (int)reqs.size();
+  const int Lt = c.n_primes();
+  KSTables& T = c.kstab(level);
+  // ModUp of every input: coefficient form, base conversion per digit, transform of the new rows
+  DBuf cf(&c, (size_t)I * nl * N);
+  launch_gather(c, cf.get(), inputs, nl);
+  launch_ntt_inv(c, cf.get(), block_rows(c, I, nl), I * nl);
+  DBuf ext(&c, (size_t)I * D * nE * N);
+  for (int j = 0; j < D; ++j) {
+    auto& dg = T.digits[j];
+    launch_bconv(c, ext.get(), dg.d_out_rows, (int)dg.targets.size(), cf.get(), dg.d_in_rows, dg.count, dg.d_mult,
+                 dg.d_mat, I, (size_t)nl * N, (size_t)D * nE * N);
+  }
+  {
+    std::string key = "ksntt:" + std::to_string(level) + ":" + std::to_string(I);
+    auto it = c.row_tables.find(key);
+    const int2* r;
+    int cnt = 0;
+    for (int j = 0; j < D; ++j) cnt += (int)T.digits[j].targets.size();
+    cnt *= I;
+    if (it != c.row_tables.end()) {
+      r = it->second;
+    } else {
+      std::vector<int2> h;
+      for (int i = 0; i < I; ++i)
+        for (int j = 0; j < D; ++j)
+          for (int o : T.digits[j].targets) h.push_back(make_int2((i * D + j) * nE + o, o < nl ? o : c.L + 1 + (o - nl)));
+      r = c.rows(key, h);
+    }
+    launch_ntt_fwd(c, ext.get(), r, cnt);
+  }
+  // inner products
+  DBuf acc(&c, (size_t)R * 2 * nE * N);
+  std::vector<KsJob2> jobs;
+  for (int q = 0; q < R; ++q) {
+    const KsReq& rq = reqs[q];
+    jobs.push_back(KsJob2{inputs[rq.input], ext.get() + (size_t)rq.input * D * nE * N, rq.key->b.get(),
+                          rq.key->a.get(), acc.get() + (size_t)q * 2 * nE * N, rq.g});
+  }
+  launch_ks_inner2(c, jobs, D, nE, level, (size_t)Lt * N);
+  // ModDown of all accumulators
+  {
+    std::string key = "mdspec:" + std::to_string(level) + ":" + std::to_string(2 * R);
+    auto it = c.row_tables.find(key);
+    const int2* r;
+    if (it != c.row_tables.end()) {
+      r = it->second;
+    } else {
+      std::vector<int2> h;
+      for (int k = 0; k < 2 * R; ++k)
+        for (int s = 0; s < c.alpha; ++s) h.push_back(make_int2(k * nE + nl + s, c.L + 1 + s));
+      r = c.rows(key, h);
+    }
+    launch_ntt_inv(c, acc.get(), r, 2 * R * c.alpha);
+  }
+  DBuf zh(&c, (size_t)2 * R * nl * N);
+  std::vector<int2> inr, outr;
+  for (int s = 0; s < c.alpha; ++s) inr.push_back(make_int2(nl + s, c.L + 1 + s));
+  for (int i = 0; i < nl; ++i) outr.push_back(make_int2(i, i));
+  launch_bconv(c, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
+               rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
+               (size_t)nE * N, (size_t)nl * N);
+  launch_ntt_fwd(c, zh.get(), block_rows(c, 2 * R, nl), 2 * R * nl);
+  std::vector<double*> outs;
+  std::vector<const double*> adds;
+  std::vector<uint64_t> gal;
+  for (auto& rq : reqs) {
+    outs.push_back(rq.out);
+    adds.push_back(rq.add);
+    gal.push_back(rq.g);
+  }
+  launch_md_finish2(c, outs, adds, gal, acc.get(), zh.get(), nE, nl, T.d_md_pinv, T.d_md_tpinv, add_mode);
+}
+
+// relinearize 3-component ciphertexts (any mix of levels)
+static std::vector<SCt> b_relin(Context& c, const Keys& k, const std::vector<const Ct*>& in3) {
+  if (!k.relin) fail(COPSE_EKEY, "relinearization key absent");
+  std::vector<SCt> out(in3.size());
+  std::map<int, std::vector<size_t>> groups;
+  for (size_t i = 0; i < in3.size(); ++i) groups[in3[i]->level].push_back(i);
+  for (auto& kv : groups) {
+    const int l = kv.first;
+    auto outs = alloc_batch(c, (int)kv.second.size(), l, 2);
+    std::vector<const double*> inputs;
+    std::vector<KsReq> reqs;
+    for (size_t q = 0; q < kv.second.size(); ++q) {
+      const Ct* x = in3[kv.second[q]];
+      inputs.push_back(x->poly(2, c.N));
+      reqs.push_back(KsReq{(int)q, k.relin.get(), 1, outs[q]->data(), x->data()});
+      out[kv.second[q]] = outs[q];
+    }
+    ks_batch(c, l, inputs, reqs, 1);
+  }
+  return out;
+}
+
+// products of pairs: equalize, tensor, relinearize, switch
+std::vector<SCt> b_mul(Context& c, const Keys& k, const std::vector<std::pair<SCt, SCt>>& pairs) {
+  std::vector<SCt> ops;
+  std::vector<int> tgt;
+  for (auto& pr : pairs) {
+    int lv = std::min(pr.first->level, pr.second->level);
+    ops.push_back(pr.first);
+    ops.push_back(pr.second);
+    tgt.push_back(lv);
+    tgt.push_back(lv);
+  }
+  ops = b_down(c, ops, tgt);
+  std::vector<SCt> out(pairs.size());
+  std::map<int, std::vector<size_t>> groups;
+  for (size_t i = 0; i < pairs.size(); ++i) groups[tgt[2 * i]].push_back(i);
+  for (auto& kv : groups) {
+    const int l = kv.first;
+    auto t3 = alloc_batch(c, (int)kv.second.size(), l, 3);
+    std::vector<double*> d;
+    std::vector<const double*> a, b;
+    for (size_t q = 0; q < kv.second.size(); ++q) {
+      size_t i = kv.second[q];
+      if (ops[2 * i]->npolys != 2 || ops[2 * i + 1]->npolys != 2) fail(COPSE_EINVAL, "product of non-linear ciphertexts");
+      d.push_back(t3[q]->data());
+      a.push_back(ops[2 * i]->data());
+      b.push_back(ops[2 * i + 1]->data());
+    }
+    launch_tensor_multi(c, d, a, b, l + 1);
+    std::vector<const Ct*> in3;
+    for (auto& x : t3) in3.push_back(x.get());
+    auto rel = b_relin(c, k, in3);
+    std::vector<const Ct*> rin;
+    for (auto& x : rel) rin.push_back(x.get());
+    auto ms = b_modswitch(c, rin);
+    for (size_t q = 0; q < kv.second.size(); ++q) out[kv.second[q]] = ms[q];
+  }
+  return out;
+}
+
+// hoisted rotations of each of v (same level) by every offset in rots, into B[u][b]
+static void b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*>& v, const std::vector<int32_t>& rots,
+                          double* B) {
+  const size_t N = c.N;
+  const int l = v[0]->level, nl = l + 1, G = (int)v.size();
+  const size_t ps = (size_t)2 * nl * N;
+  std::vector<const double*> inputs;
+  for (auto* x : v) {
+    if (x->level != l || x->npolys != 2) fail(COPSE_EINVAL, "rotation batch must share one level");
+    inputs.push_back(x->poly(1, N));
+  }
+  std::vector<KsReq> reqs;
+  for (size_t u = 0; u < rots.size(); ++u) {
+    uint64_t g = galois_of(c, rots[u]);
+    for (int b = 0; b < G; ++b) {
+      double* dst = B + ((size_t)u * G + b) * ps;
+      if (g == 1) {
+        COPSE_HIP(hipMemcpyAsync(dst, v[b]->data(), ps * 8, hipMemcpyDeviceToDevice, c.stream));
+        continue;
+      }
+      auto it = k.rot.find(g);
+      if (it == k.rot.end()) fail(COPSE_EKEY, "rotation key for offset " + std::to_string(rots[u]) + " absent");
+      reqs.push_back(KsReq{b, it->second.get(), g, dst, v[b]->data()});
+    }
+  }
+  ks_batch(c, l, inputs, reqs, 2);
+}
+
+// ------------------------------------------------------------------ MatMul (baby-step / giant-step)
+// babies: B[u][b] for the plan's rotation slots; result: one ciphertext per b (after the switch)
+static std::vector<SCt> b_matmul(Context& c, const Keys& k, const MatPlan& P, const double* B, int G, int level) {
+  const size_t N = c.N;
+  const int nl = level + 1;
+  const size_t ps2 = (size_t)2 * nl * N, ps3 = (size_t)3 * nl * N;
+  const int ng = (int)P.groups.size();
+  DBuf inner(&c, (size_t)ng * G * (P.enc ? ps3 : ps2));
+  if (!P.enc) {
+    launch_mm_inner(c, inner.get(), B, P.d_terms, P.d_off, ng, G, nl, (size_t)G * ps2, ps2);
+  }
+  std::vector<SCt> in2;   // per (group, b) 2-poly inner sums
+  if (P.enc) {
+    launch_mm_inner_enc(c, inner.get(), B, P.d_terms, P.d_off, ng, G, nl, (size_t)G * ps2, ps2);
+    std::vector<SCt> t3;
+    for (int z = 0; z < ng * G; ++z) {
+      auto ct = std::make_shared<Ct>();
+      ct->level = level; ct->npolys = 3; ct->n = N; ct->ptr = inner.get() + (size_t)z * ps3;
+      t3.push_back(ct);
+    }
+    std::vector<const Ct*> in3;
+    for (auto& x : t3) in3.push_back(x.get());
+    in2 = b_relin(c, k, in3);
+  }
+  auto ptr2 = [&](int z) -> const double* { return P.enc ? in2[z]->data() : inner.get() + (size_t)z * ps2; };
+  DBuf rb(&c, (size_t)ng * G * ps2);
+  std::vector<const double*> inputs;
+  std::vector<KsReq> reqs;
+  for (int s = 0; s < ng; ++s) {
+    const uint32_t g = P.groups[s];
+    for (int b = 0; b < G; ++b) {
+      const int z = s * G + b;
+      double* dst = rb.get() + (size_t)z * ps2;
+      if (g == 0) {
+        COPSE_HIP(hipMemcpyAsync(dst, ptr2(z), ps2 * 8, hipMemcpyDeviceToDevice, c.stream));
+        continue;
+      }
+      const uint64_t gal = galois_of(c, (int64_t)g * P.n1);
+      auto it = k.rot.find(gal);
+      if (it == k.rot.end()) fail(COPSE_EKEY, "giant-step key absent");
+      inputs.push_back(ptr2(z) + (size_t)nl * N);
+      reqs.push_back(KsReq{(int)inputs.size() - 1, it->second.get(), gal, dst, ptr2(z)});
+    }
+  }
+  ks_batch(c, level, inputs, reqs, 2);
+  auto sums = alloc_batch(c, G, level, 2);
+  launch_sum_parts(c, sums[0]->data(), rb.get(), ng, (size_t)G * ps2, ps2, nl, 2 * nl, G);
+  std::vector<const Ct*> sin;
+  for (auto& x : sums) sin.push_back(x.get());
+  return b_modswitch(c, sin);
+}
+
+// ------------------------------------------------------------------ sums and masks
+static std::vector<SCt> b_sum_all(Context& c, const std::vector<std::vector<SCt>>& terms_per_b) {
+  // per b: switch every term to the lowest level, then add
+  std::vector<SCt> flat;
+  std::vector<int> tgt;
+  std::vector<size_t> start;
+  for (auto& terms : terms_per_b) {
+    int lv = terms[0]->level;
+    for (auto& t : terms) lv = std::min(lv, t->level);
+    start.push_back(flat.size());
+    for (auto& t : terms) {
+      flat.push_back(t);
+      tgt.push_back(lv);
+    }
+  }
+  flat = b_down(c, flat, tgt);
+  const int G = (int)terms_per_b.size();
+  std::vector<SCt> out(G);
+  // accumulate term by term, all b at once (terms of one b share a level; levels may differ across b)
+  std::map<int, std::vector<int>> by_level;
+  for (int b = 0; b < G; ++b) by_level[flat[start[b]]->level].push_back(b);
+  for (auto& kv : by_level) {
+    const int l = kv.first, nl = l + 1;
+    auto acc = alloc_batch(c, (int)kv.second.size(), l, 2);
+    size_t T = terms_per_b[kv.second[0]].size();
+    for (int b : kv.second)
+      if (terms_per_b[b].size() != T) fail(COPSE_EINVAL, "internal: ragged sums");
+    for (size_t t = 1; t < T; ++t) {
+      std::vector<double*> o;
+      std::vector<const double*> a, bb;
+      for (size_t q = 0; q < kv.second.size(); ++q) {
+        int b = kv.second[q];
+        o.push_back(acc[q]->data());
+        a.push_back(t == 1 ? flat[start[b]]->data() : acc[q]->data());
+        bb.push_back(flat[start[b] + t]->data());
+      }
+      launch_ew_multi(c, 0, o, a, bb, nl, 2 * nl, 2 * nl);
+    }
+    for (size_t q = 0; q < kv.second.size(); ++q) out[kv.second[q]] = T == 1 ? flat[start[kv.second[q]]] : acc[q];
+  }
+  return out;
+}
+
+// ------------------------------------------------------------------ the evaluation
+std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
+                                   const std::vector<std::vector<const Ct*>>& groups) {
+  const int G = (int)groups.size();
+  const int p = (int)M.meta.precision;
+  const size_t N = c.N;
+  for (auto& g : groups) {
+    if ((int)g.size() != p) fail(COPSE_EINVAL, "query group must hold one ciphertext per bit plane");
+    for (auto* x : g)
+      if (x->npolys != 2 || x->level != c.L) fail(COPSE_EINVAL, "query ciphertexts must be fresh (top level)");
+  }
+  auto view = [](const Ct* x) { return SCt(const_cast<Ct*>(x), [](Ct*) {}); };
+  // 1. comparison
+  std::vector<std::vector<SCt>> eq(p, std::vector<SCt>(G)), lt(p, std::vector<SCt>(G));
+  if (!M.encrypted) {
+    const int L = c.L, nl = L + 1;
+    const int J = (2 * p - 1) * G;
+    auto raw = alloc_batch(c, J, L, 2);
+    std::vector<double*> out;
+    std::vector<const double*> a, mul, add;
+    int z = 0;
+    std::vector<std::pair<int, int>> where;   // (k, is_eq)
+    for (int kb = 0; kb < p; ++kb)
+      for (int e = (kb >= 1 ? 1 : 0); e >= 0; --e)
+        for (int b = 0; b < G; ++b) {
+          out.push_back(raw[z++]->data());
+          a.push_back(groups[b][kb]->data());
+          mul.push_back(e ? M.E[kb].pt->buf.get() : M.G[kb].pt->buf.get());
+          add.push_back(e ? M.C[kb].pt->buf.get() : M.TH[kb].pt->buf.get());
+          where.push_back({kb, e});
+        }
+    launch_ptlayer(c, out, a, mul, add, nl);
+    std::vector<const Ct*> rin;
+    for (auto& x : raw) rin.push_back(x.get());
+    auto sw = b_modswitch(c, rin);
+    z = 0;
+    for (int kb = 0; kb < p; ++kb)
+      for (int e = (kb >= 1 ? 1 : 0); e >= 0; --e)
+        for (int b = 0; b < G; ++b) (e ? eq : lt)[kb][b] = sw[z++];
+  } else {
+    std::vector<std::pair<SCt, SCt>> pairs;
+    for (int kb = 0; kb < p; ++kb)
+      for (int b = 0; b < G; ++b) pairs.push_back({view(groups[b][kb]), view(M.TH[kb].ct.get())});
+    auto u = b_mul(c, k, pairs);
+    std::vector<const Ct*> xin, tin;
+    for (int kb = 0; kb < p; ++kb) {
+      tin.push_back(M.TH[kb].ct.get());
+      for (int b = 0; b < G; ++b) xin.push_back(groups[b][kb]);
+    }
+    auto xs = b_modswitch(c, xin);
+    auto ts = b_modswitch(c, tin);
+    const int l = c.L - 1, nl = l + 1;
+    auto eqb = alloc_batch(c, p * G, l, 2), ltb = alloc_batch(c, p * G, l, 2);
+    std::vector<double*> pe, pl;
+    std::vector<const double*> pu, px, pt;
+    for (int kb = 0; kb < p; ++kb)
+      for (int b = 0; b < G; ++b) {
+        int z = kb * G + b;
+        pe.push_back(kb >= 1 ? eqb[z]->data() : nullptr);
+        pl.push_back(ltb[z]->data());
+        pu.push_back(u[z]->data());
+        px.push_back(xs[z]->data());
+        pt.push_back(ts[kb]->data());
+        if (kb >= 1) eq[kb][b] = eqb[z];
+        lt[kb][b] = ltb[z];
+      }
+    launch_seccomp_combine(c, pe, pl, pu, px, pt, nl);
+  }
+  // prefix products of (eq_{p-1}, ..., eq_1), Kogge-Stone
+  std::vector<std::vector<SCt>> cur(p - 1, std::vector<SCt>(G));
+  for (int i = 0; i < p - 1; ++i)
+    for (int b = 0; b < G; ++b) cur[i][b] = eq[p - 1 - i][b];
+  for (int s = 1; s < p - 1; s *= 2) {
+    std::vector<std::pair<SCt, SCt>> pairs;
+    for (int i = s; i < p - 1; ++i)
+      for (int b = 0; b < G; ++b) pairs.push_back({cur[i][b], cur[i - s][b]});
+    auto r = b_mul(c, k, pairs);
+    auto nxt = cur;
+    size_t z = 0;
+    for (int i = s; i < p - 1; ++i)
+      for (int b = 0; b < G; ++b) nxt[i][b] = r[z++];
+    cur = std::move(nxt);
+  }
+  std::vector<std::pair<SCt, SCt>> fin;
+  for (int kb = 0; kb < p - 1; ++kb)
+    for (int b = 0; b < G; ++b) fin.push_back({lt[kb][b], cur[p - 2 - kb][b]});
+  auto prods = b_mul(c, k, fin);
+  std::vector<std::vector<SCt>> terms(G);
+  for (int b = 0; b < G; ++b) {
+    terms[b].push_back(lt[p - 1][b]);
+    for (int kb = 0; kb < p - 1; ++kb) terms[b].push_back(prods[kb * G + b]);
+  }
+  std::vector<SCt> dec = b_sum_all(c, terms);
+  for (auto& x : dec)
+    if (x->level != M.dec_level) fail(COPSE_EINVAL, "internal: comparison ended at an unexpected level");
+  // 2. reshuffle
+  std::vector<SCt> src = dec;
+  if (!M.meta.fold) {
+    const MatPlan& P = M.plan_R;
+    const int l = dec[0]->level;
+    DBuf B(&c, P.rots.size() * G * 2 * (size_t)(l + 1) * N);
+    std::vector<const Ct*> v;
+    for (auto& x : dec) v.push_back(x.get());
+    b_rotate_into(c, k, v, P.rots, B.get());
+    src = b_matmul(c, k, P, B.get(), G, l);
+  }
+  // 3. levels: one set of hoisted baby rotations shared by every level
+  std::vector<std::vector<SCt>> lv(M.meta.d);
+  {
+    const int l = src[0]->level;
+    DBuf B(&c, M.lvl_rots.size() * G * 2 * (size_t)(l + 1) * N);
+    std::vector<const Ct*> v;
+    for (auto& x : src) v.push_back(x.get());
+    b_rotate_into(c, k, v, M.lvl_rots, B.get());
+    for (uint32_t L_ = 0; L_ < M.meta.d; ++L_) {
+      auto r = b_matmul(c, k, M.plan_L[L_], B.get(), G, l);
+      // mask
+      const int ml = r[0]->level, nl = ml + 1;
+      auto outb = alloc_batch(c, G, ml, 2);
+      std::vector<double*> o;
+      std::vector<const double*> a, m;
+      for (int b = 0; b < G; ++b) {
+        o.push_back(outb[b]->data());
+        a.push_back(r[b]->data());
+      }
+      if (M.masks[L_].ct) {
+        if (M.masks[L_].ct->level != ml) fail(COPSE_EINVAL, "internal: mask level");
+        for (int b = 0; b < G; ++b) m.push_back(M.masks[L_].ct->data());
+        launch_ew_multi(c, 0, o, a, m, nl, 2 * nl, 2 * nl);
+      } else {
+        // plaintext mask goes to c0 only; c1 is copied
+        for (int b = 0; b < G; ++b) {
+          m.push_back(M.masks[L_].pt->buf.get());
+          COPSE_HIP(hipMemcpyAsync(outb[b]->poly(1, N), r[b]->poly(1, N), (size_t)nl * N * 8,
+                                   hipMemcpyDeviceToDevice, c.stream));
+        }
+        launch_ew_multi(c, 0, o, a, m, nl, nl, nl);
+      }
+      lv[L_] = outb;
+    }
+  }
+  // 4. product tree
+  while (lv.size() > 1) {
+    std::vector<std::pair<SCt, SCt>> pairs;
+    for (size_t i = 0; i + 1 < lv.size(); i += 2)
+      for (int b = 0; b < G; ++b) pairs.push_back({lv[i][b], lv[i + 1][b]});
+    auto r = b_mul(c, k, pairs);
+    std::vector<std::vector<SCt>> nxt;
+    size_t z = 0;
+    for (size_t i = 0; i + 1 < lv.size(); i += 2) {
+      nxt.emplace_back();
+      for (int b = 0; b < G; ++b) nxt.back().push_back(r[z++]);
+    }
+    if (lv.size() % 2) nxt.push_back(lv.back());
+    lv = std::move(nxt);
+  }
+  std::vector<SCt> res = b_down(c, lv[0], std::vector<int>(G, 0));
+  std::vector<CtPtr> out;
+  for (int b = 0; b < G; ++b) out.push_back(std::make_unique<Ct>(*res[b]));   // shares the storage
+  return out;
+}
+
+CtPtr evaluate_group(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes) {
+  auto r = evaluate_groups(c, M, k, {planes});
+  return std::move(r[0]);
+}
+
+}  // namespace copse

@@ -28,10 +28,6 @@
 
 namespace copse {
 
-using SCt = std::shared_ptr<Ct>;
-
-static SCt share(CtPtr p) { return SCt(p.release()); }
-
 static int seccomp_depth(uint32_t p) {
   if (p <= 2) return (int)p;
   int r = 0;
@@ -71,7 +67,7 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
     bool nz = std::any_of(slots.begin(), slots.end(), [](uint64_t v) { return v != 0; });
     if (encrypt_model) {
       o.ct = enc_slots(slots, level, obj);
-      M->bytes += o.ct->buf.size() * 8;
+      M->bytes += o.ct->words() * 8;
     } else if (nz || !skip_zero) {
       o.pt = make_plain_slots(c, slots.data(), level);
       M->bytes += o.pt->buf.size() * 8;
@@ -148,158 +144,61 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
     replicate_blocks(meta, N, mk, slots, t);
     M->masks.push_back(make_operand(slots, M->lvl_level, obj_id(5, 0, l), false));
   }
+  // matrix-product plans; the level products share one set of baby rotations
+  if (!meta.fold) build_plan(c, M->plan_R, M->rdiag, meta.n1_R, encrypt_model, nullptr);
+  {
+    std::set<int32_t> used;
+    for (auto& dl : M->ldiag)
+      for (size_t kd = 0; kd < dl.size(); ++kd)
+        if (!dl[kd].zero()) used.insert((int32_t)(kd % meta.n1_L));
+    M->lvl_rots.assign(used.begin(), used.end());
+  }
+  M->plan_L.resize(meta.d);
+  for (uint32_t l = 0; l < meta.d; ++l) build_plan(c, M->plan_L[l], M->ldiag[l], meta.n1_L, encrypt_model, &M->lvl_rots);
   COPSE_HIP(hipStreamSynchronize(c.stream));
   return M;
 }
 
-// ------------------------------------------------------------------ evaluation of one group
-namespace {
-struct Eval {
-  Context& c;
-  const Model& M;
-  const Keys& k;
-
-  SCt mul(const SCt& a, const SCt& b) { return share(op_mul(c, k, *a, *b)); }
-
-  SCt sum_all(std::vector<SCt> terms) {
-    int lv = terms[0]->level;
-    for (auto& t : terms) lv = std::min(lv, t->level);
-    for (auto& t : terms)
-      if (t->level > lv) t = share(op_modswitch_to(c, *t, lv));
-    SCt out = terms[0];
-    for (size_t i = 1; i < terms.size(); ++i) out = share(op_add(c, *out, *terms[i]));
-    return out;
-  }
-
-  SCt seccomp(const std::vector<const Ct*>& X) {
-    const int p = (int)X.size();
-    std::vector<SCt> eq(p), lt(p);
-    for (int kb = 0; kb < p; ++kb) {
-      if (!M.encrypted) {
-        if (kb >= 1) {
-          auto t1 = op_mul_plain(c, *X[kb], *M.E[kb].pt);
-          auto t2 = op_add_plain(c, *t1, *M.C[kb].pt);
-          eq[kb] = share(op_modswitch(c, *t2));
-        }
-        auto t1 = op_mul_plain(c, *X[kb], *M.G[kb].pt);
-        auto t2 = op_add_plain(c, *t1, *M.TH[kb].pt);
-        lt[kb] = share(op_modswitch(c, *t2));
-      } else {
-        const Ct& th = *M.TH[kb].ct;
-        auto u = share(op_mul(c, k, *X[kb], th));
-        auto xs = op_modswitch(c, *X[kb]);
-        auto ts = op_modswitch(c, th);
-        if (kb >= 1) {
-          auto u2 = op_mul_int(c, *u, 2);
-          auto a1 = op_sub(c, *u2, *xs);
-          auto a2 = op_sub(c, *a1, *ts);
-          eq[kb] = share(op_add_const(c, *a2, 1));
-        }
-        lt[kb] = share(op_sub(c, *ts, *u));
-      }
-    }
-    std::vector<SCt> cur;
-    for (int i = 0; i < p - 1; ++i) cur.push_back(eq[p - 1 - i]);
-    for (size_t s = 1; s < cur.size(); s *= 2) {
-      std::vector<SCt> nxt = cur;
-      for (size_t i = s; i < cur.size(); ++i) nxt[i] = mul(cur[i], cur[i - s]);
-      cur = std::move(nxt);
-    }
-    std::vector<SCt> terms{lt[p - 1]};
-    for (int kb = 0; kb < p - 1; ++kb) terms.push_back(mul(lt[kb], cur[p - 2 - kb]));
-    return sum_all(terms);
-  }
-
-  SCt matmul(const SCt& v, const std::vector<Operand>& diags, uint32_t n1) {
-    const uint32_t n = (uint32_t)diags.size();
-    const uint32_t n2 = (n + n1 - 1) / n1;
+// ------------------------------------------------------------------ matrix-product plans
+void build_plan(Context& c, MatPlan& P, const std::vector<Operand>& diags, uint32_t n1, bool enc,
+                const std::vector<int32_t>* shared_rots) {
+  const uint32_t n = (uint32_t)diags.size();
+  P.n1 = n1;
+  P.enc = enc;
+  if (shared_rots) {
+    P.rots = *shared_rots;
+  } else {
     std::set<int32_t> used;
     for (uint32_t kd = 0; kd < n; ++kd)
       if (!diags[kd].zero()) used.insert((int32_t)(kd % n1));
-    std::vector<int32_t> rs(used.begin(), used.end());
-    auto baby_v = op_rotate_hoisted(c, k, *v, rs);
-    std::map<int32_t, size_t> at;
-    for (size_t i = 0; i < rs.size(); ++i) at[rs[i]] = i;
-    const size_t N = c.N;
-    const int nl = v->level + 1;
-    std::vector<SCt> parts;
-    for (uint32_t g = 0; g < n2; ++g) {
-      std::vector<std::pair<uint32_t, const Operand*>> terms;
-      for (uint32_t j = 0; j < n1; ++j) {
-        uint32_t kd = g * n1 + j;
-        if (kd < n && !diags[kd].zero()) terms.push_back({j, &diags[kd]});
-      }
-      if (terms.empty()) continue;
-      CtPtr inner;
-      if (!M.encrypted) {
-        inner = ct_alloc(c, v->level, 2);
-        bool first = true;
-        for (auto& tj : terms) {
-          const Ct& bj = *baby_v[at[(int32_t)tj.first]];
-          if (first) launch_mul_plain(c, inner->buf.get(), bj.buf.get(), tj.second->pt->buf.get(), 2, nl);
-          else launch_mac_plain(c, inner->buf.get(), bj.buf.get(), tj.second->pt->buf.get(), 2, nl);
-          first = false;
-        }
-      } else {
-        auto acc = ct_alloc(c, v->level, 3);
-        bool first = true;
-        for (auto& tj : terms) {
-          const Ct& bj = *baby_v[at[(int32_t)tj.first]];
-          const Ct& dj = *tj.second->ct;
-          if (dj.level != v->level) fail(COPSE_EINVAL, "encrypted diagonal at the wrong level");
-          launch_tensor(c, acc->buf.get(), bj.buf.get(), dj.buf.get(), nl, !first);
-          first = false;
-        }
-        inner = op_relin(c, k, *acc);
-      }
-      (void)N;
-      if (g > 0) inner = op_rotate(c, k, *inner, (int32_t)(g * n1));
-      parts.push_back(share(std::move(inner)));
-    }
-    SCt out = parts[0];
-    for (size_t i = 1; i < parts.size(); ++i) out = share(op_add(c, *out, *parts[i]));
-    return share(op_modswitch(c, *out));
+    P.rots.assign(used.begin(), used.end());
   }
-
-  SCt add_mask(const SCt& a, const Operand& mk) {
-    if (mk.ct) return share(op_add(c, *a, *mk.ct));
-    return share(op_add_plain(c, *a, *mk.pt));
-  }
-
-  CtPtr run(const std::vector<const Ct*>& X) {
-    if (X.size() != M.meta.precision) fail(COPSE_EINVAL, "query group must hold one ciphertext per bit plane");
-    for (auto* x : X)
-      if (x->npolys != 2 || x->level != c.L) fail(COPSE_EINVAL, "query ciphertexts must be fresh (top level)");
-    SCt dec = seccomp(X);
-    if (dec->level != M.dec_level) fail(COPSE_EINVAL, "internal: comparison ended at an unexpected level");
-    std::vector<SCt> lv;
-    if (M.meta.fold) {
-      for (uint32_t l = 0; l < M.meta.d; ++l) lv.push_back(add_mask(matmul(dec, M.ldiag[l], M.meta.n1_L), M.masks[l]));
-    } else {
-      SCt br = matmul(dec, M.rdiag, M.meta.n1_R);
-      for (uint32_t l = 0; l < M.meta.d; ++l) lv.push_back(add_mask(matmul(br, M.ldiag[l], M.meta.n1_L), M.masks[l]));
+  std::map<int32_t, int> slot;
+  for (size_t u = 0; u < P.rots.size(); ++u) slot[P.rots[u]] = (int)u;
+  std::vector<MMTerm> terms;
+  std::vector<int> off{0};
+  const uint32_t n2 = (n + n1 - 1) / n1;
+  for (uint32_t g = 0; g < n2; ++g) {
+    size_t before = terms.size();
+    for (uint32_t j = 0; j < n1; ++j) {
+      uint32_t kd = g * n1 + j;
+      if (kd >= n || diags[kd].zero()) continue;
+      const double* dp = enc ? diags[kd].ct->data() : diags[kd].pt->buf.get();
+      terms.push_back(MMTerm{slot.at((int32_t)j), dp});
     }
-    while (lv.size() > 1) {
-      std::vector<SCt> nxt;
-      for (size_t i = 0; i + 1 < lv.size(); i += 2) nxt.push_back(mul(lv[i], lv[i + 1]));
-      if (lv.size() % 2) nxt.push_back(lv.back());
-      lv = std::move(nxt);
+    if (terms.size() > before) {
+      P.groups.push_back(g);
+      off.push_back((int)terms.size());
     }
-    return op_modswitch_to(c, *lv[0], 0);
   }
-};
-}  // namespace
-
-CtPtr evaluate_group(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes) {
-  Eval e{c, M, k};
-  return e.run(planes);
-}
-
-std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
-                                   const std::vector<std::vector<const Ct*>>& groups) {
-  std::vector<CtPtr> out;
-  for (auto& g : groups) out.push_back(evaluate_group(c, M, k, g));
-  return out;
+  P.terms_buf = DBuf(&c, std::max<size_t>(1, terms.size()) * 2);
+  P.off_buf = DBuf(&c, (off.size() + 1) / 2 + 1);
+  COPSE_HIP(hipMemcpyAsync(P.terms_buf.get(), terms.data(), terms.size() * sizeof(MMTerm), hipMemcpyHostToDevice,
+                           c.stream));
+  COPSE_HIP(hipMemcpyAsync(P.off_buf.get(), off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  COPSE_HIP(hipStreamSynchronize(c.stream));
+  P.d_terms = reinterpret_cast<const MMTerm*>(P.terms_buf.get());
+  P.d_off = reinterpret_cast<const int*>(P.off_buf.get());
 }
 
 }  // namespace copse

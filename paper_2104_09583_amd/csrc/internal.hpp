@@ -119,13 +119,18 @@ class DBuf {
   size_t n_ = 0;
 };
 
-// A ciphertext (or a 3-component tensor) in NTT form: [npolys][level+1][N].
+// A ciphertext (or a 3-component tensor) in NTT form: [npolys][level+1][N] starting at ptr.
+// The storage may be shared by several ciphertexts produced by one batched launch.
 struct Ct {
   int level = 0;
   int npolys = 0;
-  DBuf buf;
-  double* poly(int k, size_t N) const { return buf.get() + (size_t)k * (level + 1) * N; }
+  std::shared_ptr<DBuf> store;
+  double* ptr = nullptr;
+  size_t n = 0;   // ring dimension
+  double* data() const { return ptr; }
+  double* poly(int k, size_t N) const { return ptr + (size_t)k * (level + 1) * N; }
   size_t limbs() const { return (size_t)level + 1; }
+  size_t words() const { return (size_t)npolys * (level + 1) * n; }
 };
 using CtPtr = std::unique_ptr<Ct>;
 
@@ -239,6 +244,50 @@ void launch_moddown_finish(Context& c, double* out, const double* y, size_t y_po
                            int npolys, int nl, const double* pinv, const double* tpinv,
                            const double* add, size_t add_poly_stride, int add_mode);
 void launch_add_const(Context& c, double* a, int nl, double v);
+
+// ------------------------------------------------------------------ batched launchers
+constexpr int kPack = 64;
+struct Pack { const double* p[kPack]; };
+struct MPack { double* p[kPack]; };
+struct GPack { uint64_t g[kPack]; };
+struct KsJob2 {
+  const double* in;      // input poly (NTT form, nl limbs): the digit's own limbs
+  const double* ext;     // [D][nE][N] ModUp output (target rows only)
+  const double* kb;
+  const double* ka;
+  double* acc;           // [2][nE][N]
+  uint64_t g;
+};
+struct KsPack {
+  static constexpr int kMax = 16;
+  KsJob2 j[kMax];
+};
+struct MMTerm {
+  int u;                 // baby slot
+  const double* diag;    // plaintext [nl][N] or ciphertext [2][nl][N]
+};
+void launch_gather(Context& c, double* dst, const std::vector<const double*>& src, int rows);
+void launch_ew_multi(Context& c, int op, const std::vector<double*>& out, const std::vector<const double*>& a,
+                     const std::vector<const double*>& b, int nl, int rows_per_job, int b_rows);
+void launch_ptlayer(Context& c, const std::vector<double*>& out, const std::vector<const double*>& a,
+                    const std::vector<const double*>& mul, const std::vector<const double*>& add, int nl);
+void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::vector<const double*>& a,
+                         const std::vector<const double*>& b, int nl);
+void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
+                            const double* w, int np, int level, const double* tab);
+void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds);
+void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
+                       const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE, int nl,
+                       const double* pinv, const double* tpinv, int add_mode);
+void launch_mm_inner(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
+                     int n_groups, int G, int nl, size_t baby_slot, size_t baby_b);
+void launch_mm_inner_enc(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
+                         int n_groups, int G, int nl, size_t baby_slot, size_t baby_b);
+void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
+                      int nl, int rows, int G);
+void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const std::vector<double*>& lt,
+                            const std::vector<const double*>& u, const std::vector<const double*>& xs,
+                            const std::vector<const double*>& ts, int nl);
 
 // profiling hooks
 void prof_begin(Context& c, int kind, hipEvent_t* ev);

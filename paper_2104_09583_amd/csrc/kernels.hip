@@ -174,6 +174,205 @@ __global__ __launch_bounds__(kThreads) void ntt_rows_kernel(double* __restrict__
   }
 }
 
+// ------------------------------------------------------------------ register-radix NTT (log N >= 11)
+// Column pass: stages 0..S1-1 touch only the 2^S1 elements r*C + c (r < 2^S1, C = N >> S1) of one
+// column c, so one thread keeps a whole column in registers and needs no LDS.  Consecutive
+// threads take consecutive columns: every load and store of a wavefront is one contiguous run.
+__device__ __forceinline__ void bfly_ct(double& x, double& y, double w, double q, double qinv) {
+  double v = mod_mul(y, w, q, qinv);
+  double u = x;
+  x = mod_add(u, v, q);
+  y = mod_sub(u, v, q);
+}
+__device__ __forceinline__ void bfly_gs(double& x, double& y, double w, double q, double qinv) {
+  double u = x, v = y;
+  x = mod_add(u, v, q);
+  y = mod_mul(mod_sub(u, v, q), w, q, qinv);
+}
+
+template <int S1, bool kInverse>
+__global__ __launch_bounds__(64) void ntt_colreg_kernel(double* __restrict__ base, const int2* __restrict__ rows,
+                                                       const DevPrime* __restrict__ P, int logN, int scale) {
+  constexpr int R = 1 << S1;
+  const int2 row = rows[blockIdx.y];
+  const DevPrime pr = P[row.y];
+  const size_t N = (size_t)1 << logN;
+  const size_t C = N >> S1;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double* a = base + (size_t)row.x * N;
+  double x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = a[r * C + c];
+  if (!kInverse) {
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int half = R >> (s + 1);
+#pragma unroll
+      for (int g = 0; g < (1 << s); ++g) {
+        const double w = pr.fwd[(1 << s) + g];
+#pragma unroll
+        for (int o = 0; o < half; ++o) bfly_ct(x[g * 2 * half + o], x[g * 2 * half + o + half], w, pr.q, pr.qinv);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = S1 - 1; s >= 0; --s) {
+      const int half = R >> (s + 1);
+#pragma unroll
+      for (int g = 0; g < (1 << s); ++g) {
+        const double w = pr.inv[(1 << s) + g];
+#pragma unroll
+        for (int o = 0; o < half; ++o) bfly_gs(x[g * 2 * half + o], x[g * 2 * half + o + half], w, pr.q, pr.qinv);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = x[r];
+    if (scale) v = mod_mul(v, pr.ninv, pr.q, pr.qinv);
+    a[r * C + c] = v;
+  }
+}
+
+// Row pass over a tile of 2048 contiguous elements (stages S1..S1+10): 256 threads x 8 registers.
+// Three radix-8 rounds (distances 1024/512/256, 128/64/32, 16/8/4) and one radix-4 round
+// (2/1), with the tile exchanged through LDS between rounds.  A thread's 8 elements j0 + d k lie in
+// one aligned block of 8d, so the three stages of a round need 1, 2 and 4 twiddles.
+__device__ __forceinline__ int lds_idx(int j) { return j + (j >> 4); }
+constexpr int kLdsTile = 2048 + 2048 / 16;
+
+__device__ __forceinline__ void radix8_ct(double* x, size_t gb, size_t d, size_t m, const DevPrime& pr) {
+  const size_t g0 = gb / (8 * d);
+  const double w0 = pr.fwd[m + g0];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_ct(x[k], x[k + 4], w0, pr.q, pr.qinv);
+  const double w1a = pr.fwd[2 * m + 2 * g0], w1b = pr.fwd[2 * m + 2 * g0 + 1];
+  bfly_ct(x[0], x[2], w1a, pr.q, pr.qinv);
+  bfly_ct(x[1], x[3], w1a, pr.q, pr.qinv);
+  bfly_ct(x[4], x[6], w1b, pr.q, pr.qinv);
+  bfly_ct(x[5], x[7], w1b, pr.q, pr.qinv);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_ct(x[2 * k], x[2 * k + 1], pr.fwd[4 * m + 4 * g0 + k], pr.q, pr.qinv);
+}
+__device__ __forceinline__ void radix8_gs(double* x, size_t gb, size_t d, size_t m, const DevPrime& pr) {
+  const size_t g0 = gb / (8 * d);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_gs(x[2 * k], x[2 * k + 1], pr.inv[4 * m + 4 * g0 + k], pr.q, pr.qinv);
+  const double w1a = pr.inv[2 * m + 2 * g0], w1b = pr.inv[2 * m + 2 * g0 + 1];
+  bfly_gs(x[0], x[2], w1a, pr.q, pr.qinv);
+  bfly_gs(x[1], x[3], w1a, pr.q, pr.qinv);
+  bfly_gs(x[4], x[6], w1b, pr.q, pr.qinv);
+  bfly_gs(x[5], x[7], w1b, pr.q, pr.qinv);
+  const double w0 = pr.inv[m + g0];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_gs(x[k], x[k + 4], w0, pr.q, pr.qinv);
+}
+
+template <bool kInverse>
+__global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ base, const int2* __restrict__ rows,
+                                                        const DevPrime* __restrict__ P, int logN, int S1, int scale) {
+  __shared__ double sh[kLdsTile];
+  const int2 row = rows[blockIdx.y];
+  const DevPrime pr = P[row.y];
+  const size_t N = (size_t)1 << logN;
+  double* a = base + (size_t)row.x * N;
+  const int t = threadIdx.x;
+  const size_t t0 = (size_t)blockIdx.x * 2048;
+  const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
+  double x[8];
+  // round geometry: A: j0 = t, d = 256; B: j0 = (t/32)*256 + t%32, d = 32; C: j0 = (t/4)*32 + t%4, d = 4;
+  // D: two groups of 4 at 8t and 8t+4 (distances 2 and 1)
+  const int jA = t, jB = (t >> 5) * 256 + (t & 31), jC = (t >> 2) * 32 + (t & 3), jD = 8 * t;
+  if (!kInverse) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = a[t0 + jA + 256 * k];
+    radix8_ct(x, t0 + jA, 256, mA, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 256 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 32 * k)];
+    radix8_ct(x, t0 + jB, 32, mB, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 32 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 4 * k)];
+    radix8_ct(x, t0 + jC, 4, mC, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 4 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const size_t gb = t0 + jD + 4 * u;
+      double* y = x + 4 * u;
+      const double w = pr.fwd[mD + gb / 4];
+      bfly_ct(y[0], y[2], w, pr.q, pr.qinv);
+      bfly_ct(y[1], y[3], w, pr.q, pr.qinv);
+      bfly_ct(y[0], y[1], pr.fwd[2 * mD + gb / 2], pr.q, pr.qinv);
+      bfly_ct(y[2], y[3], pr.fwd[2 * mD + gb / 2 + 1], pr.q, pr.qinv);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[t0 + jD + k] = x[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = a[t0 + jD + k];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const size_t gb = t0 + jD + 4 * u;
+      double* y = x + 4 * u;
+      bfly_gs(y[0], y[1], pr.inv[2 * mD + gb / 2], pr.q, pr.qinv);
+      bfly_gs(y[2], y[3], pr.inv[2 * mD + gb / 2 + 1], pr.q, pr.qinv);
+      const double w = pr.inv[mD + gb / 4];
+      bfly_gs(y[0], y[2], w, pr.q, pr.qinv);
+      bfly_gs(y[1], y[3], w, pr.q, pr.qinv);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 4 * k)];
+    radix8_gs(x, t0 + jC, 4, mC, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 4 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 32 * k)];
+    radix8_gs(x, t0 + jB, 32, mB, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 32 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 256 * k)];
+    radix8_gs(x, t0 + jA, 256, mA, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      double v = x[k];
+      if (scale) v = mod_mul(v, pr.ninv, pr.q, pr.qinv);
+      a[t0 + jA + 256 * k] = v;
+    }
+  }
+}
+
+template <bool kInverse>
+static void launch_colreg(Context& c, double* base, const int2* rows, int nrows, int S1, int scale) {
+  const unsigned C = (unsigned)(c.N >> S1);
+  dim3 grid((C + 63) / 64, nrows), blk(64);
+  const int logN = (int)c.log_n;
+  switch (S1) {
+    case 1: hipLaunchKernelGGL((ntt_colreg_kernel<1, kInverse>), grid, blk, 0, c.stream, base, rows, c.d_primes, logN, scale); break;
+    case 2: hipLaunchKernelGGL((ntt_colreg_kernel<2, kInverse>), grid, blk, 0, c.stream, base, rows, c.d_primes, logN, scale); break;
+    case 3: hipLaunchKernelGGL((ntt_colreg_kernel<3, kInverse>), grid, blk, 0, c.stream, base, rows, c.d_primes, logN, scale); break;
+    case 4: hipLaunchKernelGGL((ntt_colreg_kernel<4, kInverse>), grid, blk, 0, c.stream, base, rows, c.d_primes, logN, scale); break;
+    case 5: hipLaunchKernelGGL((ntt_colreg_kernel<5, kInverse>), grid, blk, 0, c.stream, base, rows, c.d_primes, logN, scale); break;
+    case 6: hipLaunchKernelGGL((ntt_colreg_kernel<6, kInverse>), grid, blk, 0, c.stream, base, rows, c.d_primes, logN, scale); break;
+    default: fail(COPSE_EINVAL, "ring too large for the column pass");
+  }
+}
+
 static void split_stages(int logN, int& S1) {
   int S2 = logN < 11 ? logN : 11;   // 2^11 = kTile
   S1 = logN - S2;
@@ -185,6 +384,14 @@ void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows) {
   prof_begin(c, 0, &ev);
   int logN = (int)c.log_n, S1;
   split_stages(logN, S1);
+  if (logN >= 11) {
+    if (S1 > 0) launch_colreg<false>(c, base, rows, nrows, S1, 0);
+    hipLaunchKernelGGL(ntt_rowreg_kernel<false>, dim3((unsigned)(c.N / 2048), nrows), dim3(256), 0, c.stream, base,
+                       rows, c.d_primes, logN, S1, 0);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 0, ev, nrows);
+    return;
+  }
   size_t N = c.N;
   if (S1 > 0)
     hipLaunchKernelGGL(ntt_cols_kernel<false>, dim3((unsigned)((N >> S1) / (kTile >> S1)), nrows), dim3(kThreads),
@@ -202,6 +409,14 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
   prof_begin(c, 1, &ev);
   int logN = (int)c.log_n, S1;
   split_stages(logN, S1);
+  if (logN >= 11) {
+    hipLaunchKernelGGL(ntt_rowreg_kernel<true>, dim3((unsigned)(c.N / 2048), nrows), dim3(256), 0, c.stream, base,
+                       rows, c.d_primes, logN, S1, S1 == 0 ? 1 : 0);
+    if (S1 > 0) launch_colreg<true>(c, base, rows, nrows, S1, 1);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 1, ev, nrows);
+    return;
+  }
   size_t N = c.N;
   unsigned tiles = (unsigned)(N > (size_t)kTile ? N / kTile : 1);
   hipLaunchKernelGGL(ntt_rows_kernel<true>, dim3(tiles, nrows), dim3(kThreads), 0, c.stream, base, rows,
@@ -551,6 +766,371 @@ void launch_moddown_finish(Context& c, double* out, const double* y, size_t ys, 
                      c.stream, out, y, ys, w, nl, pinv, tpinv, add, adds, add_mode, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
   prof_end(c, 4, ev, (double)nl * npolys);
+}
+
+}  // namespace copse
+
+// ================================================================== batched kernels
+// Operations over many ciphertexts at once take per-job pointers by value
+// (Pack: up to kPack jobs per launch; longer lists are launched in chunks).
+namespace copse {
+
+// dst row (j * rows + r) <- src_j row r
+__global__ void gather_kernel(double* dst, Pack src, int rows, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int r = blockIdx.y, j = blockIdx.z;
+  dst[((size_t)j * rows + r) * N + i] = src.p[j][(size_t)r * N + i];
+}
+
+void launch_gather(Context& c, double* dst, const std::vector<const double*>& src, int rows) {
+  for (size_t first = 0; first < src.size(); first += kPack) {
+    int cnt = (int)std::min<size_t>(kPack, src.size() - first);
+    Pack pk;
+    for (int k = 0; k < cnt; ++k) pk.p[k] = src[first + k];
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((c.N + 255) / 256), rows, cnt), dim3(256), 0, c.stream,
+                       dst + first * rows * c.N, pk, rows, (int)c.log_n);
+  }
+  COPSE_HIP(hipGetLastError());
+}
+
+// out_j = a_j (op) b_j over rows_per_job rows (row r has prime r % nl); b row = r % b_rows
+__global__ void ew_multi_kernel(MPack out, Pack a, Pack b, int op, int nl, int b_rows, const DevPrime* P,
+                                int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int r = blockIdx.y, j = blockIdx.z;
+  const DevPrime& pr = P[r % nl];
+  const double x = a.p[j][(size_t)r * N + i];
+  const double y = b.p[j][(size_t)(r % b_rows) * N + i];
+  double v;
+  switch (op) {
+    case 0: v = mod_add(x, y, pr.q); break;
+    case 1: v = mod_sub(x, y, pr.q); break;
+    default: v = mod_mul(x, y, pr.q, pr.qinv); break;
+  }
+  out.p[j][(size_t)r * N + i] = v;
+}
+
+void launch_ew_multi(Context& c, int op, const std::vector<double*>& out, const std::vector<const double*>& a,
+                     const std::vector<const double*>& b, int nl, int rows_per_job, int b_rows) {
+  for (size_t first = 0; first < out.size(); first += kPack) {
+    int cnt = (int)std::min<size_t>(kPack, out.size() - first);
+    MPack po;
+    Pack pa, pb;
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k];
+      pa.p[k] = a[first + k];
+      pb.p[k] = b[first + k];
+    }
+    hipEvent_t ev;
+    prof_begin(c, 4, &ev);
+    hipLaunchKernelGGL(ew_multi_kernel, dim3((unsigned)((c.N + 255) / 256), rows_per_job, cnt), dim3(256), 0,
+                       c.stream, po, pa, pb, op, nl, b_rows, c.d_primes, (int)c.log_n);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 4, ev, (double)rows_per_job * cnt);
+  }
+}
+
+// plaintext layer: out_j = (a0 * m_j + p_j, a1 * m_j)  (2 polys, nl limbs)
+__global__ void ptlayer_kernel(MPack out, Pack a, Pack mul, Pack add, int nl, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int l = blockIdx.y, j = blockIdx.z;
+  const DevPrime& pr = P[l];
+  const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
+  const double m = mul.p[j][o];
+  out.p[j][o] = mod_add(mod_mul(a.p[j][o], m, pr.q, pr.qinv), add.p[j][o], pr.q);
+  out.p[j][ps + o] = mod_mul(a.p[j][ps + o], m, pr.q, pr.qinv);
+}
+
+void launch_ptlayer(Context& c, const std::vector<double*>& out, const std::vector<const double*>& a,
+                    const std::vector<const double*>& mul, const std::vector<const double*>& add, int nl) {
+  for (size_t first = 0; first < out.size(); first += kPack) {
+    int cnt = (int)std::min<size_t>(kPack, out.size() - first);
+    MPack po;
+    Pack pa, pm, pd;
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k]; pa.p[k] = a[first + k]; pm.p[k] = mul[first + k]; pd.p[k] = add[first + k];
+    }
+    hipLaunchKernelGGL(ptlayer_kernel, dim3((unsigned)((c.N + 255) / 256), nl, cnt), dim3(256), 0, c.stream, po, pa,
+                       pm, pd, nl, c.d_primes, (int)c.log_n);
+  }
+  COPSE_HIP(hipGetLastError());
+}
+
+// d_j = (a0 b0, a0 b1 + a1 b0, a1 b1)
+__global__ void tensor_multi_kernel(MPack d, Pack a, Pack b, int nl, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int l = blockIdx.y, j = blockIdx.z;
+  const DevPrime& pr = P[l];
+  const size_t ps = (size_t)nl * N, o = (size_t)l * N + i;
+  const double a0 = a.p[j][o], a1 = a.p[j][ps + o], b0 = b.p[j][o], b1 = b.p[j][ps + o];
+  d.p[j][o] = mod_mul(a0, b0, pr.q, pr.qinv);
+  d.p[j][ps + o] = mod_add(mod_mul(a0, b1, pr.q, pr.qinv), mod_mul(a1, b0, pr.q, pr.qinv), pr.q);
+  d.p[j][2 * ps + o] = mod_mul(a1, b1, pr.q, pr.qinv);
+}
+
+void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::vector<const double*>& a,
+                         const std::vector<const double*>& b, int nl) {
+  for (size_t first = 0; first < d.size(); first += kPack) {
+    int cnt = (int)std::min<size_t>(kPack, d.size() - first);
+    MPack pd;
+    Pack pa, pb;
+    for (int k = 0; k < cnt; ++k) { pd.p[k] = d[first + k]; pa.p[k] = a[first + k]; pb.p[k] = b[first + k]; }
+    hipEvent_t ev;
+    prof_begin(c, 4, &ev);
+    hipLaunchKernelGGL(tensor_multi_kernel, dim3((unsigned)((c.N + 255) / 256), nl, cnt), dim3(256), 0, c.stream,
+                       pd, pa, pb, nl, c.d_primes, (int)c.log_n);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 4, ev, 3.0 * nl * cnt);
+  }
+}
+
+// modulus switch finish over jobs: out_j[k][i] = in_j[k][i] q_l^-1 - w[(j np + k)][i] t q_l^-1
+__global__ void ms_finish_multi_kernel(MPack out, Pack in, const double* w, int np, int l, const double* tab,
+                                       const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const int i = blockIdx.y;
+  const int z = blockIdx.z;
+  const int j = z / np, k = z % np;
+  const DevPrime& pi = P[i];
+  const double x = in.p[j][((size_t)k * (l + 1) + i) * N + c];
+  const double y = w[((size_t)z * l + i) * N + c];
+  out.p[j][((size_t)k * l + i) * N + c] =
+      mod_sub(mod_mul(x, tab[2 + 2 * i], pi.q, pi.qinv), mod_mul(y, tab[3 + 2 * i], pi.q, pi.qinv), pi.q);
+}
+
+void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
+                            const double* w, int np, int level, const double* tab) {
+  for (size_t first = 0; first < out.size(); first += kPack) {
+    int cnt = (int)std::min<size_t>(kPack, out.size() - first);
+    MPack po;
+    Pack pi;
+    for (int k = 0; k < cnt; ++k) { po.p[k] = out[first + k]; pi.p[k] = in[first + k]; }
+    hipEvent_t ev;
+    prof_begin(c, 4, &ev);
+    hipLaunchKernelGGL(ms_finish_multi_kernel, dim3((unsigned)((c.N + 255) / 256), level, cnt * np), dim3(256), 0,
+                       c.stream, po, pi, w + first * np * level * c.N, np, level, tab, c.d_primes, (int)c.log_n);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 4, ev, (double)level * np * cnt);
+  }
+}
+
+// key-switch inner product over jobs; digit rows come straight from the job's input poly
+__global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha, int logN, size_t key_ds,
+                                 const DevPrime* P) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int o = blockIdx.y;
+  const KsJob2 jb = jobs.j[blockIdx.z];
+  const int prime = o < nl ? o : L + 1 + (o - nl);
+  const DevPrime& pr = P[prime];
+  const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
+  const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
+  double a0 = 0.0, a1 = 0.0;
+  for (int j = 0; j < D; ++j) {
+    const double e = (j == own) ? jb.in[(size_t)o * N + src] : jb.ext[((size_t)j * nE + o) * N + src];
+    const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
+    a0 = mod_add(a0, mod_mul(e, jb.kb[ko], pr.q, pr.qinv), pr.q);
+    a1 = mod_add(a1, mod_mul(e, jb.ka[ko], pr.q, pr.qinv), pr.q);
+  }
+  jb.acc[(size_t)o * N + i] = a0;
+  jb.acc[((size_t)nE + o) * N + i] = a1;
+}
+
+void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds) {
+  for (size_t first = 0; first < jobs.size(); first += KsPack::kMax) {
+    int cnt = (int)std::min<size_t>(KsPack::kMax, jobs.size() - first);
+    KsPack pk;
+    for (int k = 0; k < cnt; ++k) pk.j[k] = jobs[first + k];
+    hipEvent_t ev;
+    prof_begin(c, 2, &ev);
+    hipLaunchKernelGGL(ks_inner2_kernel, dim3((unsigned)((c.N + 255) / 256), nE, cnt), dim3(256), 0, c.stream, pk, D,
+                       nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 2, ev, (double)nE * cnt);
+  }
+}
+
+// ModDown finish over jobs of 2 polys: out_j[k] = y * P^-1 - w * t P^-1, plus
+// mode 1: add_j poly k;  mode 2: for k = 0 add sigma_{g_j}(add_j poly 0)
+__global__ void md_finish2_kernel(MPack out, Pack add, GPack gal, const double* acc, const double* w, int nE, int nl,
+                                  const double* pinv, const double* tpinv, int add_mode, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const int i = blockIdx.y;
+  const int z = blockIdx.z;       // job * 2 + k
+  const int j = z >> 1, k = z & 1;
+  const DevPrime& pi = P[i];
+  const double yv = acc[((size_t)z * nE + i) * N + c];
+  const double wv = w[((size_t)z * nl + i) * N + c];
+  double v = mod_sub(mod_mul(yv, pinv[i], pi.q, pi.qinv), mod_mul(wv, tpinv[i], pi.q, pi.qinv), pi.q);
+  if (add_mode == 1) v = mod_add(v, add.p[j][((size_t)k * nl + i) * N + c], pi.q);
+  if (add_mode == 2 && k == 0) {
+    const size_t src = gal.g[j] == 1 ? c : auto_src((uint32_t)c, gal.g[j], logN);
+    v = mod_add(v, add.p[j][(size_t)i * N + src], pi.q);
+  }
+  out.p[j][((size_t)k * nl + i) * N + c] = v;
+}
+
+void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
+                       const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE, int nl,
+                       const double* pinv, const double* tpinv, int add_mode) {
+  for (size_t first = 0; first < out.size(); first += kPack) {
+    int cnt = (int)std::min<size_t>(kPack, out.size() - first);
+    MPack po;
+    Pack pa;
+    GPack pg;
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k];
+      pa.p[k] = add.empty() ? nullptr : add[first + k];
+      pg.g[k] = gal.empty() ? 1 : gal[first + k];
+    }
+    hipEvent_t ev;
+    prof_begin(c, 4, &ev);
+    hipLaunchKernelGGL(md_finish2_kernel, dim3((unsigned)((c.N + 255) / 256), nl, 2 * cnt), dim3(256), 0, c.stream,
+                       po, pa, pg, acc + first * 2 * nE * c.N, w + first * 2 * nl * c.N, nE, nl, pinv, tpinv,
+                       add_mode, c.d_primes, (int)c.log_n);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 4, ev, 2.0 * nl * cnt);
+  }
+}
+
+// MatMul inner sums with a plaintext model: for output job z (group g, batch b)
+//   out[z] = sum_t baby[u_t][b] (.) diag_t   over the terms of group g
+__global__ void mm_inner_kernel(double* out, const double* baby, const MMTerm* terms, const int* group_off, int G,
+                                int nl, size_t baby_slot, size_t baby_b, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int l = blockIdx.y;
+  const int z = blockIdx.z;
+  const int g = z / G, b = z % G;
+  const DevPrime& pr = P[l];
+  const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
+  double a0 = 0.0, a1 = 0.0;
+  for (int t = group_off[g]; t < group_off[g + 1]; ++t) {
+    const MMTerm tm = terms[t];
+    const double* bp = baby + (size_t)tm.u * baby_slot + (size_t)b * baby_b;
+    const double d = tm.diag[o];
+    a0 = mod_add(a0, mod_mul(bp[o], d, pr.q, pr.qinv), pr.q);
+    a1 = mod_add(a1, mod_mul(bp[ps + o], d, pr.q, pr.qinv), pr.q);
+  }
+  double* op = out + (size_t)z * 2 * ps;
+  op[o] = a0;
+  op[ps + o] = a1;
+}
+
+void launch_mm_inner(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
+                     int n_groups, int G, int nl, size_t baby_slot, size_t baby_b) {
+  hipEvent_t ev;
+  prof_begin(c, 4, &ev);
+  hipLaunchKernelGGL(mm_inner_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * G), dim3(256), 0, c.stream,
+                     out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+  COPSE_HIP(hipGetLastError());
+  prof_end(c, 4, ev, 2.0 * nl * n_groups * G);
+}
+
+// Encrypted-model MatMul inner sums: out[z] (3 polys) = sum_t tensor(baby[u_t][b], diag_t)
+__global__ void mm_inner_enc_kernel(double* out, const double* baby, const MMTerm* terms, const int* group_off,
+                                    int G, int nl, size_t baby_slot, size_t baby_b, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int l = blockIdx.y;
+  const int z = blockIdx.z;
+  const int g = z / G, b = z % G;
+  const DevPrime& pr = P[l];
+  const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int t = group_off[g]; t < group_off[g + 1]; ++t) {
+    const MMTerm tm = terms[t];
+    const double* bp = baby + (size_t)tm.u * baby_slot + (size_t)b * baby_b;
+    const double x0 = bp[o], x1 = bp[ps + o], y0 = tm.diag[o], y1 = tm.diag[ps + o];
+    d0 = mod_add(d0, mod_mul(x0, y0, pr.q, pr.qinv), pr.q);
+    d1 = mod_add(d1, mod_add(mod_mul(x0, y1, pr.q, pr.qinv), mod_mul(x1, y0, pr.q, pr.qinv), pr.q), pr.q);
+    d2 = mod_add(d2, mod_mul(x1, y1, pr.q, pr.qinv), pr.q);
+  }
+  double* op = out + (size_t)z * 3 * ps;
+  op[o] = d0;
+  op[ps + o] = d1;
+  op[2 * ps + o] = d2;
+}
+
+void launch_mm_inner_enc(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
+                         int n_groups, int G, int nl, size_t baby_slot, size_t baby_b) {
+  hipEvent_t ev;
+  prof_begin(c, 4, &ev);
+  hipLaunchKernelGGL(mm_inner_enc_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * G), dim3(256), 0,
+                     c.stream, out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+  COPSE_HIP(hipGetLastError());
+  prof_end(c, 4, ev, 3.0 * nl * n_groups * G);
+}
+
+// out_b = sum_{p < nparts} parts[p * stride_p + b * stride_b]  over rows (row r has prime r % nl)
+__global__ void sum_parts_kernel(double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
+                                 int nl, int rows, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int r = blockIdx.y, b = blockIdx.z;
+  const DevPrime& pr = P[r % nl];
+  const size_t o = (size_t)r * N + i;
+  double acc = 0.0;
+  for (int p = 0; p < nparts; ++p) acc = mod_add(acc, parts[(size_t)p * stride_p + (size_t)b * stride_b + o], pr.q);
+  out[(size_t)b * rows * N + o] = acc;
+}
+
+void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
+                      int nl, int rows, int G) {
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((c.N + 255) / 256), rows, G), dim3(256), 0, c.stream, out,
+                     parts, nparts, stride_p, stride_b, nl, rows, c.d_primes, (int)c.log_n);
+  COPSE_HIP(hipGetLastError());
+}
+
+// encrypted comparison combine: eq = 2u - xs - ts + 1 (if want_eq), lt = ts - u
+__global__ void seccomp_combine_kernel(MPack eq, MPack lt, Pack u, Pack xs, Pack ts, int nl, const DevPrime* P,
+                                       int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int r = blockIdx.y, j = blockIdx.z;   // r < 2 nl
+  const DevPrime& pr = P[r % nl];
+  const size_t o = (size_t)r * N + i;
+  const double uv = u.p[j][o], x = xs.p[j][o], tv = ts.p[j][o];
+  if (eq.p[j]) {
+    double v = mod_sub(mod_sub(mod_add(uv, uv, pr.q), x, pr.q), tv, pr.q);
+    if (r < nl) v = mod_add(v, 1.0, pr.q);
+    eq.p[j][o] = v;
+  }
+  lt.p[j][o] = mod_sub(tv, uv, pr.q);
+}
+
+void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const std::vector<double*>& lt,
+                            const std::vector<const double*>& u, const std::vector<const double*>& xs,
+                            const std::vector<const double*>& ts, int nl) {
+  for (size_t first = 0; first < lt.size(); first += kPack) {
+    int cnt = (int)std::min<size_t>(kPack, lt.size() - first);
+    MPack pe, pl;
+    Pack pu, px, pt;
+    for (int k = 0; k < cnt; ++k) {
+      pe.p[k] = eq[first + k]; pl.p[k] = lt[first + k];
+      pu.p[k] = u[first + k]; px.p[k] = xs[first + k]; pt.p[k] = ts[first + k];
+    }
+    hipLaunchKernelGGL(seccomp_combine_kernel, dim3((unsigned)((c.N + 255) / 256), 2 * nl, cnt), dim3(256), 0,
+                       c.stream, pe, pl, pu, px, pt, nl, c.d_primes, (int)c.log_n);
+  }
+  COPSE_HIP(hipGetLastError());
 }
 
 }  // namespace copse

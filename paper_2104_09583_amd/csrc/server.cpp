@@ -51,7 +51,7 @@ struct copse_server {
 
   size_t request_bytes(const copse_cts& q) const {
     size_t b = 0;
-    for (auto& ct : q.v) b += ct->buf.size() * 8;
+    for (auto& ct : q.v) b += ct->words() * 8;
     // working set of one group: baby rotations and key-switch buffers, bounded by
     // a fixed number of top-level ciphertexts (measured peak is below this)
     size_t ct_top = 2 * (size_t)(c->L + 1) * c->N * 8;

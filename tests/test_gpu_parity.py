@@ -249,3 +249,74 @@ def test_workload_c1_full_size(C):
     same(ctx.export(res)[0], out["result"])
     _, trees = F.parse_forest(text)
     assert (ctx.decrypt_labels(keys, meta, res, 1)[0] == np.array(F.evaluate(trees, list(queries[0])))).all()
+
+
+@pytest.mark.parametrize("enc", [False, True])
+def test_batched_groups_equal_single_and_oracle(C, enc):
+    """evaluate_batch over several query groups gives, per group, the same bits
+    as evaluating that group alone, and as the oracle."""
+    shape = synth.ForestShape(3, 4, 0.7, 3, 4, 3)
+    seed = 21
+    text = synth.gen_forest_text(shape, seed)
+    oc = OC.compile_forest(text, 3, 4)
+    need = CI.seccomp_depth(4) + 2 + math.ceil(math.log2(oc.d))
+    ch = dict(log_n=11, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=3, special_max=1 << 49)
+    ctx = C.Context(**ch)
+    comp, meta = C.forest_compile(text, 3, 4, 11)
+    kseed = b"\x44" * 32
+    keys = ctx.keygen(kseed, C.compiled_rotations(meta))
+    model = ctx.model_encode(comp, keys if enc else None, encrypt=enc, seed=kseed if enc else None)
+    G = 3
+    qsets = [synth.gen_queries(meta.queries_per_ct, 3, 4, 900 + g) for g in range(G)]
+    groups = [ctx.query_encrypt(keys, meta, qsets[g], kseed, group=g) for g in range(G)]
+    say("batched groups", G, "enc", enc)
+    batch = ctx.evaluate_batch(model, keys, groups)
+    single = [ctx.evaluate(model, keys, groups[g]) for g in range(G)]
+    sc = B.BGV(nt.make_chain(11, T, need + 1, 1 << 49, 1 << 42, 3, 1 << 49))
+    pl = CI.make_plan(oc, sc.N, sc.L, encrypted_model=enc)
+    okeys = sc.keygen(kseed, rotations=pl.rotations())
+    omodel = CI.encrypt_model(sc, okeys, pl, kseed) if enc else CI.encode_model(sc, pl)
+    _, trees = F.parse_forest(text)
+    for g in range(G):
+        eb, es = ctx.export(batch[g])[0], ctx.export(single[g])[0]
+        assert all((a == b).all() for a, b in zip(eb["polys"], es["polys"]))
+        X = CI.encrypt_queries(sc, okeys, pl, qsets[g], kseed, g)
+        same(eb, CI.Evaluator(sc, okeys, pl).run(X, omodel)["result"])
+        bits = ctx.decrypt_labels(keys, meta, batch[g], len(qsets[g]))
+        assert (bits == np.array([F.evaluate(trees, list(x)) for x in qsets[g]])).all()
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["c2_forest16_d5", "c5_serve_8x_d4"])
+def test_workload_full_size_against_stored_oracle(C, name):
+    """Full-size workloads: the result ciphertext's SHA-256 and sampled
+    coefficients equal the oracle's (stored by tests/golden/make_golden.py)."""
+    import hashlib
+    gold = _golden(name)
+    w = synth.WORKLOADS[name]
+    text, queries, seed = synth.workload_inputs(w)
+    say("full size", name)
+    ctx = C.Context(**w.chain)
+    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold)
+    keys = ctx.keygen(seed, C.compiled_rotations(meta))
+    model = ctx.model_encode(comp)
+    nq = gold["n_queries"]
+    qct = ctx.query_encrypt(keys, meta, queries[:nq], seed, group=gold["group"])
+    res = ctx.evaluate(model, ctx.export_eval(keys), qct)
+    ex = ctx.export(res)[0]
+    assert ex["level"] == gold["level"]
+    h = hashlib.sha256()
+    for p in ex["polys"]:
+        h.update(np.ascontiguousarray(p, dtype="<u8").tobytes())
+    assert [int(ex["polys"][0][0, i]) for i in gold["sample_index"]] == gold["sample_c0"]
+    assert [int(ex["polys"][1][0, i]) for i in gold["sample_index"]] == gold["sample_c1"]
+    assert h.hexdigest() == gold["sha256"]
+    bits = ctx.decrypt_labels(keys, meta, res, nq)
+    assert bits.tolist() == gold["labels"]
