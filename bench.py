@@ -47,6 +47,26 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def measured_traffic(kernel: str, limbs_per_launch: float, N: int):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain
+    copy of known size), as bytes per limb times this run's limbs per launch;
+    None when the kernels' source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ntt_rowreg_c2_forest16_d5_hbm_bytes.json")
+    src = os.path.join(ROOT, "paper_2104_09583_amd", "csrc", "kernels.hip")
+    key = {"ntt_fwd_rows": "ntt_rowreg_kernel<false>", "ntt_inv_rows": "ntt_rowreg_kernel<true>"}.get(kernel)
+    if key is None or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != doc["kernels_hip_sha256"] or N != 32768:
+            return None
+    k = doc["kernels"].get(key)
+    return None if k is None else round(k["bytes_per_limb"] * limbs_per_launch)
+
+
 def cpu_baseline(w, text, queries, seed, budget_s: float = 25.0):
     """The oracle, timed on a bounded sample of one evaluation of the same
     workload: the comparison, the reshuffle product and the first level
@@ -103,6 +123,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2_forest16_d5")
     ap.add_argument("--batch", type=int, default=1, help="query groups evaluated together per step")
+    ap.add_argument("--plain", action="store_true",
+                    help="the unbatched path: each group alone, one homomorphic operation per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -142,6 +164,8 @@ def main():
     queries_per_step = nq_group * args.batch
 
     def step():
+        if args.plain:
+            return [ctx.evaluate_plain(model, evk, g) for g in groups]
         if args.batch == 1:
             return [ctx.evaluate(model, evk, groups[0])]
         return ctx.evaluate_batch(model, evk, groups)
@@ -160,13 +184,12 @@ def main():
     torch.cuda.synchronize()
 
     ctx.profile_enable(True)
-    for k in range(5):
+    for k in range(C.PROF_KINDS):
         ctx.profile_read(k, reset=True)
     per_step = []
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    wall0 = time.perf_counter()
     for _ in range(args.steps):
         with torch.cuda.stream(stream):
             ev0.record(stream)
@@ -177,29 +200,33 @@ def main():
         per_step.append(ev0.elapsed_time(ev1))
     ctx.sync()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    prof = {k: ctx.profile_read(k) for k in range(5)}
+    prof = {k: ctx.profile_read(k) for k in range(C.PROF_KINDS)}
     ctx.profile_enable(False)
-    # The profiled loop above brackets kernels with events; time an unprofiled loop for the headline.
+    # Headline: an unprofiled loop, bracketed by device synchronization, timed on the host clock.
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall1 = time.perf_counter()
-    for _ in range(args.steps):
+    for e0, e1 in evs:
+        e0.record(stream)
         step()
+        e1.record(stream)
     ctx.sync()
     torch.cuda.synchronize()
     wall_clean = time.perf_counter() - wall1
+    lat = [e0.elapsed_time(e1) for e0, e1 in evs]
     ms_per_step = wall_clean * 1000.0 / args.steps
+    # reference copy of known size for the byte counters of a separate --pmc run
+    ctx.calib_copy(256 << 20)
 
     # roofline of the dominant kernel class (by total time)
-    names = {0: "ntt_fwd", 1: "ntt_inv", 2: "ks_inner", 3: "bconv", 4: "elementwise"}
-    dom = max(range(5), key=lambda k: prof[k]["ms"])
+    names = {0: "ntt_fwd_rows", 1: "ntt_fwd_cols", 2: "ntt_inv_rows", 3: "ntt_inv_cols", 4: "ks_inner",
+             5: "bconv", 6: "elementwise"}
+    dom = max(range(C.PROF_KINDS), key=lambda k: prof[k]["ms"])
     N = 1 << w.log_n
     p = prof[dom]
-    # algorithmic bytes per limb row: transforms read and write each limb once (2 N 8 bytes);
+    # algorithmic bytes per limb row: a transform pass reads and writes each limb once (2 N 8 bytes);
     # the key-switch inner product reads D digit rows and 2 D key rows and writes 2 rows per ext limb
-    if dom in (0, 1, 4):
-        bytes_per_limb = 2 * N * 8
-    elif dom == 2:
+    if dom == 4:
         D = math.ceil(ch["n_data_primes"] / ch["alpha"])
         bytes_per_limb = (3 * D + 2) * N * 8
     else:
@@ -208,12 +235,15 @@ def main():
     limbs_per_launch = p["limbs"] / max(1, p["launches"])
     achieved = bytes_per_limb * limbs_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(names[dom], limbs_per_launch, N),
                 "kernel": names[dom], "avg_launch_ms": round(avg_ms, 5),
                 "limbs_per_launch": round(limbs_per_launch, 2), "algorithmic_bytes_per_limb": bytes_per_limb,
                 "share_of_step": round(p["ms"] / sum(per_step), 3)}
     kernels = {names[k]: {"launches_per_step": prof[k]["launches"] / args.steps,
-                          "ms_per_step": round(prof[k]["ms"] / args.steps, 3)} for k in range(5)}
+                          "ms_per_step": round(prof[k]["ms"] / args.steps, 3),
+                          "avg_launch_us": round(1000 * prof[k]["ms"] / max(1, prof[k]["launches"]), 2)}
+               for k in range(C.PROF_KINDS)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -235,10 +265,12 @@ def main():
         "config": {"workload": w.name, "trees": w.shape.n_trees, "max_depth": w.shape.max_depth,
                    "features": w.shape.n_features, "precision": w.shape.precision, "classes": w.shape.n_classes,
                    "queries_per_step": queries_per_step, "query_groups_per_step": args.batch,
+                   "path": "plain (one group per call, one operation per launch)" if args.plain else
+                           ("batched" if args.batch > 1 else "single group"),
                    "N": N, "data_primes": ch["n_data_primes"], "special_primes": ch["alpha"],
                    "model": "plaintext" if not w.encrypted_model else "encrypted",
                    "b": meta.b, "m": meta.m, "q": meta.q, "d": meta.d, "W": meta.block_w},
-        "latency_ms": {"p50": round(percentile(per_step, 50), 3), "p99": round(percentile(per_step, 99), 3),
+        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "profiled_mean": round(sum(per_step) / len(per_step), 3)},
         "roofline": roofline,
         "kernels": kernels,

@@ -221,6 +221,11 @@ int copse_cts_level(const copse_cts* c, size_t i);
  */
 int copse_evaluate(copse_ctx* ctx, const copse_model* model, const copse_keys* keys,
                    const copse_cts* query, copse_cts** result);
+/* The unbatched reference path: one homomorphic operation per call (every
+ * rotation its own key switch, every product its own launches), same
+ * schedule and the same result bits as copse_evaluate. */
+int copse_evaluate_plain(copse_ctx* ctx, const copse_model* model, const copse_keys* keys,
+                         const copse_cts* query, copse_cts** result);
 /* Same for several query groups at once: the groups' ciphertexts travel
  * through every step together (one launch per step for all of them).
  * queries[i] and results[i] belong to group i.  Each result is bit-identical
@@ -273,9 +278,11 @@ int copse_poly_mul(copse_ctx* ctx, int prime, const uint64_t* a, const uint64_t*
 
 /* ---------------------------------------------------------------- profiling */
 /* When on, the library brackets each launch of the named kernel class with
- * HIP events on the launching stream and accumulates the durations.
- * kind: 0 = forward NTT, 1 = inverse NTT, 2 = key-switch inner product,
- * 3 = base conversion, 4 = elementwise.  reset clears the counters. */
+ * HIP events on the launching stream and accumulates the durations and the
+ * number of limb rows processed.  kind: 0 = forward NTT row pass,
+ * 1 = forward NTT column pass, 2 = inverse NTT row pass, 3 = inverse NTT
+ * column pass, 4 = key-switch inner product, 5 = base conversion,
+ * 6 = elementwise.  reset clears the counters. */
 int copse_profile_enable(copse_ctx* ctx, int on);
 int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
                        double* limbs, int reset);
@@ -285,6 +292,11 @@ int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* tot
  * Request loop: resident models, encrypted queries admitted while device
  * memory is under hbm_budget_bytes, batched as they arrive (continuous
  * batching across query groups), results in arrival-independent bits.
+ * The library starts no thread: a thread blocked in copse_server_wait runs
+ * the queued batches (one leader at a time) until its ticket completes;
+ * requests submitted meanwhile join the next batch.  Submission and waiting
+ * may come from any threads.  copse_server_destroy first finishes every
+ * admitted request.
  */
 int copse_server_create(copse_ctx* ctx, size_t hbm_budget_bytes, int max_batch, copse_server** out);
 void copse_server_destroy(copse_server* s);
@@ -304,6 +316,9 @@ int copse_server_latency(copse_server* s, uint64_t ticket, double* ms);
  * independent SHAKE-256.  kind: 0 uniform mod q (limb = global prime
  * index), 1 ternary, 2 centered binomial. */
 int copse_test_shake256(const uint8_t* msg, size_t len, uint8_t* out, size_t outlen);
+/* Copies `bytes` bytes between two fresh device buffers with a plain copy
+ * kernel: a known-size reference for hardware byte counters. */
+int copse_calib_copy(copse_ctx* ctx, size_t bytes);
 /* Prime chain of the parameters, computed on the host (no device needed). */
 int copse_chain_primes(const copse_params* params, uint64_t* out, size_t cap, size_t* n);
 /* Host encoder: slots[2*(N/2)] mod t -> centered coefficients[N]. */

@@ -6,6 +6,7 @@ loudly when the library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from typing import List, Optional, Sequence
@@ -26,7 +27,9 @@ COPSE_ETIMEOUT = -7
 
 OP_ADD, OP_SUB, OP_TENSOR, OP_RELIN, OP_MODSWITCH, OP_MUL, OP_ROTATE, OP_MUL_PLAIN, OP_ADD_PLAIN = range(1, 10)
 
-PROF_NTT_FWD, PROF_NTT_INV, PROF_KS_INNER, PROF_BCONV, PROF_ELEMENTWISE = range(5)
+(PROF_NTT_FWD_ROWS, PROF_NTT_FWD_COLS, PROF_NTT_INV_ROWS, PROF_NTT_INV_COLS, PROF_KS_INNER, PROF_BCONV,
+ PROF_ELEMENTWISE) = range(7)
+PROF_KINDS = 7
 
 
 class CopseError(RuntimeError):
@@ -51,6 +54,15 @@ class Meta(ctypes.Structure):
 
 
 _lib = None
+_SHUTTING_DOWN = False
+
+
+def _mark_shutdown():
+    global _SHUTTING_DOWN
+    _SHUTTING_DOWN = True
+
+
+atexit.register(_mark_shutdown)
 
 
 def lib() -> ctypes.CDLL:
@@ -79,6 +91,7 @@ def lib() -> ctypes.CDLL:
         "copse_cts_level": [P, sz],
         "copse_evaluate": [P, P, P, P, PP],
         "copse_evaluate_batch": [P, P, P, PP, sz, PP],
+        "copse_evaluate_plain": [P, P, P, P, PP],
         "copse_decrypt_labels": [P, P, ctypes.POINTER(Meta), P, sz, u8p, sz],
         "copse_encrypt_slots": [P, P, u64p, i32, u8p, u64, PP],
         "copse_decrypt_slots": [P, P, P, sz, u64p],
@@ -91,6 +104,7 @@ def lib() -> ctypes.CDLL:
         "copse_profile_read": [P, i32, u64p, ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32],
         "copse_test_shake256": [u8p, sz, u8p, sz],
         "copse_chain_primes": [ctypes.POINTER(Params), u64p, sz, ctypes.POINTER(sz)],
+        "copse_calib_copy": [P, sz],
         "copse_test_encode": [u32, u64, u64p, i64p],
         "copse_test_sample": [u8p, ctypes.c_char_p, u64, u32, i32, u64, sz, i64p],
         "copse_server_create": [P, sz, i32, PP],
@@ -151,6 +165,8 @@ class _Handle:
             self.ptr = ctypes.c_void_p()
 
     def __del__(self):
+        if _SHUTTING_DOWN:
+            return   # the process is exiting: leave the memory to the OS
         try:
             self.close()
         except Exception:
@@ -257,6 +273,11 @@ class Context(_Handle):
         check(lib().copse_evaluate(self.ptr, model.ptr, keys.ptr, query.ptr, ctypes.byref(h)))
         return Cts(h, self)
 
+    def evaluate_plain(self, model: Model, keys: Keys, query: Cts) -> Cts:
+        h = ctypes.c_void_p()
+        check(lib().copse_evaluate_plain(self.ptr, model.ptr, keys.ptr, query.ptr, ctypes.byref(h)))
+        return Cts(h, self)
+
     def evaluate_batch(self, model: Model, keys: Keys, queries: Sequence[Cts]) -> List[Cts]:
         n = len(queries)
         arr = (ctypes.c_void_p * n)(*[q.ptr.value for q in queries])
@@ -333,6 +354,9 @@ class Context(_Handle):
                                    _arr(out, ctypes.c_uint64)))
         return out
 
+    def calib_copy(self, nbytes: int) -> None:
+        check(lib().copse_calib_copy(self.ptr, nbytes))
+
     def profile_enable(self, on: bool = True) -> None:
         check(lib().copse_profile_enable(self.ptr, int(on)))
 
@@ -391,3 +415,37 @@ def encode(log_n: int, slots: np.ndarray, t: int = 65537) -> np.ndarray:
     out = np.zeros(1 << log_n, dtype=np.int64)
     check(lib().copse_test_encode(log_n, t, _arr(s, ctypes.c_uint64), _arr(out, ctypes.c_int64)))
     return out
+
+
+class Server(_Handle):
+    """Request loop over resident models (copse_server_*)."""
+    _destroy = "copse_server_destroy"
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_batch: int = 8):
+        h = ctypes.c_void_p()
+        check(lib().copse_server_create(ctx.ptr, hbm_budget_bytes, max_batch, ctypes.byref(h)))
+        super().__init__(h, ctx)
+        self._keep = []
+
+    def add_model(self, model: Model, eval_keys: Keys) -> int:
+        mid = ctypes.c_int()
+        check(lib().copse_server_add_model(self.ptr, model.ptr, eval_keys.ptr, ctypes.byref(mid)))
+        self._keep.append((model, eval_keys))
+        return mid.value
+
+    def submit(self, model_id: int, query: Cts) -> int:
+        t = ctypes.c_uint64()
+        rc = lib().copse_server_submit(self.ptr, model_id, query.ptr, ctypes.byref(t))
+        check(rc)
+        query.release()   # ownership moved to the server
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> Cts:
+        h = ctypes.c_void_p()
+        check(lib().copse_server_wait(self.ptr, ticket, timeout_ms, ctypes.byref(h)))
+        return Cts(h, self.owner)
+
+    def latency_ms(self, ticket: int) -> float:
+        v = ctypes.c_double()
+        check(lib().copse_server_latency(self.ptr, ticket, ctypes.byref(v)))
+        return v.value

@@ -14,20 +14,21 @@
 namespace copse {
 
 // ------------------------------------------------------------------ DBuf
-DBuf::DBuf(Context* c, size_t doubles) : c_(c), n_(doubles) {
-  p_ = doubles ? (double*)c->pool->alloc(doubles * sizeof(double)) : nullptr;
+DBuf::DBuf(Context* c, size_t doubles) : pool_(c->pool), n_(doubles) {
+  p_ = doubles ? (double*)pool_->alloc(doubles * sizeof(double)) : nullptr;
 }
 DBuf& DBuf::operator=(DBuf&& o) noexcept {
   if (this != &o) {
     reset();
-    c_ = o.c_; p_ = o.p_; n_ = o.n_;
-    o.c_ = nullptr; o.p_ = nullptr; o.n_ = 0;
+    pool_ = std::move(o.pool_); p_ = o.p_; n_ = o.n_;
+    o.p_ = nullptr; o.n_ = 0;
   }
   return *this;
 }
 void DBuf::reset() {
-  if (p_ && c_) c_->pool->free(p_);
+  if (p_ && pool_) pool_->free(p_);
   p_ = nullptr; n_ = 0;
+  pool_.reset();
 }
 
 // ------------------------------------------------------------------ profiling
@@ -53,7 +54,7 @@ void prof_end(Context& c, int kind, hipEvent_t ev, double limbs) {
   if (c.pending[kind].size() > 4096) prof_collect(c);
 }
 void prof_collect(Context& c) {
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < kProfKinds; ++k) {
     for (auto& pr : c.pending[k]) {
       COPSE_HIP(hipEventSynchronize(pr.second));
       float ms = 0;
@@ -71,7 +72,7 @@ Context::~Context() {
   if (!d_primes && !own_stream && tables.empty()) return;   // host-only context
   hipSetDevice(device);
   for (auto& ev : event_cache) (void)hipEventDestroy(ev);
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < kProfKinds; ++k)
     for (auto& pr : pending[k]) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
   for (auto& kv : ks)
     for (double* p : kv.second->owned) (void)hipFree(p);

@@ -111,7 +111,7 @@ int copse_ctx_create(const copse_params* p, copse_ctx** out) {
     c->t = p->t;
     c->alpha = (int)p->alpha;
     c->L = (int)p->n_data_primes - 1;
-    c->pool = std::make_unique<Pool>(p->device);
+    c->pool = std::make_shared<Pool>(p->device);
     c->primes = make_chain(*p);
     // transform tables
     std::vector<DevPrime> dp;
@@ -320,6 +320,19 @@ int copse_evaluate(copse_ctx* ctx, const copse_model* model, const copse_keys* k
     for (auto& p : query->v) planes.push_back(p.get());
     auto r = std::make_unique<copse_cts>();
     r->v.push_back(evaluate_group(*ctx->c, *model->m, *keys->k, planes));
+    *result = r.release();
+  });
+}
+
+int copse_evaluate_plain(copse_ctx* ctx, const copse_model* model, const copse_keys* keys, const copse_cts* query,
+                         copse_cts** result) {
+  return guarded([&] {
+    NEED(ctx && model && keys && query && result);
+    *result = nullptr;
+    std::vector<const Ct*> planes;
+    for (auto& p : query->v) planes.push_back(p.get());
+    auto r = std::make_unique<copse_cts>();
+    r->v.push_back(evaluate_group_plain(*ctx->c, *model->m, *keys->k, planes));
     *result = r.release();
   });
 }
@@ -588,13 +601,25 @@ int copse_profile_enable(copse_ctx* ctx, int on) {
 
 int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms, double* limbs, int reset) {
   return guarded([&] {
-    NEED(ctx && kind >= 0 && kind < 5);
+    NEED(ctx && kind >= 0 && kind < kProfKinds);
     Context& c = *ctx->c;
     prof_collect(c);
     if (launches) *launches = c.prof[kind].launches;
     if (total_ms) *total_ms = c.prof[kind].ms;
     if (limbs) *limbs = c.prof[kind].limbs;
     if (reset) c.prof[kind] = ProfSlot();
+  });
+}
+
+int copse_calib_copy(copse_ctx* ctx, size_t bytes) {
+  return guarded([&] {
+    NEED(ctx && bytes >= 8);
+    Context& c = *ctx->c;
+    size_t n = bytes / 8;
+    DBuf a(&c, n), b(&c, n);
+    COPSE_HIP(hipMemsetAsync(a.get(), 0, n * 8, c.stream));
+    launch_calib_copy(c, b.get(), a.get(), n);
+    COPSE_HIP(hipStreamSynchronize(c.stream));
   });
 }
 

@@ -82,6 +82,7 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
 void build_plan(Context& c, MatPlan& P, const std::vector<Operand>& diags, uint32_t n1, bool enc,
                 const std::vector<int32_t>* shared_rots);
 CtPtr evaluate_group(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes);
+CtPtr evaluate_group_plain(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes);
 std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
                                    const std::vector<std::vector<const Ct*>>& groups);
 

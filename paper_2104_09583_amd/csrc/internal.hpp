@@ -114,7 +114,7 @@ class DBuf {
   size_t size() const { return n_; }
 
  private:
-  Context* c_ = nullptr;
+  std::shared_ptr<Pool> pool_;   // keeps the pool alive while the buffer lives
   double* p_ = nullptr;
   size_t n_ = 0;
 };
@@ -134,7 +134,10 @@ struct Ct {
 };
 using CtPtr = std::unique_ptr<Ct>;
 
-// Profiling counters per kernel class.
+// Profiling counters per kernel class: 0 forward NTT (row pass), 1 forward NTT (column pass),
+// 2 inverse NTT (row pass), 3 inverse NTT (column pass), 4 key-switch inner product,
+// 5 base conversion, 6 elementwise.
+constexpr int kProfKinds = 7;
 struct ProfSlot {
   uint64_t launches = 0;
   double ms = 0;
@@ -156,14 +159,14 @@ struct Context {
   std::vector<uint64_t> psi;      // the device transform's 2N-th roots
   DevPrime* d_primes = nullptr;
   std::vector<double*> tables;
-  std::unique_ptr<Pool> pool;
+  std::shared_ptr<Pool> pool;
   uint64_t zeta = 0;              // slot root mod t
   std::vector<uint32_t> slot_pos; // slot (r,j) -> natural evaluation index (host encode)
   std::map<int, std::unique_ptr<KSTables>> ks;   // by level
   std::map<std::string, int2*> row_tables;       // cached device row lists
   bool profiling = false;
-  ProfSlot prof[5];
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[5];
+  ProfSlot prof[kProfKinds];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kProfKinds];
   std::vector<hipEvent_t> event_cache;
 
   int n_primes() const { return (int)primes.size(); }
@@ -288,6 +291,8 @@ void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, 
 void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const std::vector<double*>& lt,
                             const std::vector<const double*>& u, const std::vector<const double*>& xs,
                             const std::vector<const double*>& ts, int nl);
+
+void launch_calib_copy(Context& c, double* dst, const double* src, size_t n);
 
 // profiling hooks
 void prof_begin(Context& c, int kind, hipEvent_t* ev);

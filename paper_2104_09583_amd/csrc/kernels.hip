@@ -378,21 +378,33 @@ static void split_stages(int logN, int& S1) {
   S1 = logN - S2;
 }
 
+constexpr int kMaxGridY = 65535;
+
 void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows) {
   if (nrows <= 0) return;
+  if (nrows > kMaxGridY) {
+    for (int first = 0; first < nrows; first += kMaxGridY)
+      launch_ntt_fwd(c, base, rows + first, std::min(kMaxGridY, nrows - first));
+    return;
+  }
   hipEvent_t ev;
-  prof_begin(c, 0, &ev);
   int logN = (int)c.log_n, S1;
   split_stages(logN, S1);
+  size_t N = c.N;
   if (logN >= 11) {
-    if (S1 > 0) launch_colreg<false>(c, base, rows, nrows, S1, 0);
-    hipLaunchKernelGGL(ntt_rowreg_kernel<false>, dim3((unsigned)(c.N / 2048), nrows), dim3(256), 0, c.stream, base,
+    if (S1 > 0) {
+      prof_begin(c, 1, &ev);
+      launch_colreg<false>(c, base, rows, nrows, S1, 0);
+      prof_end(c, 1, ev, nrows);
+    }
+    prof_begin(c, 0, &ev);
+    hipLaunchKernelGGL(ntt_rowreg_kernel<false>, dim3((unsigned)(N / 2048), nrows), dim3(256), 0, c.stream, base,
                        rows, c.d_primes, logN, S1, 0);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 0, ev, nrows);
     return;
   }
-  size_t N = c.N;
+  prof_begin(c, 0, &ev);
   if (S1 > 0)
     hipLaunchKernelGGL(ntt_cols_kernel<false>, dim3((unsigned)((N >> S1) / (kTile >> S1)), nrows), dim3(kThreads),
                        0, c.stream, base, rows, c.d_primes, logN, S1, 0);
@@ -405,19 +417,29 @@ void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows) {
 
 void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
   if (nrows <= 0) return;
-  hipEvent_t ev;
-  prof_begin(c, 1, &ev);
-  int logN = (int)c.log_n, S1;
-  split_stages(logN, S1);
-  if (logN >= 11) {
-    hipLaunchKernelGGL(ntt_rowreg_kernel<true>, dim3((unsigned)(c.N / 2048), nrows), dim3(256), 0, c.stream, base,
-                       rows, c.d_primes, logN, S1, S1 == 0 ? 1 : 0);
-    if (S1 > 0) launch_colreg<true>(c, base, rows, nrows, S1, 1);
-    COPSE_HIP(hipGetLastError());
-    prof_end(c, 1, ev, nrows);
+  if (nrows > kMaxGridY) {
+    for (int first = 0; first < nrows; first += kMaxGridY)
+      launch_ntt_inv(c, base, rows + first, std::min(kMaxGridY, nrows - first));
     return;
   }
+  hipEvent_t ev;
+  int logN = (int)c.log_n, S1;
+  split_stages(logN, S1);
   size_t N = c.N;
+  if (logN >= 11) {
+    prof_begin(c, 2, &ev);
+    hipLaunchKernelGGL(ntt_rowreg_kernel<true>, dim3((unsigned)(N / 2048), nrows), dim3(256), 0, c.stream, base,
+                       rows, c.d_primes, logN, S1, S1 == 0 ? 1 : 0);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 2, ev, nrows);
+    if (S1 > 0) {
+      prof_begin(c, 3, &ev);
+      launch_colreg<true>(c, base, rows, nrows, S1, 1);
+      prof_end(c, 3, ev, nrows);
+    }
+    return;
+  }
+  prof_begin(c, 2, &ev);
   unsigned tiles = (unsigned)(N > (size_t)kTile ? N / kTile : 1);
   hipLaunchKernelGGL(ntt_rows_kernel<true>, dim3(tiles, nrows), dim3(kThreads), 0, c.stream, base, rows,
                      c.d_primes, logN, S1, S1 == 0 ? 1 : 0);
@@ -425,7 +447,7 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
     hipLaunchKernelGGL(ntt_cols_kernel<true>, dim3((unsigned)((N >> S1) / (kTile >> S1)), nrows), dim3(kThreads),
                        0, c.stream, base, rows, c.d_primes, logN, S1, 1);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 1, ev, nrows);
+  prof_end(c, 2, ev, nrows);
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -478,12 +500,13 @@ static dim3 ew_grid(const Context& c, int nrows) { return dim3((unsigned)((c.N +
 #define EW_LAUNCH(kern, ...)                                                                      \
   do {                                                                                            \
     if (nrows <= 0) return;                                                                       \
+    if (nrows > 65535) fail(COPSE_EINVAL, "too many rows for one elementwise launch");            \
     hipEvent_t ev;                                                                                \
-    prof_begin(c, 4, &ev);                                                                        \
+    prof_begin(c, 6, &ev);                                                                        \
     hipLaunchKernelGGL(kern, ew_grid(c, nrows), dim3(256), 0, c.stream, __VA_ARGS__, rows, c.d_primes, \
                        (int)c.log_n);                                                             \
     COPSE_HIP(hipGetLastError());                                                                 \
-    prof_end(c, 4, ev, nrows);                                                                    \
+    prof_end(c, 6, ev, nrows);                                                                    \
   } while (0)
 
 void launch_add(Context& c, double* out, const double* a, const double* b, const int2* rows, int nrows) {
@@ -527,19 +550,19 @@ __global__ void mul_plain_kernel(double* out, const double* a, const double* pt,
 
 void launch_mul_plain(Context& c, double* out, const double* a, const double* pt, int npolys, int nl) {
   hipEvent_t ev;
-  prof_begin(c, 4, &ev);
+  prof_begin(c, 6, &ev);
   hipLaunchKernelGGL(mul_plain_kernel, ew_grid(c, nl), dim3(256), 0, c.stream, out, a, pt, nl, npolys, c.d_primes,
                      (int)c.log_n, 0);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 4, ev, nl * npolys);
+  prof_end(c, 6, ev, nl * npolys);
 }
 void launch_mac_plain(Context& c, double* acc, const double* a, const double* pt, int npolys, int nl) {
   hipEvent_t ev;
-  prof_begin(c, 4, &ev);
+  prof_begin(c, 6, &ev);
   hipLaunchKernelGGL(mul_plain_kernel, ew_grid(c, nl), dim3(256), 0, c.stream, acc, a, pt, nl, npolys, c.d_primes,
                      (int)c.log_n, 1);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 4, ev, nl * npolys);
+  prof_end(c, 6, ev, nl * npolys);
 }
 
 // d = (a0 b0, a0 b1 + a1 b0, a1 b1), optionally accumulated into d
@@ -567,11 +590,11 @@ __global__ void tensor_kernel(double* d, const double* a, const double* b, int n
 
 void launch_tensor(Context& c, double* d, const double* a, const double* b, int nl, bool accumulate) {
   hipEvent_t ev;
-  prof_begin(c, 4, &ev);
+  prof_begin(c, 6, &ev);
   hipLaunchKernelGGL(tensor_kernel, ew_grid(c, nl), dim3(256), 0, c.stream, d, a, b, nl, c.d_primes, (int)c.log_n,
                      accumulate ? 1 : 0);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 4, ev, 3 * nl);
+  prof_end(c, 6, ev, 3 * nl);
 }
 
 __global__ void add_const_kernel(double* a, int nl, double v, const DevPrime* P, int logN) {
@@ -642,12 +665,12 @@ void launch_bconv(Context& c, double* out_base, const int2* out_rows, int n_out,
                   size_t in_bs, size_t out_bs) {
   if (n_out <= 0 || batch <= 0) return;
   hipEvent_t ev;
-  prof_begin(c, 3, &ev);
+  prof_begin(c, 5, &ev);
   hipLaunchKernelGGL(bconv_kernel, dim3((unsigned)((c.N + 255) / 256), n_out, batch), dim3(256), 0, c.stream,
                      out_base, out_rows, n_out, in_base, in_rows, n_in, mult, mat, c.d_primes, (int)c.log_n, in_bs,
                      out_bs);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 3, ev, (double)n_out * batch);
+  prof_end(c, 5, ev, (double)n_out * batch);
 }
 
 // ------------------------------------------------------------------ key-switch inner product
@@ -681,11 +704,11 @@ void launch_ks_inner(Context& c, const KsJob* jobs, int njobs, int D, int nE, in
     KsJobs pack;
     for (int k = 0; k < cnt; ++k) pack.j[k] = jobs[first + k];
     hipEvent_t ev;
-    prof_begin(c, 2, &ev);
+    prof_begin(c, 4, &ev);
     hipLaunchKernelGGL(ks_inner_kernel, dim3((unsigned)((c.N + 255) / 256), nE, cnt), dim3(256), 0, c.stream, pack,
                        D, nE, level + 1, c.L, (int)c.log_n, key_ds, c.d_primes);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 2, ev, (double)nE * cnt);
+    prof_end(c, 4, ev, (double)nE * cnt);
   }
 }
 
@@ -730,11 +753,11 @@ void launch_ms_prep(Context& c, double* out, const double* top, int npolys, int 
 void launch_ms_finish(Context& c, double* out, const double* in, const double* w, int npolys, int level,
                       const double* tab) {
   hipEvent_t ev;
-  prof_begin(c, 4, &ev);
+  prof_begin(c, 6, &ev);
   hipLaunchKernelGGL(ms_finish_kernel, dim3((unsigned)((c.N + 255) / 256), level, npolys), dim3(256), 0,
                      c.stream, out, in, w, npolys, level, tab, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 4, ev, (double)level * npolys);
+  prof_end(c, 6, ev, (double)level * npolys);
 }
 
 // ------------------------------------------------------------------ ModDown finish
@@ -761,11 +784,11 @@ void launch_moddown_finish(Context& c, double* out, const double* y, size_t ys, 
                            int nl, const double* pinv, const double* tpinv, const double* add, size_t adds,
                            int add_mode) {
   hipEvent_t ev;
-  prof_begin(c, 4, &ev);
+  prof_begin(c, 6, &ev);
   hipLaunchKernelGGL(moddown_finish_kernel, dim3((unsigned)((c.N + 255) / 256), nl, npolys), dim3(256), 0,
                      c.stream, out, y, ys, w, nl, pinv, tpinv, add, adds, add_mode, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 4, ev, (double)nl * npolys);
+  prof_end(c, 6, ev, (double)nl * npolys);
 }
 
 }  // namespace copse
@@ -826,11 +849,11 @@ void launch_ew_multi(Context& c, int op, const std::vector<double*>& out, const 
       pb.p[k] = b[first + k];
     }
     hipEvent_t ev;
-    prof_begin(c, 4, &ev);
+    prof_begin(c, 6, &ev);
     hipLaunchKernelGGL(ew_multi_kernel, dim3((unsigned)((c.N + 255) / 256), rows_per_job, cnt), dim3(256), 0,
                        c.stream, po, pa, pb, op, nl, b_rows, c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 4, ev, (double)rows_per_job * cnt);
+    prof_end(c, 6, ev, (double)rows_per_job * cnt);
   }
 }
 
@@ -884,11 +907,11 @@ void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::v
     Pack pa, pb;
     for (int k = 0; k < cnt; ++k) { pd.p[k] = d[first + k]; pa.p[k] = a[first + k]; pb.p[k] = b[first + k]; }
     hipEvent_t ev;
-    prof_begin(c, 4, &ev);
+    prof_begin(c, 6, &ev);
     hipLaunchKernelGGL(tensor_multi_kernel, dim3((unsigned)((c.N + 255) / 256), nl, cnt), dim3(256), 0, c.stream,
                        pd, pa, pb, nl, c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 4, ev, 3.0 * nl * cnt);
+    prof_end(c, 6, ev, 3.0 * nl * cnt);
   }
 }
 
@@ -916,11 +939,11 @@ void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const s
     Pack pi;
     for (int k = 0; k < cnt; ++k) { po.p[k] = out[first + k]; pi.p[k] = in[first + k]; }
     hipEvent_t ev;
-    prof_begin(c, 4, &ev);
+    prof_begin(c, 6, &ev);
     hipLaunchKernelGGL(ms_finish_multi_kernel, dim3((unsigned)((c.N + 255) / 256), level, cnt * np), dim3(256), 0,
                        c.stream, po, pi, w + first * np * level * c.N, np, level, tab, c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 4, ev, (double)level * np * cnt);
+    prof_end(c, 6, ev, (double)level * np * cnt);
   }
 }
 
@@ -953,11 +976,11 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
     KsPack pk;
     for (int k = 0; k < cnt; ++k) pk.j[k] = jobs[first + k];
     hipEvent_t ev;
-    prof_begin(c, 2, &ev);
+    prof_begin(c, 4, &ev);
     hipLaunchKernelGGL(ks_inner2_kernel, dim3((unsigned)((c.N + 255) / 256), nE, cnt), dim3(256), 0, c.stream, pk, D,
                        nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 2, ev, (double)nE * cnt);
+    prof_end(c, 4, ev, (double)nE * cnt);
   }
 }
 
@@ -997,12 +1020,12 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
       pg.g[k] = gal.empty() ? 1 : gal[first + k];
     }
     hipEvent_t ev;
-    prof_begin(c, 4, &ev);
+    prof_begin(c, 6, &ev);
     hipLaunchKernelGGL(md_finish2_kernel, dim3((unsigned)((c.N + 255) / 256), nl, 2 * cnt), dim3(256), 0, c.stream,
                        po, pa, pg, acc + first * 2 * nE * c.N, w + first * 2 * nl * c.N, nE, nl, pinv, tpinv,
                        add_mode, c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 4, ev, 2.0 * nl * cnt);
+    prof_end(c, 6, ev, 2.0 * nl * cnt);
   }
 }
 
@@ -1034,11 +1057,11 @@ __global__ void mm_inner_kernel(double* out, const double* baby, const MMTerm* t
 void launch_mm_inner(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
                      int n_groups, int G, int nl, size_t baby_slot, size_t baby_b) {
   hipEvent_t ev;
-  prof_begin(c, 4, &ev);
+  prof_begin(c, 6, &ev);
   hipLaunchKernelGGL(mm_inner_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * G), dim3(256), 0, c.stream,
                      out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 4, ev, 2.0 * nl * n_groups * G);
+  prof_end(c, 6, ev, 2.0 * nl * n_groups * G);
 }
 
 // Encrypted-model MatMul inner sums: out[z] (3 polys) = sum_t tensor(baby[u_t][b], diag_t)
@@ -1070,11 +1093,11 @@ __global__ void mm_inner_enc_kernel(double* out, const double* baby, const MMTer
 void launch_mm_inner_enc(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
                          int n_groups, int G, int nl, size_t baby_slot, size_t baby_b) {
   hipEvent_t ev;
-  prof_begin(c, 4, &ev);
+  prof_begin(c, 6, &ev);
   hipLaunchKernelGGL(mm_inner_enc_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * G), dim3(256), 0,
                      c.stream, out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 4, ev, 3.0 * nl * n_groups * G);
+  prof_end(c, 6, ev, 3.0 * nl * n_groups * G);
 }
 
 // out_b = sum_{p < nparts} parts[p * stride_p + b * stride_b]  over rows (row r has prime r % nl)
@@ -1133,4 +1156,15 @@ void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const st
   COPSE_HIP(hipGetLastError());
 }
 
+}  // namespace copse
+
+namespace copse {
+__global__ void calib_copy_kernel(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+void launch_calib_copy(Context& c, double* dst, const double* src, size_t n) {
+  hipLaunchKernelGGL(calib_copy_kernel, dim3(4096), dim3(256), 0, c.stream, dst, src, n);
+  COPSE_HIP(hipGetLastError());
+}
 }  // namespace copse

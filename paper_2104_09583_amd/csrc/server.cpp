@@ -1,19 +1,21 @@
 // Request loop for serving encrypted queries against resident models.
 //
-// Clients submit query groups (already encrypted); a worker thread owns the
-// device and repeatedly takes every waiting request of one model (up to
-// max_batch) and evaluates them together, so requests that arrive while a
-// batch runs join the next one (continuous batching).  A request is
-// admitted only while the device memory it needs (its ciphertexts plus the
-// evaluation working set, estimated from the ring and level sizes) fits the
-// budget left after resident models and keys; otherwise submit returns
-// COPSE_ENOMEM.  Each group's result is computed by the same deterministic
-// schedule whether it runs alone or in a batch, so its bits do not depend on
-// the mix.
+// Clients submit query groups (already encrypted) from any thread; the
+// device work is driven by the threads that wait for results: the first
+// waiter that finds no batch running becomes the leader and repeatedly takes
+// every queued request of one model (up to max_batch) and evaluates them
+// together, until the queue is empty.  Requests submitted while a batch is on
+// the GPU join the next batch (continuous batching); other waiters sleep
+// until their ticket completes.  The library starts no thread of its own.
+// A request is admitted only while the device memory it needs (its
+// ciphertexts plus the evaluation working set, estimated from the ring and
+// level sizes) fits the budget left after resident models and keys;
+// otherwise submit returns COPSE_ENOMEM.  Each group's result is computed by
+// the same deterministic schedule whether it runs alone or in a batch, so its
+// bits do not depend on the mix.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
-#include <thread>
 
 #include "compiled.hpp"
 
@@ -41,74 +43,78 @@ struct copse_server {
   int max_batch = 1;
   std::vector<std::pair<const Model*, const Keys*>> models;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_done;
   std::deque<Req*> queue;
   std::map<uint64_t, std::unique_ptr<Req>> reqs;
   size_t in_flight = 0;
   uint64_t next_ticket = 1;
-  bool stop = false;
-  std::thread worker;
+  bool leader = false;     // a thread is running batches
 
   size_t request_bytes(const copse_cts& q) const {
     size_t b = 0;
     for (auto& ct : q.v) b += ct->words() * 8;
     // working set of one group: baby rotations and key-switch buffers, bounded by
-    // a fixed number of top-level ciphertexts (measured peak is below this)
+    // a fixed number of top-level ciphertexts
     size_t ct_top = 2 * (size_t)(c->L + 1) * c->N * 8;
     return b + 64 * ct_top;
   }
 
-  void run() {
-    hipSetDevice(c->device);
-    while (true) {
-      std::vector<Req*> batch;
-      {
-        std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
-        if (stop && queue.empty()) return;
-        int model = queue.front()->model;
-        for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
-          if ((*it)->model == model) {
-            batch.push_back(*it);
-            it = queue.erase(it);
-          } else {
-            ++it;
-          }
-        }
+  // Called with mu held by the leader: takes one batch, runs it unlocked, publishes results.
+  void run_one_batch(std::unique_lock<std::mutex>& lk) {
+    std::vector<Req*> batch;
+    int model = queue.front()->model;
+    for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
+      if ((*it)->model == model) {
+        batch.push_back(*it);
+        it = queue.erase(it);
+      } else {
+        ++it;
       }
-      std::vector<std::vector<const Ct*>> groups;
-      for (Req* r : batch) {
-        std::vector<const Ct*> planes;
-        for (auto& p : r->q->v) planes.push_back(p.get());
-        groups.push_back(planes);
-      }
-      std::vector<CtPtr> res;
-      int rc = COPSE_OK;
-      std::string err;
-      try {
-        res = evaluate_groups(*c, *models[batch[0]->model].first, *models[batch[0]->model].second, groups);
-        COPSE_HIP(hipStreamSynchronize(c->stream));
-      } catch (const Error& e) {
-        rc = e.code;
-        err = e.msg;
-      }
-      std::lock_guard<std::mutex> lk(mu);
-      auto now = Clock::now();
-      for (size_t i = 0; i < batch.size(); ++i) {
-        Req* r = batch[i];
-        r->rc = rc;
-        r->err = err;
-        if (rc == COPSE_OK) {
-          r->result = std::make_unique<copse_cts>();
-          r->result->v.push_back(std::move(res[i]));
-        }
-        r->q.reset();
-        in_flight -= r->bytes;
-        r->t_done = now;
-        r->done = true;
-      }
-      cv_done.notify_all();
     }
+    lk.unlock();
+    std::vector<std::vector<const Ct*>> groups;
+    for (Req* r : batch) {
+      std::vector<const Ct*> planes;
+      for (auto& p : r->q->v) planes.push_back(p.get());
+      groups.push_back(planes);
+    }
+    std::vector<CtPtr> res;
+    int rc = COPSE_OK;
+    std::string err;
+    try {
+      COPSE_HIP(hipSetDevice(c->device));
+      res = evaluate_groups(*c, *models[model].first, *models[model].second, groups);
+      COPSE_HIP(hipStreamSynchronize(c->stream));
+    } catch (const Error& e) {
+      rc = e.code;
+      err = e.msg;
+    }
+    auto now = Clock::now();
+    std::vector<std::unique_ptr<copse_cts>> spent;
+    lk.lock();
+    for (size_t i = 0; i < batch.size(); ++i) {
+      Req* r = batch[i];
+      r->rc = rc;
+      r->err = err;
+      if (rc == COPSE_OK) {
+        r->result = std::make_unique<copse_cts>();
+        r->result->v.push_back(std::move(res[i]));
+      }
+      spent.push_back(std::move(r->q));
+      in_flight -= r->bytes;
+      r->t_done = now;
+      r->done = true;
+    }
+    cv_done.notify_all();
+  }
+
+  // Lead until the queue is empty (or until `stop_when` holds); mu held on entry and exit.
+  template <typename P>
+  void lead(std::unique_lock<std::mutex>& lk, P stop_when) {
+    leader = true;
+    while (!queue.empty() && !stop_when()) run_one_batch(lk);
+    leader = false;
+    cv_done.notify_all();
   }
 };
 
@@ -120,7 +126,6 @@ int copse_server_create(copse_ctx* ctx, size_t hbm_budget_bytes, int max_batch, 
   s->c = ctx->c.get();
   s->budget = hbm_budget_bytes;
   s->max_batch = max_batch;
-  s->worker = std::thread([s] { s->run(); });
   *out = s;
   return COPSE_OK;
 }
@@ -128,11 +133,13 @@ int copse_server_create(copse_ctx* ctx, size_t hbm_budget_bytes, int max_batch, 
 void copse_server_destroy(copse_server* s) {
   if (!s) return;
   {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
+    // finish every admitted request before releasing the server
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (!s->queue.empty() || s->leader) {
+      if (!s->leader) s->lead(lk, [] { return false; });
+      else s->cv_done.wait(lk);
+    }
   }
-  s->cv_work.notify_all();
-  if (s->worker.joinable()) s->worker.join();
   delete s;
 }
 
@@ -149,7 +156,7 @@ int copse_server_add_model(copse_server* s, const copse_model* m, const copse_ke
 
 int copse_server_submit(copse_server* s, int model_id, copse_cts* q, uint64_t* ticket) {
   if (!s || !q || !ticket) return COPSE_EINVAL;
-  std::unique_lock<std::mutex> lk(s->mu);
+  std::lock_guard<std::mutex> lk(s->mu);
   if (model_id < 0 || model_id >= (int)s->models.size()) return COPSE_EINVAL;
   if (q->v.size() != s->models[model_id].first->meta.precision) return COPSE_EINVAL;
   size_t need = s->request_bytes(*q);
@@ -164,8 +171,6 @@ int copse_server_submit(copse_server* s, int model_id, copse_cts* q, uint64_t* t
   *ticket = r->ticket;
   s->queue.push_back(r.get());
   s->reqs[r->ticket] = std::move(r);
-  lk.unlock();
-  s->cv_work.notify_one();
   return COPSE_OK;
 }
 
@@ -175,9 +180,19 @@ int copse_server_wait(copse_server* s, uint64_t ticket, int timeout_ms, copse_ct
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return COPSE_EINVAL;
   Req* r = it->second.get();
-  auto pred = [&] { return r->done; };
-  if (timeout_ms < 0) s->cv_done.wait(lk, pred);
-  else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) return COPSE_ETIMEOUT;
+  auto deadline = Clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+  while (!r->done) {
+    if (!s->leader && !s->queue.empty()) {
+      // lead until this ticket is done (the batch holding it completes)
+      s->lead(lk, [&] { return r->done; });
+      continue;
+    }
+    if (timeout_ms < 0) {
+      s->cv_done.wait(lk);
+    } else if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout && !r->done) {
+      return COPSE_ETIMEOUT;
+    }
+  }
   if (r->rc != COPSE_OK) return r->rc;
   if (!r->result) return COPSE_EINVAL;   // already collected
   *result = r->result.release();

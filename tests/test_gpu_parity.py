@@ -208,6 +208,8 @@ def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
     omodel = CI.encrypt_model(sc, okeys, pl, kseed) if enc else CI.encode_model(sc, pl)
     out = CI.Evaluator(sc, okeys, pl).run(X, omodel)
     same(ctx.export(res)[0], out["result"])
+    # the unbatched one-operation-at-a-time path gives the same bits
+    same(ctx.export(ctx.evaluate_plain(model, evk, qct))[0], out["result"])
     bits = ctx.decrypt_labels(keys, meta, res, nq)
     _, trees = F.parse_forest(text)
     want = np.array([F.evaluate(trees, list(x)) for x in queries])
