@@ -62,7 +62,8 @@ typedef struct copse_server copse_server;
  * Ring and prime chain.  Ring dimension N = 2^log_n, plaintext modulus t
  * (must satisfy t = 1 mod 2N so there are N slots).  Every prime q is
  * q = k (2 N t) + 1 (so dropping q in a modulus switch keeps the plaintext:
- * q^-1 = 1 mod t) and q < 2^50 (residues are held exactly in fp64).
+ * q^-1 = 1 mod t) and q < 2^49 (residues are held exactly in fp64, with
+ * headroom for lazily reduced intermediates in the transforms).
  * Candidates k(2Nt)+1 are scanned downward in k below exclusive bounds:
  *   1. alpha special primes p_0 > p_1 > ... below special_max;
  *   2. data primes q_1 > ... > q_L (L = n_data_primes - 1) below data_max,

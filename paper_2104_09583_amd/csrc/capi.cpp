@@ -52,9 +52,9 @@ void check_params(const copse_params* p) {
   if (!is_prime(p->t)) fail(COPSE_EINVAL, "t must be prime");
   if (p->alpha == 0 || p->n_data_primes == 0) fail(COPSE_EINVAL, "need at least one data and one special prime");
   if (p->n_data_primes + p->alpha > (uint32_t)kMaxPrimes) fail(COPSE_EINVAL, "too many primes");
-  const uint64_t lim = 1ULL << 50;
+  const uint64_t lim = 1ULL << 49;
   if (p->q0_max > lim || p->data_max > lim || p->special_max > lim)
-    fail(COPSE_EINVAL, "prime bounds must not exceed 2^50");
+    fail(COPSE_EINVAL, "prime bounds must not exceed 2^49");
 }
 
 // q_0, q_1..q_L, p_0..p_{alpha-1} (see copse_params)

@@ -1,7 +1,7 @@
 // Internal declarations of the COPSE gfx950 library.
 //
 // Residues modulo every prime are held as IEEE doubles with exact integer
-// values in [0, q), q < 2^50.  A product a*b mod q is computed exactly with
+// values in [0, q), q < 2^49.  A product a*b mod q is computed exactly with
 // the fused multiply-add: h = a*b (rounded), l = fma(a, b, -h) (the exact
 // rounding error, so a*b = h + l), k = floor(h * (1/q)) is the quotient up
 // to +-1 (|error| < 0.4 because a*b/q < 2^50 and three roundings of 2^-53),

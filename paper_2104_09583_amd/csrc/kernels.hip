@@ -41,6 +41,25 @@ __device__ __forceinline__ double mod_reduce(double v, double q, double qinv) {
   return r;
 }
 
+// Lazy (signed) residues for the transforms.  With q < 2^49 and |a| < 4q, |b| < q:
+//   mul_lazy: k = rint(a b / q) is within 0.5 + 2^-3 of the exact quotient, so
+//   r = a b - k q = fma(-k, q, h) + l is an exact integer with |r| < 0.91 q;
+//   reduce_sym: x - q rint(x / q) lies in [-q/2, q/2] for |x| < 8 q;
+//   canon: maps [-q/2, q/2] to [0, q).
+// A radix-8 round grows |x| from q/2 by at most 3 x 0.91 q (forward) or by a
+// factor 8 (inverse sums), so one reduce_sym per element and round keeps every
+// intermediate below 4 q and every product below 2^101 (exact in fp64).
+__device__ __forceinline__ double mul_lazy(double a, double b, double q, double qinv) {
+  double h = a * b;
+  double l = __fma_rn(a, b, -h);
+  double k = rint(h * qinv);
+  return __fma_rn(-k, q, h) + l;
+}
+__device__ __forceinline__ double reduce_sym(double x, double q, double qinv) {
+  return __fma_rn(-rint(x * qinv), q, x);
+}
+__device__ __forceinline__ double canon(double x, double q) { return x < 0.0 ? x + q : x; }
+
 // ------------------------------------------------------------------ NTT
 // Forward transform: Cooley-Tukey butterflies, natural-order input,
 // bit-reversed output.  Stage s (0-based, m = 2^s) pairs j and j + t with
@@ -179,15 +198,15 @@ __global__ __launch_bounds__(kThreads) void ntt_rows_kernel(double* __restrict__
 // column c, so one thread keeps a whole column in registers and needs no LDS.  Consecutive
 // threads take consecutive columns: every load and store of a wavefront is one contiguous run.
 __device__ __forceinline__ void bfly_ct(double& x, double& y, double w, double q, double qinv) {
-  double v = mod_mul(y, w, q, qinv);
+  double v = mul_lazy(y, w, q, qinv);
   double u = x;
-  x = mod_add(u, v, q);
-  y = mod_sub(u, v, q);
+  x = u + v;
+  y = u - v;
 }
 __device__ __forceinline__ void bfly_gs(double& x, double& y, double w, double q, double qinv) {
   double u = x, v = y;
-  x = mod_add(u, v, q);
-  y = mod_mul(mod_sub(u, v, q), w, q, qinv);
+  x = u + v;
+  y = mul_lazy(u - v, w, q, qinv);
 }
 
 template <int S1, bool kInverse>
@@ -230,8 +249,10 @@ __global__ __launch_bounds__(64) void ntt_colreg_kernel(double* __restrict__ bas
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     double v = x[r];
-    if (scale) v = mod_mul(v, pr.ninv, pr.q, pr.qinv);
-    a[r * C + c] = v;
+    if (scale) v = mul_lazy(v, pr.ninv, pr.q, pr.qinv);
+    v = reduce_sym(v, pr.q, pr.qinv);
+    // forward: the row pass follows and accepts signed values; inverse: final, canonical
+    a[r * C + c] = kInverse ? canon(v, pr.q) : v;
   }
 }
 
@@ -269,6 +290,11 @@ __device__ __forceinline__ void radix8_gs(double* x, size_t gb, size_t d, size_t
   for (int k = 0; k < 4; ++k) bfly_gs(x[k], x[k + 4], w0, pr.q, pr.qinv);
 }
 
+__device__ __forceinline__ void red8(double* x, const DevPrime& pr) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = reduce_sym(x[k], pr.q, pr.qinv);
+}
+
 template <bool kInverse>
 __global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ base, const int2* __restrict__ rows,
                                                         const DevPrime* __restrict__ P, int logN, int S1, int scale) {
@@ -288,18 +314,21 @@ __global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ ba
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = a[t0 + jA + 256 * k];
     radix8_ct(x, t0 + jA, 256, mA, pr);
+    red8(x, pr);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 256 * k)] = x[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 32 * k)];
     radix8_ct(x, t0 + jB, 32, mB, pr);
+    red8(x, pr);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 32 * k)] = x[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 4 * k)];
     radix8_ct(x, t0 + jC, 4, mC, pr);
+    red8(x, pr);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 4 * k)] = x[k];
     __syncthreads();
@@ -316,7 +345,7 @@ __global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ ba
       bfly_ct(y[2], y[3], pr.fwd[2 * mD + gb / 2 + 1], pr.q, pr.qinv);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[t0 + jD + k] = x[k];
+    for (int k = 0; k < 8; ++k) a[t0 + jD + k] = canon(reduce_sym(x[k], pr.q, pr.qinv), pr.q);
   } else {
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = a[t0 + jD + k];
@@ -330,18 +359,21 @@ __global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ ba
       bfly_gs(y[0], y[2], w, pr.q, pr.qinv);
       bfly_gs(y[1], y[3], w, pr.q, pr.qinv);
     }
+    red8(x, pr);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 4 * k)];
     radix8_gs(x, t0 + jC, 4, mC, pr);
+    red8(x, pr);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 4 * k)] = x[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 32 * k)];
     radix8_gs(x, t0 + jB, 32, mB, pr);
+    red8(x, pr);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 32 * k)] = x[k];
     __syncthreads();
@@ -351,8 +383,88 @@ __global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ ba
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       double v = x[k];
-      if (scale) v = mod_mul(v, pr.ninv, pr.q, pr.qinv);
-      a[t0 + jA + 256 * k] = v;
+      if (scale) v = mul_lazy(v, pr.ninv, pr.q, pr.qinv);
+      v = reduce_sym(v, pr.q, pr.qinv);
+      a[t0 + jA + 256 * k] = scale ? canon(v, pr.q) : v;
+    }
+  }
+}
+
+// Row pass over a tile of 4096 contiguous elements (stages S1..S1+11): 512 threads x 8 registers,
+// four radix-8 rounds (distances 2048/1024/512, 256/128/64, 32/16/8, 4/2/1) with three LDS exchanges.
+constexpr int kLdsTile4 = 4096 + 4096 / 16;
+
+template <bool kInverse>
+__global__ __launch_bounds__(512) void ntt_rowreg4_kernel(double* __restrict__ base, const int2* __restrict__ rows,
+                                                         const DevPrime* __restrict__ P, int logN, int S1, int scale) {
+  __shared__ double sh[kLdsTile4];
+  const int2 row = rows[blockIdx.y];
+  const DevPrime pr = P[row.y];
+  const size_t N = (size_t)1 << logN;
+  double* a = base + (size_t)row.x * N;
+  const int t = threadIdx.x;
+  const size_t t0 = (size_t)blockIdx.x * 4096;
+  const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
+  double x[8];
+  const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
+  if (!kInverse) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = a[t0 + jA + 512 * k];
+    radix8_ct(x, t0 + jA, 512, mA, pr);
+    red8(x, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
+    radix8_ct(x, t0 + jB, 64, mB, pr);
+    red8(x, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
+    radix8_ct(x, t0 + jC, 8, mC, pr);
+    red8(x, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
+    radix8_ct(x, t0 + jD, 1, mD, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[t0 + jD + k] = canon(reduce_sym(x[k], pr.q, pr.qinv), pr.q);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = a[t0 + jD + k];
+    radix8_gs(x, t0 + jD, 1, mD, pr);
+    red8(x, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
+    radix8_gs(x, t0 + jC, 8, mC, pr);
+    red8(x, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
+    radix8_gs(x, t0 + jB, 64, mB, pr);
+    red8(x, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 512 * k)];
+    radix8_gs(x, t0 + jA, 512, mA, pr);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      double v = x[k];
+      if (scale) v = mul_lazy(v, pr.ninv, pr.q, pr.qinv);
+      v = reduce_sym(v, pr.q, pr.qinv);
+      a[t0 + jA + 512 * k] = scale ? canon(v, pr.q) : v;
     }
   }
 }
@@ -391,15 +503,24 @@ void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows) {
   int logN = (int)c.log_n, S1;
   split_stages(logN, S1);
   size_t N = c.N;
-  if (logN >= 11) {
-    if (S1 > 0) {
+  if (logN >= 12) {
+    const int S1r = logN - 12;
+    if (S1r > 0) {
       prof_begin(c, 1, &ev);
-      launch_colreg<false>(c, base, rows, nrows, S1, 0);
+      launch_colreg<false>(c, base, rows, nrows, S1r, 0);
       prof_end(c, 1, ev, nrows);
     }
     prof_begin(c, 0, &ev);
-    hipLaunchKernelGGL(ntt_rowreg_kernel<false>, dim3((unsigned)(N / 2048), nrows), dim3(256), 0, c.stream, base,
-                       rows, c.d_primes, logN, S1, 0);
+    hipLaunchKernelGGL(ntt_rowreg4_kernel<false>, dim3((unsigned)(N / 4096), nrows), dim3(512), 0, c.stream, base,
+                       rows, c.d_primes, logN, S1r, 0);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 0, ev, nrows);
+    return;
+  }
+  if (logN == 11) {
+    prof_begin(c, 0, &ev);
+    hipLaunchKernelGGL(ntt_rowreg_kernel<false>, dim3(1, nrows), dim3(256), 0, c.stream, base, rows, c.d_primes,
+                       logN, 0, 0);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 0, ev, nrows);
     return;
@@ -426,17 +547,26 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
   int logN = (int)c.log_n, S1;
   split_stages(logN, S1);
   size_t N = c.N;
-  if (logN >= 11) {
+  if (logN >= 12) {
+    const int S1r = logN - 12;
     prof_begin(c, 2, &ev);
-    hipLaunchKernelGGL(ntt_rowreg_kernel<true>, dim3((unsigned)(N / 2048), nrows), dim3(256), 0, c.stream, base,
-                       rows, c.d_primes, logN, S1, S1 == 0 ? 1 : 0);
+    hipLaunchKernelGGL(ntt_rowreg4_kernel<true>, dim3((unsigned)(N / 4096), nrows), dim3(512), 0, c.stream, base,
+                       rows, c.d_primes, logN, S1r, S1r == 0 ? 1 : 0);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 2, ev, nrows);
-    if (S1 > 0) {
+    if (S1r > 0) {
       prof_begin(c, 3, &ev);
-      launch_colreg<true>(c, base, rows, nrows, S1, 1);
+      launch_colreg<true>(c, base, rows, nrows, S1r, 1);
       prof_end(c, 3, ev, nrows);
     }
+    return;
+  }
+  if (logN == 11) {
+    prof_begin(c, 2, &ev);
+    hipLaunchKernelGGL(ntt_rowreg_kernel<true>, dim3(1, nrows), dim3(256), 0, c.stream, base, rows, c.d_primes,
+                       logN, 0, 1);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 2, ev, nrows);
     return;
   }
   prof_begin(c, 2, &ev);
@@ -636,39 +766,56 @@ void launch_automorphism(Context& c, double* out, const double* in, uint64_t g, 
 
 // ------------------------------------------------------------------ fast base conversion
 // out_o[c] = sum_i [in_i[c] * mult_i]_{q_i} * mat[i][o]  mod p_o
-// grid: x over coefficients, y over output rows, z over batch
+// A thread converts one coefficient for up to kBcOut outputs: the n_in inputs are read once and
+// their scaled residues y_i stay in registers.  grid: x over coefficients, y over output chunks,
+// z over the batch.
+constexpr int kBcIn = 8;
+constexpr int kBcOut = 8;
 __global__ void bconv_kernel(double* out_base, const int2* out_rows, int n_out, const double* in_base,
                              const int2* in_rows, int n_in, const double* mult, const double* mat,
                              const DevPrime* P, int logN, size_t in_bs, size_t out_bs) {
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const int o = blockIdx.y;
   const double* in = in_base + (size_t)blockIdx.z * in_bs;
   double* out = out_base + (size_t)blockIdx.z * out_bs;
-  const int2 orow = out_rows[o];
-  const DevPrime& po = P[orow.y];
-  double acc = 0.0;
-  for (int k = 0; k < n_in; ++k) {
-    const int2 irow = in_rows[k];
-    const DevPrime& pk = P[irow.y];
-    double y = mod_mul(in[(size_t)irow.x * N + i], mult[k], pk.q, pk.qinv);
-    // y < q_k may exceed p_o: reduce before the product
-    double yr = mod_reduce(y, po.q, po.qinv);
-    acc = mod_add(acc, mod_mul(yr, mat[k * n_out + o], po.q, po.qinv), po.q);
+  double y[kBcIn];
+#pragma unroll
+  for (int k = 0; k < kBcIn; ++k) {
+    if (k < n_in) {
+      const int2 irow = in_rows[k];
+      const DevPrime& pk = P[irow.y];
+      y[k] = mod_mul(in[(size_t)irow.x * N + i], mult[k], pk.q, pk.qinv);
+    }
   }
-  out[(size_t)orow.x * N + i] = acc;
+  const int o0 = blockIdx.y * kBcOut;
+  const int o1 = min(n_out, o0 + kBcOut);
+  for (int o = o0; o < o1; ++o) {
+    const int2 orow = out_rows[o];
+    const DevPrime& po = P[orow.y];
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBcIn; ++k) {
+      if (k < n_in) {
+        // y < q_k may exceed p_o: reduce before the product
+        const double yr = mod_reduce(y[k], po.q, po.qinv);
+        acc = mod_add(acc, mod_mul(yr, mat[k * n_out + o], po.q, po.qinv), po.q);
+      }
+    }
+    out[(size_t)orow.x * N + i] = acc;
+  }
 }
 
 void launch_bconv(Context& c, double* out_base, const int2* out_rows, int n_out, const double* in_base,
                   const int2* in_rows, int n_in, const double* mult, const double* mat, int batch,
                   size_t in_bs, size_t out_bs) {
   if (n_out <= 0 || batch <= 0) return;
+  if (n_in > kBcIn) fail(COPSE_EINVAL, "base conversion supports at most 8 source primes");
   hipEvent_t ev;
   prof_begin(c, 5, &ev);
-  hipLaunchKernelGGL(bconv_kernel, dim3((unsigned)((c.N + 255) / 256), n_out, batch), dim3(256), 0, c.stream,
-                     out_base, out_rows, n_out, in_base, in_rows, n_in, mult, mat, c.d_primes, (int)c.log_n, in_bs,
-                     out_bs);
+  hipLaunchKernelGGL(bconv_kernel, dim3((unsigned)((c.N + 255) / 256), (n_out + kBcOut - 1) / kBcOut, batch),
+                     dim3(256), 0, c.stream, out_base, out_rows, n_out, in_base, in_rows, n_in, mult, mat,
+                     c.d_primes, (int)c.log_n, in_bs, out_bs);
   COPSE_HIP(hipGetLastError());
   prof_end(c, 5, ev, (double)n_out * batch);
 }
@@ -959,15 +1106,16 @@ __global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int 
   const DevPrime& pr = P[prime];
   const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
   const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
+  // lazy sums: each product is in (-0.91 q, 0.91 q); D <= 8 digits stay far below 2^52
   double a0 = 0.0, a1 = 0.0;
   for (int j = 0; j < D; ++j) {
     const double e = (j == own) ? jb.in[(size_t)o * N + src] : jb.ext[((size_t)j * nE + o) * N + src];
     const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
-    a0 = mod_add(a0, mod_mul(e, jb.kb[ko], pr.q, pr.qinv), pr.q);
-    a1 = mod_add(a1, mod_mul(e, jb.ka[ko], pr.q, pr.qinv), pr.q);
+    a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
+    a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
   }
-  jb.acc[(size_t)o * N + i] = a0;
-  jb.acc[((size_t)nE + o) * N + i] = a1;
+  jb.acc[(size_t)o * N + i] = canon(reduce_sym(a0, pr.q, pr.qinv), pr.q);
+  jb.acc[((size_t)nE + o) * N + i] = canon(reduce_sym(a1, pr.q, pr.qinv), pr.q);
 }
 
 void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds) {
@@ -1029,37 +1177,65 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
   }
 }
 
-// MatMul inner sums with a plaintext model: for output job z (group g, batch b)
-//   out[z] = sum_t baby[u_t][b] (.) diag_t   over the terms of group g
+// MatMul inner sums with a plaintext model: for group g and batch element b
+//   out[g][b] = sum_t baby[u_t][b] (.) diag_t   over the terms of group g.
+// A thread takes one coefficient of one limb for one group and up to kMmB batch elements, so each
+// diagonal value is read once per kMmB ciphertexts.  grid: x coefficients, y limbs,
+// z = group * ceil(G / kMmB) + chunk.
+constexpr int kMmB = 4;
 __global__ void mm_inner_kernel(double* out, const double* baby, const MMTerm* terms, const int* group_off, int G,
                                 int nl, size_t baby_slot, size_t baby_b, const DevPrime* P, int logN) {
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int l = blockIdx.y;
-  const int z = blockIdx.z;
-  const int g = z / G, b = z % G;
+  const int chunks = (G + kMmB - 1) / kMmB;
+  const int g = blockIdx.z / chunks, b0 = (blockIdx.z % chunks) * kMmB;
+  const int nb = min(kMmB, G - b0);
   const DevPrime& pr = P[l];
   const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
-  double a0 = 0.0, a1 = 0.0;
+  double a0[kMmB], a1[kMmB];
+#pragma unroll
+  for (int k = 0; k < kMmB; ++k) { a0[k] = 0.0; a1[k] = 0.0; }
+  // lazy sums of products in (-0.91 q, 0.91 q), folded back every 8 terms
+  int cnt = 0;
   for (int t = group_off[g]; t < group_off[g + 1]; ++t) {
     const MMTerm tm = terms[t];
-    const double* bp = baby + (size_t)tm.u * baby_slot + (size_t)b * baby_b;
     const double d = tm.diag[o];
-    a0 = mod_add(a0, mod_mul(bp[o], d, pr.q, pr.qinv), pr.q);
-    a1 = mod_add(a1, mod_mul(bp[ps + o], d, pr.q, pr.qinv), pr.q);
+    const double* bp = baby + (size_t)tm.u * baby_slot + (size_t)b0 * baby_b;
+#pragma unroll
+    for (int k = 0; k < kMmB; ++k) {
+      if (k < nb) {
+        a0[k] += mul_lazy(bp[(size_t)k * baby_b + o], d, pr.q, pr.qinv);
+        a1[k] += mul_lazy(bp[(size_t)k * baby_b + ps + o], d, pr.q, pr.qinv);
+      }
+    }
+    if (++cnt == 8) {
+      cnt = 0;
+#pragma unroll
+      for (int k = 0; k < kMmB; ++k) {
+        a0[k] = reduce_sym(a0[k], pr.q, pr.qinv);
+        a1[k] = reduce_sym(a1[k], pr.q, pr.qinv);
+      }
+    }
   }
-  double* op = out + (size_t)z * 2 * ps;
-  op[o] = a0;
-  op[ps + o] = a1;
+#pragma unroll
+  for (int k = 0; k < kMmB; ++k) {
+    if (k < nb) {
+      double* op = out + ((size_t)g * G + b0 + k) * 2 * ps;
+      op[o] = canon(reduce_sym(a0[k], pr.q, pr.qinv), pr.q);
+      op[ps + o] = canon(reduce_sym(a1[k], pr.q, pr.qinv), pr.q);
+    }
+  }
 }
 
 void launch_mm_inner(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
                      int n_groups, int G, int nl, size_t baby_slot, size_t baby_b) {
   hipEvent_t ev;
   prof_begin(c, 6, &ev);
-  hipLaunchKernelGGL(mm_inner_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * G), dim3(256), 0, c.stream,
-                     out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+  const int chunks = (G + kMmB - 1) / kMmB;
+  hipLaunchKernelGGL(mm_inner_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * chunks), dim3(256), 0,
+                     c.stream, out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
   prof_end(c, 6, ev, 2.0 * nl * n_groups * G);
 }
