@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--plain", action="store_true",
                     help="the unbatched path: each group alone, one homomorphic operation per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n1-r", type=int, default=0, help="baby steps of the reshuffle product (0: compiler default)")
+    ap.add_argument("--n1-l", type=int, default=0, help="baby steps of the level products (0: compiler default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is query-group "
@@ -146,7 +148,8 @@ def main():
     ctx = C.Context(**ch)
     stream = torch.cuda.Stream()
     ctx.set_stream(stream.cuda_stream)
-    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold)
+    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
+                                  n1_R=args.n1_r, n1_L=args.n1_l)
     rots = C.compiled_rotations(meta)
     keys = ctx.keygen(seed, rots)
     evk = ctx.export_eval(keys)
@@ -170,13 +173,9 @@ def main():
             return [ctx.evaluate(model, evk, groups[0])]
         return ctx.evaluate_batch(model, evk, groups)
 
-    # correctness of what is timed: decrypt the first warmup result
+    # the first warmup result is kept for the label check of the CPU-baseline leg
     res = step()
-    bits = ctx.decrypt_labels(keys, meta, res[0], nq_group)
-    from oracle import forest as F
-    _, trees = F.parse_forest(text)
-    want = np.array([F.evaluate(trees, list(x)) for x in queries[:nq_group]])
-    assert (bits == want).all(), "decrypted labels differ from plain evaluation"
+    first_bits = ctx.decrypt_labels(keys, meta, res[0], nq_group)
     del res
     for _ in range(max(0, args.warmup - 1)):
         step()
@@ -247,6 +246,11 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        # the oracle's plain forest evaluation checks the labels of what was timed
+        from oracle import forest as F
+        _, trees = F.parse_forest(text)
+        want = np.array([F.evaluate(trees, list(x)) for x in queries[:nq_group]])
+        assert (first_bits == want).all(), "decrypted labels differ from plain evaluation"
         cpu = cpu_baseline(w, text, queries, seed)
 
     out = {
@@ -269,7 +273,8 @@ def main():
                            ("batched" if args.batch > 1 else "single group"),
                    "N": N, "data_primes": ch["n_data_primes"], "special_primes": ch["alpha"],
                    "model": "plaintext" if not w.encrypted_model else "encrypted",
-                   "b": meta.b, "m": meta.m, "q": meta.q, "d": meta.d, "W": meta.block_w},
+                   "b": meta.b, "m": meta.m, "q": meta.q, "d": meta.d, "W": meta.block_w,
+                   "n1_R": meta.n1_R, "n1_L": meta.n1_L},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "profiled_mean": round(sum(per_step) / len(per_step), 3)},
         "roofline": roofline,

@@ -611,10 +611,19 @@ CtPtr op_modswitch(Context& c, const Ct& a) {
   std::vector<int2> tr;
   for (int k = 0; k < np; ++k) tr.push_back(make_int2(k, l));
   const int2* trows = c.rows("top:" + std::to_string(np) + ":" + std::to_string(l), tr);
-  launch_ntt_inv(c, top.get(), trows, np);
   DBuf w(&c, (size_t)np * l * N);
-  launch_ms_prep(c, w.get(), top.get(), np, l, T.d_ms);
-  launch_ntt_fwd(c, w.get(), ct_rows(c, np, l), np * l);
+  if (bridge_supported(c, 1)) {
+    std::vector<int2> ir{make_int2(0, l)}, orr;
+    for (int i = 0; i < l; ++i) orr.push_back(make_int2(i, i));
+    launch_ntt_inv_rows(c, top.get(), trows, np);
+    launch_bridge(c, 1, w.get(), c.rows("msout:" + std::to_string(l), orr), l, top.get(),
+                  c.rows("msin:" + std::to_string(l), ir), 1, T.d_ms + 1, nullptr, np, N, (size_t)l * N);
+    launch_ntt_fwd_rows(c, w.get(), ct_rows(c, np, l), np * l);
+  } else {
+    launch_ntt_inv(c, top.get(), trows, np);
+    launch_ms_prep(c, w.get(), top.get(), np, l, T.d_ms);
+    launch_ntt_fwd(c, w.get(), ct_rows(c, np, l), np * l);
+  }
   auto o = ct_alloc(c, l - 1, np);
   launch_ms_finish(c, o->data(), a.data(), w.get(), np, l, T.d_ms);
   return o;
@@ -628,19 +637,26 @@ static DBuf modup(Context& c, const double* d, int level) {
   KSTables& T = c.kstab(level);
   DBuf coef(&c, (size_t)nl * N);
   COPSE_HIP(hipMemcpyAsync(coef.get(), d, (size_t)nl * N * 8, hipMemcpyDeviceToDevice, c.stream));
-  launch_ntt_inv(c, coef.get(), ct_rows(c, 1, nl), nl);
+  const bool fused = bridge_supported(c, c.alpha);
+  if (fused) launch_ntt_inv_rows(c, coef.get(), ct_rows(c, 1, nl), nl);
+  else launch_ntt_inv(c, coef.get(), ct_rows(c, 1, nl), nl);
   DBuf ext(&c, (size_t)D * nE * N);
   std::vector<int2> nttrows;
   for (int j = 0; j < D; ++j) {
     auto& dg = T.digits[j];
-    launch_bconv(c, ext.get(), dg.d_out_rows, (int)dg.targets.size(), coef.get(), dg.d_in_rows, dg.count,
-                 dg.d_mult, dg.d_mat, 1, 0, 0);
+    if (fused)
+      launch_bridge(c, 0, ext.get(), dg.d_out_rows, (int)dg.targets.size(), coef.get(), dg.d_in_rows, dg.count,
+                    dg.d_mult, dg.d_mat, 1, 0, 0);
+    else
+      launch_bconv(c, ext.get(), dg.d_out_rows, (int)dg.targets.size(), coef.get(), dg.d_in_rows, dg.count,
+                   dg.d_mult, dg.d_mat, 1, 0, 0);
     COPSE_HIP(hipMemcpyAsync(ext.get() + ((size_t)j * nE + dg.first) * N, d + (size_t)dg.first * N,
                              (size_t)dg.count * N * 8, hipMemcpyDeviceToDevice, c.stream));
     for (int o : dg.targets) nttrows.push_back(make_int2(j * nE + o, o < nl ? o : c.L + 1 + (o - nl)));
   }
   const int2* nr = c.rows("modup:" + std::to_string(level), nttrows);
-  launch_ntt_fwd(c, ext.get(), nr, (int)nttrows.size());
+  if (fused) launch_ntt_fwd_rows(c, ext.get(), nr, (int)nttrows.size());
+  else launch_ntt_fwd(c, ext.get(), nr, (int)nttrows.size());
   return ext;
 }
 
@@ -654,16 +670,24 @@ static void moddown(Context& c, double* acc, int count, int level, double* out, 
   for (int k = 0; k < count; ++k)
     for (int r = 0; r < c.alpha; ++r) sr.push_back(make_int2(k * nE + nl + r, c.L + 1 + r));
   const int2* srows = c.rows("mdspec:" + std::to_string(level) + ":" + std::to_string(count), sr);
-  launch_ntt_inv(c, acc, srows, count * c.alpha);
+  const bool fused = bridge_supported(c, c.alpha);
+  if (fused) launch_ntt_inv_rows(c, acc, srows, count * c.alpha);
+  else launch_ntt_inv(c, acc, srows, count * c.alpha);
   DBuf zh(&c, (size_t)count * nl * N);
   std::vector<int2> inr, outr;
   for (int r = 0; r < c.alpha; ++r) inr.push_back(make_int2(nl + r, c.L + 1 + r));
   for (int i = 0; i < nl; ++i) outr.push_back(make_int2(i, i));
   const int2* in_rows = c.rows("mdin:" + std::to_string(level), inr);
   const int2* out_rows = c.rows("mdout:" + std::to_string(level), outr);
-  launch_bconv(c, zh.get(), out_rows, nl, acc, in_rows, c.alpha, T.d_md_mult, T.d_md_mat, count, (size_t)nE * N,
-               (size_t)nl * N);
-  launch_ntt_fwd(c, zh.get(), ct_rows(c, count, nl), count * nl);
+  if (fused) {
+    launch_bridge(c, 0, zh.get(), out_rows, nl, acc, in_rows, c.alpha, T.d_md_mult, T.d_md_mat, count,
+                  (size_t)nE * N, (size_t)nl * N);
+    launch_ntt_fwd_rows(c, zh.get(), ct_rows(c, count, nl), count * nl);
+  } else {
+    launch_bconv(c, zh.get(), out_rows, nl, acc, in_rows, c.alpha, T.d_md_mult, T.d_md_mat, count, (size_t)nE * N,
+                 (size_t)nl * N);
+    launch_ntt_fwd(c, zh.get(), ct_rows(c, count, nl), count * nl);
+  }
   launch_moddown_finish(c, out, acc, (size_t)nE * N, zh.get(), count, nl, T.d_md_pinv, T.d_md_tpinv, add, adds,
                         add_mode);
 }

@@ -55,10 +55,10 @@ struct MatPlan {
   uint32_t n1 = 1;
   bool enc = false;
   std::vector<int32_t> rots;
-  std::vector<uint32_t> groups;
-  DBuf terms_buf, off_buf;   // device MMTerm[] and int[groups + 1]
-  const MMTerm* d_terms = nullptr;
-  const int* d_off = nullptr;
+  std::vector<uint32_t> groups;   // giant groups with at least one nonzero diagonal
+  std::vector<const double*> tab;   // [rots][groups] diagonal pointers (null = zero diagonal)
+  DBuf tab_buf;                      // device copy of tab
+  const double* const* d_tab = nullptr;
 };
 
 struct Model {
@@ -66,6 +66,8 @@ struct Model {
   MatPlan plan_R;
   std::vector<MatPlan> plan_L;
   std::vector<int32_t> lvl_rots;
+  DBuf lcat_buf;                                // the level plans' tables side by side: [lvl_rots][sum of groups]
+  const double* const* d_lcat = nullptr;
   bool encrypted = false;
   int dec_level = 0, br_level = 0, lvl_level = 0;
   // comparison operands: plaintext thresholds -> E, C, G, TH plaintexts; encrypted -> TH ciphertexts

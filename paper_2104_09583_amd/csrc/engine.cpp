@@ -45,7 +45,9 @@ static const int2* block_rows(Context& c, int np, int nl) {
 }
 
 // ------------------------------------------------------------------ modulus switch (batched)
-std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in) {
+// adds (optional, one per input, may be null): added after the switch to the first add_np polys
+std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in,
+                             const std::vector<const double*>* adds = nullptr, int add_np = 0) {
   std::vector<SCt> out(in.size());
   std::map<std::pair<int, int>, std::vector<size_t>> groups;
   for (size_t i = 0; i < in.size(); ++i) groups[{in[i]->level, in[i]->npolys}].push_back(i);
@@ -63,19 +65,31 @@ std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in) {
     launch_gather(c, top.get(), src, 1);
     std::vector<int2> tr;
     for (int z = 0; z < J * np; ++z) tr.push_back(make_int2(z, l));
-    launch_ntt_inv(c, top.get(), rows_cached(c, "top:" + std::to_string(J * np) + ":" + std::to_string(l), tr), J * np);
+    const int2* trows = rows_cached(c, "top:" + std::to_string(J * np) + ":" + std::to_string(l), tr);
     DBuf w(&c, (size_t)J * np * l * N);
-    launch_ms_prep(c, w.get(), top.get(), J * np, l, T.d_ms);
-    launch_ntt_fwd(c, w.get(), block_rows(c, J * np, l), J * np * l);
+    if (bridge_supported(c, 1)) {
+      std::vector<int2> ir{make_int2(0, l)}, orr;
+      for (int i = 0; i < l; ++i) orr.push_back(make_int2(i, i));
+      launch_ntt_inv_rows(c, top.get(), trows, J * np);
+      launch_bridge(c, 1, w.get(), rows_cached(c, "msout:" + std::to_string(l), orr), l, top.get(),
+                    rows_cached(c, "msin:" + std::to_string(l), ir), 1, T.d_ms + 1, nullptr, J * np, N,
+                    (size_t)l * N);
+      launch_ntt_fwd_rows(c, w.get(), block_rows(c, J * np, l), J * np * l);
+    } else {
+      launch_ntt_inv(c, top.get(), trows, J * np);
+      launch_ms_prep(c, w.get(), top.get(), J * np, l, T.d_ms);
+      launch_ntt_fwd(c, w.get(), block_rows(c, J * np, l), J * np * l);
+    }
     auto outs = alloc_batch(c, J, l - 1, np);
     std::vector<double*> po;
-    std::vector<const double*> pi;
+    std::vector<const double*> pi, pa;
     for (int j = 0; j < J; ++j) {
       po.push_back(outs[j]->data());
       pi.push_back(in[idx[j]]->data());
+      if (adds) pa.push_back((*adds)[idx[j]]);
       out[idx[j]] = outs[j];
     }
-    launch_ms_finish_multi(c, po, pi, w.get(), np, l, T.d_ms);
+    launch_ms_finish_multi(c, po, pi, w.get(), np, l, T.d_ms, adds ? &pa : nullptr, add_np);
   }
   return out;
 }
@@ -114,12 +128,24 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   // ModUp of every input: coefficient form, base conversion per digit, transform of the new rows
   DBuf cf(&c, (size_t)I * nl * N);
   launch_gather(c, cf.get(), inputs, nl);
-  launch_ntt_inv(c, cf.get(), block_rows(c, I, nl), I * nl);
   DBuf ext(&c, (size_t)I * D * nE * N);
-  for (int j = 0; j < D; ++j) {
-    auto& dg = T.digits[j];
-    launch_bconv(c, ext.get(), dg.d_out_rows, (int)dg.targets.size(), cf.get(), dg.d_in_rows, dg.count, dg.d_mult,
-                 dg.d_mat, I, (size_t)nl * N, (size_t)D * nE * N);
+  const bool fused = bridge_supported(c, c.alpha);
+  if (fused) {
+    // inverse row pass, then per digit the fused column passes with the base conversion, then the
+    // forward row pass of every new row
+    launch_ntt_inv_rows(c, cf.get(), block_rows(c, I, nl), I * nl);
+    for (int j = 0; j < D; ++j) {
+      auto& dg = T.digits[j];
+      launch_bridge(c, 0, ext.get(), dg.d_out_rows, (int)dg.targets.size(), cf.get(), dg.d_in_rows, dg.count,
+                    dg.d_mult, dg.d_mat, I, (size_t)nl * N, (size_t)D * nE * N);
+    }
+  } else {
+    launch_ntt_inv(c, cf.get(), block_rows(c, I, nl), I * nl);
+    for (int j = 0; j < D; ++j) {
+      auto& dg = T.digits[j];
+      launch_bconv(c, ext.get(), dg.d_out_rows, (int)dg.targets.size(), cf.get(), dg.d_in_rows, dg.count, dg.d_mult,
+                   dg.d_mat, I, (size_t)nl * N, (size_t)D * nE * N);
+    }
   }
   {
     std::string key = "ksntt:" + std::to_string(level) + ":" + std::to_string(I);
@@ -137,7 +163,8 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
           for (int o : T.digits[j].targets) h.push_back(make_int2((i * D + j) * nE + o, o < nl ? o : c.L + 1 + (o - nl)));
       r = c.rows(key, h);
     }
-    launch_ntt_fwd(c, ext.get(), r, cnt);
+    if (fused) launch_ntt_fwd_rows(c, ext.get(), r, cnt);
+    else launch_ntt_fwd(c, ext.get(), r, cnt);
   }
   // inner products
   DBuf acc(&c, (size_t)R * 2 * nE * N);
@@ -161,16 +188,24 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
         for (int s = 0; s < c.alpha; ++s) h.push_back(make_int2(k * nE + nl + s, c.L + 1 + s));
       r = c.rows(key, h);
     }
-    launch_ntt_inv(c, acc.get(), r, 2 * R * c.alpha);
+    if (fused) launch_ntt_inv_rows(c, acc.get(), r, 2 * R * c.alpha);
+    else launch_ntt_inv(c, acc.get(), r, 2 * R * c.alpha);
   }
   DBuf zh(&c, (size_t)2 * R * nl * N);
   std::vector<int2> inr, outr;
   for (int s = 0; s < c.alpha; ++s) inr.push_back(make_int2(nl + s, c.L + 1 + s));
   for (int i = 0; i < nl; ++i) outr.push_back(make_int2(i, i));
-  launch_bconv(c, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
-               rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
-               (size_t)nE * N, (size_t)nl * N);
-  launch_ntt_fwd(c, zh.get(), block_rows(c, 2 * R, nl), 2 * R * nl);
+  if (fused) {
+    launch_bridge(c, 0, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
+                  rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
+                  (size_t)nE * N, (size_t)nl * N);
+    launch_ntt_fwd_rows(c, zh.get(), block_rows(c, 2 * R, nl), 2 * R * nl);
+  } else {
+    launch_bconv(c, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
+                 rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
+                 (size_t)nE * N, (size_t)nl * N);
+    launch_ntt_fwd(c, zh.get(), block_rows(c, 2 * R, nl), 2 * R * nl);
+  }
   std::vector<double*> outs;
   std::vector<const double*> adds;
   std::vector<uint64_t> gal;
@@ -272,21 +307,32 @@ static void b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*
 }
 
 // ------------------------------------------------------------------ MatMul (baby-step / giant-step)
-// babies: B[u][b] for the plan's rotation slots; result: one ciphertext per b (after the switch)
-static std::vector<SCt> b_matmul(Context& c, const Keys& k, const MatPlan& P, const double* B, int G, int level) {
+// Several products that share one baby-step buffer B[u][b] (the same rotation slots): one launch of the
+// inner sums over the giant groups of all of them (tab is their concatenated [u][group] diagonal table),
+// one batch of giant rotations, a sum per product and batch element, one switch for all.  adds[i * G + b]
+// (optional) is added to the first add_np polys of result (i, b) after the switch.
+static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, const std::vector<const MatPlan*>& plans,
+                                                   const double* const* tab, int n_u, const double* B, int G,
+                                                   int level, const std::vector<const double*>* adds = nullptr,
+                                                   int add_np = 0) {
   const size_t N = c.N;
   const int nl = level + 1;
   const size_t ps2 = (size_t)2 * nl * N, ps3 = (size_t)3 * nl * N;
-  const int ng = (int)P.groups.size();
-  DBuf inner(&c, (size_t)ng * G * (P.enc ? ps3 : ps2));
-  if (!P.enc) {
-    launch_mm_inner(c, inner.get(), B, P.d_terms, P.d_off, ng, G, nl, (size_t)G * ps2, ps2);
+  const bool enc = plans[0]->enc;
+  std::vector<int> off;
+  int ngs = 0;
+  for (auto* P : plans) {
+    if (P->enc != enc || P->n1 != plans[0]->n1) fail(COPSE_EINVAL, "internal: products of one batch differ");
+    if (P->groups.empty()) fail(COPSE_EINVAL, "internal: product without a nonzero diagonal");
+    off.push_back(ngs);
+    ngs += (int)P->groups.size();
   }
-  std::vector<SCt> in2;   // per (group, b) 2-poly inner sums
-  if (P.enc) {
-    launch_mm_inner_enc(c, inner.get(), B, P.d_terms, P.d_off, ng, G, nl, (size_t)G * ps2, ps2);
+  DBuf inner(&c, (size_t)ngs * G * (enc ? ps3 : ps2));
+  launch_mm_inner(c, inner.get(), B, tab, n_u, ngs, G, nl, (size_t)G * ps2, ps2, enc);
+  std::vector<SCt> in2;   // encrypted model: per (group, b) relinearized inner sums
+  if (enc) {
     std::vector<SCt> t3;
-    for (int z = 0; z < ng * G; ++z) {
+    for (int z = 0; z < ngs * G; ++z) {
       auto ct = std::make_shared<Ct>();
       ct->level = level; ct->npolys = 3; ct->n = N; ct->ptr = inner.get() + (size_t)z * ps3;
       t3.push_back(ct);
@@ -295,32 +341,45 @@ static std::vector<SCt> b_matmul(Context& c, const Keys& k, const MatPlan& P, co
     for (auto& x : t3) in3.push_back(x.get());
     in2 = b_relin(c, k, in3);
   }
-  auto ptr2 = [&](int z) -> const double* { return P.enc ? in2[z]->data() : inner.get() + (size_t)z * ps2; };
-  DBuf rb(&c, (size_t)ng * G * ps2);
+  auto ptr2 = [&](int z) -> const double* { return enc ? in2[z]->data() : inner.get() + (size_t)z * ps2; };
+  DBuf rb(&c, (size_t)ngs * G * ps2);
   std::vector<const double*> inputs;
   std::vector<KsReq> reqs;
-  for (int s = 0; s < ng; ++s) {
-    const uint32_t g = P.groups[s];
-    for (int b = 0; b < G; ++b) {
-      const int z = s * G + b;
-      double* dst = rb.get() + (size_t)z * ps2;
-      if (g == 0) {
-        COPSE_HIP(hipMemcpyAsync(dst, ptr2(z), ps2 * 8, hipMemcpyDeviceToDevice, c.stream));
-        continue;
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const MatPlan& P = *plans[i];
+    for (size_t s = 0; s < P.groups.size(); ++s) {
+      const uint32_t g = P.groups[s];
+      for (int b = 0; b < G; ++b) {
+        const int z = (off[i] + (int)s) * G + b;
+        double* dst = rb.get() + (size_t)z * ps2;
+        if (g == 0) {
+          // group 0 needs no rotation: the plaintext-model sum reads it in place
+          if (enc) COPSE_HIP(hipMemcpyAsync(dst, ptr2(z), ps2 * 8, hipMemcpyDeviceToDevice, c.stream));
+          continue;
+        }
+        const uint64_t gal = galois_of(c, (int64_t)g * P.n1);
+        auto it = k.rot.find(gal);
+        if (it == k.rot.end()) fail(COPSE_EKEY, "giant-step key absent");
+        inputs.push_back(ptr2(z) + (size_t)nl * N);
+        reqs.push_back(KsReq{(int)inputs.size() - 1, it->second.get(), gal, dst, ptr2(z)});
       }
-      const uint64_t gal = galois_of(c, (int64_t)g * P.n1);
-      auto it = k.rot.find(gal);
-      if (it == k.rot.end()) fail(COPSE_EKEY, "giant-step key absent");
-      inputs.push_back(ptr2(z) + (size_t)nl * N);
-      reqs.push_back(KsReq{(int)inputs.size() - 1, it->second.get(), gal, dst, ptr2(z)});
     }
   }
   ks_batch(c, level, inputs, reqs, 2);
-  auto sums = alloc_batch(c, G, level, 2);
-  launch_sum_parts(c, sums[0]->data(), rb.get(), ng, (size_t)G * ps2, ps2, nl, 2 * nl, G);
+  const int np = (int)plans.size();
+  auto sums = alloc_batch(c, np * G, level, 2);
+  for (int i = 0; i < np; ++i) {
+    const MatPlan& P = *plans[i];
+    const double* first = (!enc && P.groups[0] == 0) ? inner.get() + (size_t)off[i] * G * ps2 : nullptr;
+    launch_sum_parts(c, sums[(size_t)i * G]->data(), rb.get() + (size_t)off[i] * G * ps2, (int)P.groups.size(),
+                     (size_t)G * ps2, ps2, first, ps2, nl, 2 * nl, G);
+  }
   std::vector<const Ct*> sin;
   for (auto& x : sums) sin.push_back(x.get());
-  return b_modswitch(c, sin);
+  auto sw = b_modswitch(c, sin, adds, add_np);
+  std::vector<std::vector<SCt>> out(np);
+  for (int i = 0; i < np; ++i) out[i].assign(sw.begin() + (size_t)i * G, sw.begin() + (size_t)(i + 1) * G);
+  return out;
 }
 
 // ------------------------------------------------------------------ sums and masks
@@ -470,7 +529,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
     std::vector<const Ct*> v;
     for (auto& x : dec) v.push_back(x.get());
     b_rotate_into(c, k, v, P.rots, B.get());
-    src = b_matmul(c, k, P, B.get(), G, l);
+    src = b_matmul_many(c, k, {&P}, P.d_tab, (int)P.rots.size(), B.get(), G, l)[0];
   }
   // 3. levels: one set of hoisted baby rotations shared by every level
   std::vector<std::vector<SCt>> lv(M.meta.d);
@@ -480,32 +539,19 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
     std::vector<const Ct*> v;
     for (auto& x : src) v.push_back(x.get());
     b_rotate_into(c, k, v, M.lvl_rots, B.get());
+    // all level products at once; the mask is added by the switch that ends each product
+    std::vector<const MatPlan*> plans;
+    std::vector<const double*> madd;
+    const int ml = l - 1;
     for (uint32_t L_ = 0; L_ < M.meta.d; ++L_) {
-      auto r = b_matmul(c, k, M.plan_L[L_], B.get(), G, l);
-      // mask
-      const int ml = r[0]->level, nl = ml + 1;
-      auto outb = alloc_batch(c, G, ml, 2);
-      std::vector<double*> o;
-      std::vector<const double*> a, m;
-      for (int b = 0; b < G; ++b) {
-        o.push_back(outb[b]->data());
-        a.push_back(r[b]->data());
-      }
-      if (M.masks[L_].ct) {
-        if (M.masks[L_].ct->level != ml) fail(COPSE_EINVAL, "internal: mask level");
-        for (int b = 0; b < G; ++b) m.push_back(M.masks[L_].ct->data());
-        launch_ew_multi(c, 0, o, a, m, nl, 2 * nl, 2 * nl);
-      } else {
-        // plaintext mask goes to c0 only; c1 is copied
-        for (int b = 0; b < G; ++b) {
-          m.push_back(M.masks[L_].pt->buf.get());
-          COPSE_HIP(hipMemcpyAsync(outb[b]->poly(1, N), r[b]->poly(1, N), (size_t)nl * N * 8,
-                                   hipMemcpyDeviceToDevice, c.stream));
-        }
-        launch_ew_multi(c, 0, o, a, m, nl, nl, nl);
-      }
-      lv[L_] = outb;
+      plans.push_back(&M.plan_L[L_]);
+      const Operand& mk = M.masks[L_];
+      if (mk.ct && mk.ct->level != ml) fail(COPSE_EINVAL, "internal: mask level");
+      if (!mk.ct && mk.pt->level != ml) fail(COPSE_EINVAL, "internal: mask level");
+      for (int b = 0; b < G; ++b) madd.push_back(mk.ct ? mk.ct->data() : mk.pt->buf.get());
     }
+    lv = b_matmul_many(c, k, plans, M.d_lcat, (int)M.lvl_rots.size(), B.get(), G, l, &madd,
+                       M.masks[0].ct ? 2 : 1);
   }
   // 4. product tree
   while (lv.size() > 1) {

@@ -155,6 +155,25 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
   }
   M->plan_L.resize(meta.d);
   for (uint32_t l = 0; l < meta.d; ++l) build_plan(c, M->plan_L[l], M->ldiag[l], meta.n1_L, encrypt_model, &M->lvl_rots);
+  {
+    // all level products run as one launch over their concatenated giant groups
+    size_t ngs = 0;
+    for (auto& P : M->plan_L) ngs += P.groups.size();
+    const size_t nu = M->lvl_rots.size();
+    std::vector<const double*> cat(nu * ngs + kMmTabPad, nullptr);
+    size_t off = 0;
+    for (auto& P : M->plan_L) {
+      const size_t ng = P.groups.size();
+      for (size_t u = 0; u < nu; ++u)
+        for (size_t s = 0; s < ng; ++s) cat[u * ngs + off + s] = P.tab[u * ng + s];
+      off += ng;
+    }
+    M->lcat_buf = DBuf(&c, cat.size());
+    COPSE_HIP(hipMemcpyAsync(M->lcat_buf.get(), cat.data(), cat.size() * sizeof(const double*), hipMemcpyHostToDevice,
+                             c.stream));
+    COPSE_HIP(hipStreamSynchronize(c.stream));   // cat is a host temporary
+    M->d_lcat = reinterpret_cast<const double* const*>(M->lcat_buf.get());
+  }
   COPSE_HIP(hipStreamSynchronize(c.stream));
   return M;
 }
@@ -175,30 +194,33 @@ void build_plan(Context& c, MatPlan& P, const std::vector<Operand>& diags, uint3
   }
   std::map<int32_t, int> slot;
   for (size_t u = 0; u < P.rots.size(); ++u) slot[P.rots[u]] = (int)u;
-  std::vector<MMTerm> terms;
-  std::vector<int> off{0};
   const uint32_t n2 = (n + n1 - 1) / n1;
+  std::vector<std::vector<std::pair<int, const double*>>> per_group;
   for (uint32_t g = 0; g < n2; ++g) {
-    size_t before = terms.size();
+    std::vector<std::pair<int, const double*>> terms;
     for (uint32_t j = 0; j < n1; ++j) {
       uint32_t kd = g * n1 + j;
       if (kd >= n || diags[kd].zero()) continue;
       const double* dp = enc ? diags[kd].ct->data() : diags[kd].pt->buf.get();
-      terms.push_back(MMTerm{slot.at((int32_t)j), dp});
+      terms.emplace_back(slot.at((int32_t)j), dp);
     }
-    if (terms.size() > before) {
+    if (!terms.empty()) {
       P.groups.push_back(g);
-      off.push_back((int)terms.size());
+      per_group.push_back(std::move(terms));
     }
   }
-  P.terms_buf = DBuf(&c, std::max<size_t>(1, terms.size()) * 2);
-  P.off_buf = DBuf(&c, (off.size() + 1) / 2 + 1);
-  COPSE_HIP(hipMemcpyAsync(P.terms_buf.get(), terms.data(), terms.size() * sizeof(MMTerm), hipMemcpyHostToDevice,
-                           c.stream));
-  COPSE_HIP(hipMemcpyAsync(P.off_buf.get(), off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  const size_t nu = P.rots.size(), ng = P.groups.size();
+  std::vector<const double*>& tab = P.tab;
+  tab.assign(nu * ng, nullptr);
+  for (size_t s = 0; s < ng; ++s)
+    for (auto& t : per_group[s]) tab[(size_t)t.first * ng + s] = t.second;
+  std::vector<const double*> padded(tab);
+  padded.resize(tab.size() + kMmTabPad, nullptr);
+  P.tab_buf = DBuf(&c, padded.size());
+  COPSE_HIP(hipMemcpyAsync(P.tab_buf.get(), padded.data(), padded.size() * sizeof(const double*),
+                           hipMemcpyHostToDevice, c.stream));
   COPSE_HIP(hipStreamSynchronize(c.stream));
-  P.d_terms = reinterpret_cast<const MMTerm*>(P.terms_buf.get());
-  P.d_off = reinterpret_cast<const int*>(P.off_buf.get());
+  P.d_tab = reinterpret_cast<const double* const*>(P.tab_buf.get());
 }
 
 }  // namespace copse

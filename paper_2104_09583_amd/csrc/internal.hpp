@@ -201,6 +201,14 @@ struct KSTables {
 // ------------------------------------------------------------------ kernel launchers (kernels.hip)
 void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows);
 void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows);
+// split transform for the fused base changes (N = 2^13 .. 2^16, at most 4 input rows)
+bool bridge_supported(const Context& c, int n_in);
+void launch_ntt_inv_rows(Context& c, double* base, const int2* rows, int nrows);
+void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows);
+// mode 0: fast base conversion (as launch_bconv); mode 1: modulus-switch lift of one row (mult = t^-1)
+void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
+                   const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,
+                   size_t out_bs);
 // out = a op b over rows (same row layout for out, a, b)
 void launch_add(Context& c, double* out, const double* a, const double* b, const int2* rows, int nrows);
 void launch_sub(Context& c, double* out, const double* a, const double* b, const int2* rows, int nrows);
@@ -265,10 +273,6 @@ struct KsPack {
   static constexpr int kMax = 16;
   KsJob2 j[kMax];
 };
-struct MMTerm {
-  int u;                 // baby slot
-  const double* diag;    // plaintext [nl][N] or ciphertext [2][nl][N]
-};
 void launch_gather(Context& c, double* dst, const std::vector<const double*>& src, int rows);
 void launch_ew_multi(Context& c, int op, const std::vector<double*>& out, const std::vector<const double*>& a,
                      const std::vector<const double*>& b, int nl, int rows_per_job, int b_rows);
@@ -277,17 +281,20 @@ void launch_ptlayer(Context& c, const std::vector<double*>& out, const std::vect
 void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::vector<const double*>& a,
                          const std::vector<const double*>& b, int nl);
 void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
-                            const double* w, int np, int level, const double* tab);
+                            const double* w, int np, int level, const double* tab,
+                            const std::vector<const double*>* add = nullptr, int add_np = 0);
 void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds);
 void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
                        const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE, int nl,
                        const double* pinv, const double* tpinv, int add_mode);
-void launch_mm_inner(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
-                     int n_groups, int G, int nl, size_t baby_slot, size_t baby_b);
-void launch_mm_inner_enc(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
-                         int n_groups, int G, int nl, size_t baby_slot, size_t baby_b);
+// MatMul inner sums.  The device table holds kMmTabPad null entries past its end (the kernel fetches
+// whole chunks of a row); tab[u * n_groups + s] is the pre-rotated diagonal that multiplies baby step u in giant
+// group s (plaintext [nl][N], or ciphertext [2][nl][N] when enc), null when that diagonal is zero.
+constexpr int kMmTabPad = 32;
+void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int n_groups,
+                     int G, int nl, size_t baby_slot, size_t baby_b, bool enc);
 void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
-                      int nl, int rows, int G);
+                      const double* first, size_t first_stride_b, int nl, int rows, int G);
 void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const std::vector<double*>& lt,
                             const std::vector<const double*>& u, const std::vector<const double*>& xs,
                             const std::vector<const double*>& ts, int nl);

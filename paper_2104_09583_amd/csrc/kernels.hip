@@ -9,6 +9,7 @@
 // operation.  Rows are contiguous and each wavefront touches consecutive
 // addresses.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -580,6 +581,167 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
   prof_end(c, 2, ev, nrows);
 }
 
+// ------------------------------------------------------------------ fused column passes + base change
+// Every ModUp, ModDown and modulus switch is "inverse transform of some rows, a coefficient-wise map
+// to rows of other primes, forward transform of those".  With the two-pass transform the inverse ends
+// and the forward begins with the same column pass (stages 0..S1-1 on columns j + C k of the
+// 2^S1 x C view), so one kernel runs, per column: the last inverse stages (and the N^-1 scaling) of the
+// n_in input rows, the coefficient map, and the first forward stages of each output row.  The row
+// passes stay separate (launch_ntt_inv_rows / launch_ntt_fwd_rows).  Maps:
+//   kMode 0 (fast base conversion): out_o = sum_k [x_k mult_k]_{p_k} mat[k][o]  mod q_o
+//   kMode 1 (modulus switch):       z = [x_0 mult_0]_{p_0} centered,  out_o = z mod q_o
+// The values handed to the forward stages are any representatives of the residues (|v| <= q/2), so the
+// transform's canonical output is the same as that of the unfused steps.
+// grid: x over column groups of 64, z over the batch (in_bs / out_bs apart).
+constexpr int kBridgeIn = 4;
+template <int S1, int kMode>
+__global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out_base, const int2* __restrict__ out_rows,
+                                                       int n_out, const double* __restrict__ in_base,
+                                                       const int2* __restrict__ in_rows, int n_in,
+                                                       const double* __restrict__ mult, const double* __restrict__ mat,
+                                                       const DevPrime* __restrict__ P, int logN, size_t in_bs,
+                                                       size_t out_bs) {
+  constexpr int R = 1 << S1;
+  const size_t N = (size_t)1 << logN;
+  const size_t C = N >> S1;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const double* in = in_base + (size_t)blockIdx.z * in_bs;
+  double* out = out_base + (size_t)blockIdx.z * out_bs;
+  double y[kBridgeIn][R];
+#pragma unroll
+  for (int k = 0; k < kBridgeIn; ++k) {
+    if (k < n_in) {
+      const int2 irow = in_rows[k];
+      const DevPrime& pk = P[irow.y];
+      const double* a = in + (size_t)irow.x * N;
+      double x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = a[r * C + c];
+#pragma unroll
+      for (int s = S1 - 1; s >= 0; --s) {
+        const int half = R >> (s + 1);
+#pragma unroll
+        for (int g = 0; g < (1 << s); ++g) {
+          const double w = pk.inv[(1 << s) + g];
+#pragma unroll
+          for (int o = 0; o < half; ++o) bfly_gs(x[g * 2 * half + o], x[g * 2 * half + o + half], w, pk.q, pk.qinv);
+        }
+      }
+      const double mk = mult[k];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // coefficient in [0, p_k), then [coef * mult_k]_{p_k} in [0, p_k)
+        const double cf = canon(reduce_sym(mul_lazy(x[r], pk.ninv, pk.q, pk.qinv), pk.q, pk.qinv), pk.q);
+        double v = canon(mul_lazy(cf, mk, pk.q, pk.qinv), pk.q);
+        if (kMode == 1 && v > (pk.q - 1.0) * 0.5) v -= pk.q;
+        y[k][r] = v;
+      }
+    }
+  }
+  for (int o = 0; o < n_out; ++o) {
+    const int2 orow = out_rows[o];
+    const DevPrime& po = P[orow.y];
+    double x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (kMode == 0) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBridgeIn; ++k)
+          if (k < n_in) acc += mul_lazy(y[k][r], mat[k * n_out + o], po.q, po.qinv);
+        x[r] = reduce_sym(acc, po.q, po.qinv);
+      } else {
+        x[r] = reduce_sym(y[0][r], po.q, po.qinv);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S1; ++s) {
+      const int half = R >> (s + 1);
+#pragma unroll
+      for (int g = 0; g < (1 << s); ++g) {
+        const double w = po.fwd[(1 << s) + g];
+#pragma unroll
+        for (int oo = 0; oo < half; ++oo) bfly_ct(x[g * 2 * half + oo], x[g * 2 * half + oo + half], w, po.q, po.qinv);
+      }
+    }
+    double* a = out + (size_t)orow.x * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r * C + c] = reduce_sym(x[r], po.q, po.qinv);
+  }
+}
+
+bool bridge_supported(const Context& c, int n_in) { return c.log_n >= 13 && c.log_n <= 16 && n_in <= kBridgeIn; }
+
+void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
+                   const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,
+                   size_t out_bs) {
+  if (n_out <= 0 || batch <= 0) return;
+  if (!bridge_supported(c, n_in)) fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
+  if (mode == 1 && n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
+  const int S1 = (int)c.log_n - 12;
+  const unsigned C = (unsigned)(c.N >> S1);
+  hipEvent_t ev;
+  prof_begin(c, 5, &ev);
+  for (int first = 0; first < batch; first += kMaxGridY) {
+    const int cnt = std::min(kMaxGridY, batch - first);
+    dim3 grid((C + 63) / 64, 1, cnt), blk(64);
+    const double* ib = in_base + (size_t)first * in_bs;
+    double* ob = out_base + (size_t)first * out_bs;
+#define COPSE_BRIDGE(S, M)                                                                                        \
+  hipLaunchKernelGGL((ntt_bridge_kernel<S, M>), grid, blk, 0, c.stream, ob, out_rows, n_out, ib, in_rows, n_in, mult, \
+                     mat, c.d_primes, (int)c.log_n, in_bs, out_bs)
+    if (mode == 0) {
+      switch (S1) {
+        case 1: COPSE_BRIDGE(1, 0); break;
+        case 2: COPSE_BRIDGE(2, 0); break;
+        case 3: COPSE_BRIDGE(3, 0); break;
+        default: COPSE_BRIDGE(4, 0); break;
+      }
+    } else {
+      switch (S1) {
+        case 1: COPSE_BRIDGE(1, 1); break;
+        case 2: COPSE_BRIDGE(2, 1); break;
+        case 3: COPSE_BRIDGE(3, 1); break;
+        default: COPSE_BRIDGE(4, 1); break;
+      }
+    }
+#undef COPSE_BRIDGE
+    COPSE_HIP(hipGetLastError());
+  }
+  prof_end(c, 5, ev, (double)(n_out + n_in) * batch);
+}
+
+// row passes alone (the column passes are done by the bridge): inverse rows leave signed residues for
+// the bridge, forward rows take the bridge's output and finish the transform (canonical)
+void launch_ntt_inv_rows(Context& c, double* base, const int2* rows, int nrows) {
+  if (nrows <= 0) return;
+  if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  for (int first = 0; first < nrows; first += kMaxGridY) {
+    const int cnt = std::min(kMaxGridY, nrows - first);
+    hipEvent_t ev;
+    prof_begin(c, 2, &ev);
+    hipLaunchKernelGGL(ntt_rowreg4_kernel<true>, dim3((unsigned)(c.N / 4096), cnt), dim3(512), 0, c.stream, base,
+                       rows + first, c.d_primes, (int)c.log_n, (int)c.log_n - 12, 0);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 2, ev, cnt);
+  }
+}
+
+void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows) {
+  if (nrows <= 0) return;
+  if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  for (int first = 0; first < nrows; first += kMaxGridY) {
+    const int cnt = std::min(kMaxGridY, nrows - first);
+    hipEvent_t ev;
+    prof_begin(c, 0, &ev);
+    hipLaunchKernelGGL(ntt_rowreg4_kernel<false>, dim3((unsigned)(c.N / 4096), cnt), dim3(512), 0, c.stream, base,
+                       rows + first, c.d_primes, (int)c.log_n, (int)c.log_n - 12, 0);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 0, ev, cnt);
+  }
+}
+
 // ------------------------------------------------------------------ elementwise
 // grid: x over coefficients (256 threads, 1 element each), y over rows
 #define EW_PROLOGUE                                          \
@@ -767,13 +929,17 @@ void launch_automorphism(Context& c, double* out, const double* in, uint64_t g, 
 // ------------------------------------------------------------------ fast base conversion
 // out_o[c] = sum_i [in_i[c] * mult_i]_{q_i} * mat[i][o]  mod p_o
 // A thread converts one coefficient for up to kBcOut outputs: the n_in inputs are read once and
-// their scaled residues y_i stay in registers.  grid: x over coefficients, y over output chunks,
+// their scaled residues y_i in [0, q_i) stay in registers.  For |a| < 2^49 and b in [0, p) the lazy
+// product a b - p rint(a b / p) is exact with magnitude below 0.69 p (the quotient estimate is off by at
+// most 2^-3 from the rounding of 1/p and 2^-4 from the dropped low product), so the n_in <= 8 terms sum
+// below 5.6 p before a single symmetric reduction.  grid: x over coefficients, y over output chunks,
 // z over the batch.
 constexpr int kBcIn = 8;
-constexpr int kBcOut = 8;
-__global__ void bconv_kernel(double* out_base, const int2* out_rows, int n_out, const double* in_base,
-                             const int2* in_rows, int n_in, const double* mult, const double* mat,
-                             const DevPrime* P, int logN, size_t in_bs, size_t out_bs) {
+constexpr int kBcOut = 16;
+__global__ __launch_bounds__(256) void bconv_kernel(double* out_base, const int2* out_rows, int n_out,
+                                                    const double* in_base, const int2* in_rows, int n_in,
+                                                    const double* mult, const double* mat, const DevPrime* P,
+                                                    int logN, size_t in_bs, size_t out_bs) {
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -785,24 +951,24 @@ __global__ void bconv_kernel(double* out_base, const int2* out_rows, int n_out, 
     if (k < n_in) {
       const int2 irow = in_rows[k];
       const DevPrime& pk = P[irow.y];
-      y[k] = mod_mul(in[(size_t)irow.x * N + i], mult[k], pk.q, pk.qinv);
+      y[k] = canon(mul_lazy(in[(size_t)irow.x * N + i], mult[k], pk.q, pk.qinv), pk.q);
     }
   }
   const int o0 = blockIdx.y * kBcOut;
-  const int o1 = min(n_out, o0 + kBcOut);
-  for (int o = o0; o < o1; ++o) {
-    const int2 orow = out_rows[o];
-    const DevPrime& po = P[orow.y];
-    double acc = 0.0;
+  const int no = min(n_out - o0, kBcOut);
+  // unrolled so that the per-output constants are fetched together and the stores overlap
 #pragma unroll
-    for (int k = 0; k < kBcIn; ++k) {
-      if (k < n_in) {
-        // y < q_k may exceed p_o: reduce before the product
-        const double yr = mod_reduce(y[k], po.q, po.qinv);
-        acc = mod_add(acc, mod_mul(yr, mat[k * n_out + o], po.q, po.qinv), po.q);
-      }
+  for (int oo = 0; oo < kBcOut; ++oo) {
+    if (oo < no) {
+      const int o = o0 + oo;
+      const int2 orow = out_rows[o];
+      const DevPrime& po = P[orow.y];
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kBcIn; ++k)
+        if (k < n_in) acc += mul_lazy(y[k], mat[k * n_out + o], po.q, po.qinv);
+      out[(size_t)orow.x * N + i] = canon(reduce_sym(acc, po.q, po.qinv), po.q);
     }
-    out[(size_t)orow.x * N + i] = acc;
   }
 }
 
@@ -1063,8 +1229,9 @@ void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::v
 }
 
 // modulus switch finish over jobs: out_j[k][i] = in_j[k][i] q_l^-1 - w[(j np + k)][i] t q_l^-1
-__global__ void ms_finish_multi_kernel(MPack out, Pack in, const double* w, int np, int l, const double* tab,
-                                       const DevPrime* P, int logN) {
+// out_j = (in_j - t z_j) q_l^-1 (+ add_j on the first add_np polys, when add_j is given)
+__global__ void ms_finish_multi_kernel(MPack out, Pack in, Pack add, int add_np, const double* w, int np, int l,
+                                       const double* tab, const DevPrime* P, int logN) {
   const size_t N = (size_t)1 << logN;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
@@ -1074,21 +1241,29 @@ __global__ void ms_finish_multi_kernel(MPack out, Pack in, const double* w, int 
   const DevPrime& pi = P[i];
   const double x = in.p[j][((size_t)k * (l + 1) + i) * N + c];
   const double y = w[((size_t)z * l + i) * N + c];
-  out.p[j][((size_t)k * l + i) * N + c] =
-      mod_sub(mod_mul(x, tab[2 + 2 * i], pi.q, pi.qinv), mod_mul(y, tab[3 + 2 * i], pi.q, pi.qinv), pi.q);
+  const size_t oo = ((size_t)k * l + i) * N + c;
+  double v = mod_sub(mod_mul(x, tab[2 + 2 * i], pi.q, pi.qinv), mod_mul(y, tab[3 + 2 * i], pi.q, pi.qinv), pi.q);
+  if (k < add_np && add.p[j] != nullptr) v = mod_add(v, add.p[j][oo], pi.q);
+  out.p[j][oo] = v;
 }
 
 void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
-                            const double* w, int np, int level, const double* tab) {
+                            const double* w, int np, int level, const double* tab,
+                            const std::vector<const double*>* add, int add_np) {
   for (size_t first = 0; first < out.size(); first += kPack) {
     int cnt = (int)std::min<size_t>(kPack, out.size() - first);
     MPack po;
-    Pack pi;
-    for (int k = 0; k < cnt; ++k) { po.p[k] = out[first + k]; pi.p[k] = in[first + k]; }
+    Pack pi, pa;
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k];
+      pi.p[k] = in[first + k];
+      pa.p[k] = add ? (*add)[first + k] : nullptr;
+    }
     hipEvent_t ev;
     prof_begin(c, 6, &ev);
     hipLaunchKernelGGL(ms_finish_multi_kernel, dim3((unsigned)((c.N + 255) / 256), level, cnt * np), dim3(256), 0,
-                       c.stream, po, pi, w + first * np * level * c.N, np, level, tab, c.d_primes, (int)c.log_n);
+                       c.stream, po, pi, pa, add ? add_np : 0, w + first * np * level * c.N, np, level, tab,
+                       c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 6, ev, (double)level * np * cnt);
   }
@@ -1177,123 +1352,161 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
   }
 }
 
-// MatMul inner sums with a plaintext model: for group g and batch element b
-//   out[g][b] = sum_t baby[u_t][b] (.) diag_t   over the terms of group g.
-// A thread takes one coefficient of one limb for one group and up to kMmB batch elements, so each
-// diagonal value is read once per kMmB ciphertexts.  grid: x coefficients, y limbs,
-// z = group * ceil(G / kMmB) + chunk.
-constexpr int kMmB = 4;
-__global__ void mm_inner_kernel(double* out, const double* baby, const MMTerm* terms, const int* group_off, int G,
-                                int nl, size_t baby_slot, size_t baby_b, const DevPrime* P, int logN) {
+// MatMul inner sums (diagonal method, one giant group per output):
+//   plaintext model:  out[s][b]     = sum_u baby[u][b] (.) diag(u, s)            (2 polys)
+//   encrypted model:  out[s][b]     = sum_u tensor(baby[u][b], diag(u, s))       (3 polys)
+// One thread owns one coefficient of one limb of one batch element and keeps the sums of GM giant
+// groups in registers, so each baby-step value is read once per launch (per group chunk) instead of
+// once per term.  A workgroup is 64 coefficients (one per lane) x 4 batch elements (one per wave), so the
+// four waves read the same diagonal values back to back (L1 hits), and the workgroups of one coefficient
+// tile are placed on one XCD back to back so that the other batch elements find them in its L2.  Per baby
+// step the GM diagonal loads are issued together (a zero diagonal loads the baby value again, which is in
+// cache, and its product is skipped by a uniform branch).
+// Sums are lazy (|term| < 0.91 q) and folded back with reduce_sym every kRed baby steps.
+// grid: x = (N / 64) x ceil(G / 4) (XCD-aware), y = limbs, z = giant-group chunks of GM.
+constexpr int kMmLanes = 64, kMmWaves = 4;
+// a load known to be from global memory (not through a flat address): it does not hold up the scalar
+// loads of the pointer table, which flat loads would (both count on the same wait counter)
+__device__ __forceinline__ double gload(const double* p) {
+  return *(const __attribute__((address_space(1))) double*)(p);
+}
+template <int GM, bool kEnc>
+__global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out, const double* __restrict__ baby,
+                                                       const double* const* __restrict__ tab, int n_u, int ng, int G,
+                                                       int nl, size_t baby_slot, size_t baby_b, const DevPrime* P,
+                                                       int logN) {
+  constexpr int kNp = kEnc ? 3 : 2;
+  constexpr int kRed = kEnc ? 3 : 7;
   const size_t N = (size_t)1 << logN;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  // consecutive workgroups go to different XCDs: give each XCD a contiguous range of logical blocks so
+  // that the batch chunks of one coefficient tile run on one XCD together
+  unsigned bx = blockIdx.x;
+  const unsigned nbx = gridDim.x;
+  if ((nbx & 7u) == 0) bx = (bx & 7u) * (nbx >> 3) + (bx >> 3);
+  const unsigned bchunks = (unsigned)(G + kMmWaves - 1) / kMmWaves;
+  // the batch element is uniform per wave: keep it (and the baby pointers) in scalar registers
+  const int b = (int)(bx % bchunks) * kMmWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kMmLanes));
+  const size_t i = (size_t)(bx / bchunks) * kMmLanes + (threadIdx.x % kMmLanes);
+  if (i >= N || b >= G) return;
   const int l = blockIdx.y;
-  const int chunks = (G + kMmB - 1) / kMmB;
-  const int g = blockIdx.z / chunks, b0 = (blockIdx.z % chunks) * kMmB;
-  const int nb = min(kMmB, G - b0);
+  const int s0 = blockIdx.z * GM;
+  const int gm = min(GM, ng - s0);
   const DevPrime& pr = P[l];
   const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
-  double a0[kMmB], a1[kMmB];
+  double acc[GM][kNp];
 #pragma unroll
-  for (int k = 0; k < kMmB; ++k) { a0[k] = 0.0; a1[k] = 0.0; }
-  // lazy sums of products in (-0.91 q, 0.91 q), folded back every 8 terms
+  for (int s = 0; s < GM; ++s)
+#pragma unroll
+    for (int p = 0; p < kNp; ++p) acc[s][p] = 0.0;
   int cnt = 0;
-  for (int t = group_off[g]; t < group_off[g + 1]; ++t) {
-    const MMTerm tm = terms[t];
-    const double d = tm.diag[o];
-    const double* bp = baby + (size_t)tm.u * baby_slot + (size_t)b0 * baby_b;
+  for (int u = 0; u < n_u; ++u) {
+    // tables carry kMmTabPad trailing entries, so all GM pointers of a row can be fetched together
+    const double* const* row = tab + (size_t)u * ng + s0;
+    const double* ptr[GM];
+    bool any = false;
 #pragma unroll
-    for (int k = 0; k < kMmB; ++k) {
-      if (k < nb) {
-        a0[k] += mul_lazy(bp[(size_t)k * baby_b + o], d, pr.q, pr.qinv);
-        a1[k] += mul_lazy(bp[(size_t)k * baby_b + ps + o], d, pr.q, pr.qinv);
+    for (int s = 0; s < GM; ++s) {
+      const double* pv = row[s];
+      ptr[s] = s < gm ? pv : nullptr;
+      any |= ptr[s] != nullptr;
+    }
+    if (!any) continue;   // uniform: this baby step has no term in the chunk
+    const double* bp = baby + (size_t)u * baby_slot + (size_t)b * baby_b;
+    const double x0 = gload(bp + o), x1 = gload(bp + ps + o);
+    double d0[GM], d1[GM];
+#pragma unroll
+    for (int s = 0; s < GM; ++s) {
+      const double* dp = ptr[s] != nullptr ? ptr[s] : bp;
+      d0[s] = gload(dp + o);
+      if (kEnc) d1[s] = gload(dp + ps + o);
+    }
+#pragma unroll
+    for (int s = 0; s < GM; ++s) {
+      if (ptr[s] != nullptr) {
+        if (kEnc) {
+          acc[s][0] += mul_lazy(x0, d0[s], pr.q, pr.qinv);
+          acc[s][1] += mul_lazy(x0, d1[s], pr.q, pr.qinv) + mul_lazy(x1, d0[s], pr.q, pr.qinv);
+          acc[s][kNp - 1] += mul_lazy(x1, d1[s], pr.q, pr.qinv);
+        } else {
+          acc[s][0] += mul_lazy(x0, d0[s], pr.q, pr.qinv);
+          acc[s][1] += mul_lazy(x1, d0[s], pr.q, pr.qinv);
+        }
       }
     }
-    if (++cnt == 8) {
+    if (++cnt == kRed) {
       cnt = 0;
 #pragma unroll
-      for (int k = 0; k < kMmB; ++k) {
-        a0[k] = reduce_sym(a0[k], pr.q, pr.qinv);
-        a1[k] = reduce_sym(a1[k], pr.q, pr.qinv);
-      }
+      for (int s = 0; s < GM; ++s)
+#pragma unroll
+        for (int p = 0; p < kNp; ++p) acc[s][p] = reduce_sym(acc[s][p], pr.q, pr.qinv);
     }
   }
 #pragma unroll
-  for (int k = 0; k < kMmB; ++k) {
-    if (k < nb) {
-      double* op = out + ((size_t)g * G + b0 + k) * 2 * ps;
-      op[o] = canon(reduce_sym(a0[k], pr.q, pr.qinv), pr.q);
-      op[ps + o] = canon(reduce_sym(a1[k], pr.q, pr.qinv), pr.q);
+  for (int s = 0; s < GM; ++s) {
+    if (s < gm) {
+      double* op = out + ((size_t)(s0 + s) * G + b) * kNp * ps;
+#pragma unroll
+      for (int p = 0; p < kNp; ++p) op[(size_t)p * ps + o] = canon(reduce_sym(acc[s][p], pr.q, pr.qinv), pr.q);
     }
   }
 }
 
-void launch_mm_inner(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
-                     int n_groups, int G, int nl, size_t baby_slot, size_t baby_b) {
+template <int GM, bool kEnc>
+static void mm_inner_launch(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng,
+                            int G, int nl, size_t baby_slot, size_t baby_b) {
+  const unsigned tiles = (unsigned)((c.N + kMmLanes - 1) / kMmLanes);
+  const unsigned bchunks = (unsigned)((G + kMmWaves - 1) / kMmWaves);
+  hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc>), dim3(tiles * bchunks, nl, (ng + GM - 1) / GM), dim3(256), 0,
+                     c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+}
+
+void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng, int G,
+                     int nl, size_t baby_slot, size_t baby_b, bool enc) {
+  if (ng <= 0 || G <= 0) return;
+  if ((size_t)((c.N + kMmLanes - 1) / kMmLanes) * (size_t)((G + kMmWaves - 1) / kMmWaves) > 0x7fffffffu)
+    fail(COPSE_EINVAL, "MatMul batch too large");
   hipEvent_t ev;
   prof_begin(c, 6, &ev);
-  const int chunks = (G + kMmB - 1) / kMmB;
-  hipLaunchKernelGGL(mm_inner_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * chunks), dim3(256), 0,
-                     c.stream, out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+  // giant groups in chunks of at most 24 (12 with three accumulators each), split evenly
+  const int cap = enc ? 12 : 24;   // at most 165 VGPRs: three waves per SIMD
+  const int chunks = (ng + cap - 1) / cap;
+  const int per = (ng + chunks - 1) / chunks;
+  auto run = [&](auto gm_tag) {
+    constexpr int GM = decltype(gm_tag)::value;
+    if (enc) mm_inner_launch<GM, true>(c, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b);
+    else mm_inner_launch<GM, false>(c, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b);
+  };
+  if (per <= 4) run(std::integral_constant<int, 4>());
+  else if (per <= 8) run(std::integral_constant<int, 8>());
+  else if (per <= 12) run(std::integral_constant<int, 12>());
+  else if (per <= 16) run(std::integral_constant<int, 16>());
+  else if (per <= 24) run(std::integral_constant<int, 24>());
+  else run(std::integral_constant<int, 32>());
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, 2.0 * nl * n_groups * G);
+  prof_end(c, 6, ev, (enc ? 3.0 : 2.0) * nl * ng * G);
 }
 
-// Encrypted-model MatMul inner sums: out[z] (3 polys) = sum_t tensor(baby[u_t][b], diag_t)
-__global__ void mm_inner_enc_kernel(double* out, const double* baby, const MMTerm* terms, const int* group_off,
-                                    int G, int nl, size_t baby_slot, size_t baby_b, const DevPrime* P, int logN) {
-  const size_t N = (size_t)1 << logN;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int l = blockIdx.y;
-  const int z = blockIdx.z;
-  const int g = z / G, b = z % G;
-  const DevPrime& pr = P[l];
-  const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
-  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-  for (int t = group_off[g]; t < group_off[g + 1]; ++t) {
-    const MMTerm tm = terms[t];
-    const double* bp = baby + (size_t)tm.u * baby_slot + (size_t)b * baby_b;
-    const double x0 = bp[o], x1 = bp[ps + o], y0 = tm.diag[o], y1 = tm.diag[ps + o];
-    d0 = mod_add(d0, mod_mul(x0, y0, pr.q, pr.qinv), pr.q);
-    d1 = mod_add(d1, mod_add(mod_mul(x0, y1, pr.q, pr.qinv), mod_mul(x1, y0, pr.q, pr.qinv), pr.q), pr.q);
-    d2 = mod_add(d2, mod_mul(x1, y1, pr.q, pr.qinv), pr.q);
-  }
-  double* op = out + (size_t)z * 3 * ps;
-  op[o] = d0;
-  op[ps + o] = d1;
-  op[2 * ps + o] = d2;
-}
-
-void launch_mm_inner_enc(Context& c, double* out, const double* baby, const MMTerm* terms, const int* group_off,
-                         int n_groups, int G, int nl, size_t baby_slot, size_t baby_b) {
-  hipEvent_t ev;
-  prof_begin(c, 6, &ev);
-  hipLaunchKernelGGL(mm_inner_enc_kernel, dim3((unsigned)((c.N + 255) / 256), nl, n_groups * G), dim3(256), 0,
-                     c.stream, out, baby, terms, group_off, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
-  COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, 3.0 * nl * n_groups * G);
-}
-
-// out_b = sum_{p < nparts} parts[p * stride_p + b * stride_b]  over rows (row r has prime r % nl)
+// out_b = sum_{p < nparts} parts[p * stride_p + b * stride_b]  over rows (row r has prime r % nl);
+// when first is given, part 0 of batch element b is read from first + b * first_stride_b instead
 __global__ void sum_parts_kernel(double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
-                                 int nl, int rows, const DevPrime* P, int logN) {
+                                 const double* first, size_t first_stride_b, int nl, int rows, const DevPrime* P,
+                                 int logN) {
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int r = blockIdx.y, b = blockIdx.z;
   const DevPrime& pr = P[r % nl];
   const size_t o = (size_t)r * N + i;
-  double acc = 0.0;
-  for (int p = 0; p < nparts; ++p) acc = mod_add(acc, parts[(size_t)p * stride_p + (size_t)b * stride_b + o], pr.q);
+  double acc = first ? first[(size_t)b * first_stride_b + o] : parts[(size_t)b * stride_b + o];
+  for (int p = 1; p < nparts; ++p) acc = mod_add(acc, parts[(size_t)p * stride_p + (size_t)b * stride_b + o], pr.q);
   out[(size_t)b * rows * N + o] = acc;
 }
 
 void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
-                      int nl, int rows, int G) {
+                      const double* first, size_t first_stride_b, int nl, int rows, int G) {
+  if (nparts <= 0) fail(COPSE_EINVAL, "internal: empty sum");
   hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((c.N + 255) / 256), rows, G), dim3(256), 0, c.stream, out,
-                     parts, nparts, stride_p, stride_b, nl, rows, c.d_primes, (int)c.log_n);
+                     parts, nparts, stride_p, stride_b, first, first_stride_b, nl, rows, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
 }
 

@@ -181,6 +181,55 @@ def test_missing_key_and_exhausted_chain(C, small):
     assert e.value.code == C.COPSE_EKEY
 
 
+# Ring sizes that take the split transform with the fused column passes (N = 2^13 .. 2^16, up to four
+# special primes) and one that takes the unfused path (five special primes): key switching (relin,
+# single and hoisted rotations) and the modulus switch at every level, bit for bit.
+RINGS = [
+    dict(log_n=13, t=65537, n_data_primes=4, q0_max=1 << 49, data_max=1 << 42, alpha=2, special_max=1 << 49),
+    dict(log_n=14, t=65537, n_data_primes=5, q0_max=1 << 49, data_max=1 << 42, alpha=3, special_max=1 << 49),
+    dict(log_n=15, t=65537, n_data_primes=5, q0_max=1 << 49, data_max=1 << 42, alpha=4, special_max=1 << 49),
+    dict(log_n=15, t=65537, n_data_primes=5, q0_max=1 << 49, data_max=1 << 42, alpha=5, special_max=1 << 49),
+    dict(log_n=16, t=5767169, n_data_primes=3, q0_max=1 << 49, data_max=1 << 48, alpha=2, special_max=1 << 49),
+]
+
+
+@pytest.mark.parametrize("ring", RINGS, ids=lambda r: f"logn{r['log_n']}-a{r['alpha']}")
+def test_key_switch_and_modswitch_across_rings(C, ring):
+    say("ring", ring)
+    t = ring["t"]
+    ctx = C.Context(**ring)
+    ch = nt.make_chain(ring["log_n"], t, ring["n_data_primes"], ring["q0_max"], ring["data_max"], ring["alpha"],
+                       ring["special_max"])
+    assert ctx.primes() == ch.all_primes()
+    sc = B.BGV(ch)
+    seed = bytes(range(32))
+    rots = [1, 3, 77]
+    keys = ctx.keygen(seed, rots)
+    okeys = sc.keygen(seed, rotations=rots)
+    rng = np.random.default_rng(ring["log_n"] * 10 + ring["alpha"])
+    va = rng.integers(0, t, size=(2, sc.N // 2))
+    vb = rng.integers(0, t, size=(2, sc.N // 2))
+    a = ctx.encrypt_slots(keys, va, sc.L, seed, 1)
+    b = ctx.encrypt_slots(keys, vb, sc.L, seed, 2)
+    oa = sc.encrypt_slots(okeys, va, seed, 1, sc.L)
+    ob = sc.encrypt_slots(okeys, vb, seed, 2, sc.L)
+    m = ctx.op(keys, C.OP_MUL, a, b)
+    om = sc.mul(oa, ob, okeys)
+    same(ctx.export(m)[0], om)
+    assert (ctx.decrypt_slots(keys, m) == (va * vb) % t).all()
+    got = ctx.rotate_many(keys, m, [0, 1, 3, 77])
+    want = sc.rotate_hoisted(om, [0, 1, 3, 77], okeys)
+    for i, r in enumerate([0, 1, 3, 77]):
+        same(ctx.export(got)[i], want[r])
+    same(ctx.export(ctx.op(keys, C.OP_ROTATE, a, arg=3))[0], sc.rotate(oa, 3, okeys))
+    x, ox = m, om
+    while ox.level > 0:
+        x = ctx.op(keys, C.OP_MODSWITCH, x)
+        ox = sc.modswitch(ox)
+        same(ctx.export(x)[0], ox)
+    assert (ctx.decrypt_slots(keys, x) == (va * vb) % t).all()
+
+
 # ---------------------------------------------------------------- end to end
 def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
     text = synth.gen_forest_text(shape, seed)
