@@ -59,27 +59,7 @@ std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in,
     const int J = (int)idx.size();
     KSTables& T = c.kstab(l);
     DBuf top(&c, (size_t)J * np * N);
-    std::vector<const double*> src;
-    for (size_t j : idx)
-      for (int k = 0; k < np; ++k) src.push_back(in[j]->poly(k, N) + (size_t)l * N);
-    launch_gather(c, top.get(), src, 1);
-    std::vector<int2> tr;
-    for (int z = 0; z < J * np; ++z) tr.push_back(make_int2(z, l));
-    const int2* trows = rows_cached(c, "top:" + std::to_string(J * np) + ":" + std::to_string(l), tr);
     DBuf w(&c, (size_t)J * np * l * N);
-    if (bridge_supported(c, 1)) {
-      std::vector<int2> ir{make_int2(0, l)}, orr;
-      for (int i = 0; i < l; ++i) orr.push_back(make_int2(i, i));
-      launch_ntt_inv_rows(c, top.get(), trows, J * np);
-      launch_bridge(c, 1, w.get(), rows_cached(c, "msout:" + std::to_string(l), orr), l, top.get(),
-                    rows_cached(c, "msin:" + std::to_string(l), ir), 1, T.d_ms + 1, nullptr, J * np, N,
-                    (size_t)l * N);
-      launch_ntt_fwd_rows(c, w.get(), block_rows(c, J * np, l), J * np * l);
-    } else {
-      launch_ntt_inv(c, top.get(), trows, J * np);
-      launch_ms_prep(c, w.get(), top.get(), J * np, l, T.d_ms);
-      launch_ntt_fwd(c, w.get(), block_rows(c, J * np, l), J * np * l);
-    }
     auto outs = alloc_batch(c, J, l - 1, np);
     std::vector<double*> po;
     std::vector<const double*> pi, pa;
@@ -88,6 +68,29 @@ std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in,
       pi.push_back(in[idx[j]]->data());
       if (adds) pa.push_back((*adds)[idx[j]]);
       out[idx[j]] = outs[j];
+    }
+    if (bridge_supported(c, 1)) {
+      // top rows read in place by the inverse row pass; the forward row pass ends the switch
+      std::vector<int2> ir{make_int2(0, l)}, orr;
+      for (int i = 0; i < l; ++i) orr.push_back(make_int2(i, i));
+      launch_ntt_inv_rows_gather(c, top.get(), pi, np, (size_t)(l + 1) * N, (size_t)l * N, l);
+      launch_bridge(c, 1, w.get(), rows_cached(c, "msout:" + std::to_string(l), orr), l, top.get(),
+                    rows_cached(c, "msin:" + std::to_string(l), ir), 1, T.d_ms + 1, nullptr, J * np, N,
+                    (size_t)l * N);
+      launch_ntt_fwd_rows_ms_finish(c, po, pi, w.get(), np, l, T.d_ms, adds ? &pa : nullptr, add_np);
+      continue;
+    }
+    {
+      std::vector<const double*> src;
+      for (size_t j : idx)
+        for (int k = 0; k < np; ++k) src.push_back(in[j]->poly(k, N) + (size_t)l * N);
+      launch_gather(c, top.get(), src, 1);
+      std::vector<int2> tr;
+      for (int z = 0; z < J * np; ++z) tr.push_back(make_int2(z, l));
+      const int2* trows = rows_cached(c, "top:" + std::to_string(J * np) + ":" + std::to_string(l), tr);
+      launch_ntt_inv(c, top.get(), trows, J * np);
+      launch_ms_prep(c, w.get(), top.get(), J * np, l, T.d_ms);
+      launch_ntt_fwd(c, w.get(), block_rows(c, J * np, l), J * np * l);
     }
     launch_ms_finish_multi(c, po, pi, w.get(), np, l, T.d_ms, adds ? &pa : nullptr, add_np);
   }
@@ -127,13 +130,13 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   KSTables& T = c.kstab(level);
   // ModUp of every input: coefficient form, base conversion per digit, transform of the new rows
   DBuf cf(&c, (size_t)I * nl * N);
-  launch_gather(c, cf.get(), inputs, nl);
   DBuf ext(&c, (size_t)I * D * nE * N);
   const bool fused = bridge_supported(c, c.alpha);
+  if (!fused) launch_gather(c, cf.get(), inputs, nl);
   if (fused) {
-    // inverse row pass, then per digit the fused column passes with the base conversion, then the
-    // forward row pass of every new row
-    launch_ntt_inv_rows(c, cf.get(), block_rows(c, I, nl), I * nl);
+    // inverse row pass read straight from the inputs, then per digit the fused column passes with the
+    // base conversion, then the forward row pass of every new row
+    launch_ntt_inv_rows_gather(c, cf.get(), inputs, nl, N, 0, -1);
     for (int j = 0; j < D; ++j) {
       auto& dg = T.digits[j];
       launch_bridge(c, 0, ext.get(), dg.d_out_rows, (int)dg.targets.size(), cf.get(), dg.d_in_rows, dg.count,
@@ -195,17 +198,6 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   std::vector<int2> inr, outr;
   for (int s = 0; s < c.alpha; ++s) inr.push_back(make_int2(nl + s, c.L + 1 + s));
   for (int i = 0; i < nl; ++i) outr.push_back(make_int2(i, i));
-  if (fused) {
-    launch_bridge(c, 0, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
-                  rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
-                  (size_t)nE * N, (size_t)nl * N);
-    launch_ntt_fwd_rows(c, zh.get(), block_rows(c, 2 * R, nl), 2 * R * nl);
-  } else {
-    launch_bconv(c, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
-                 rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
-                 (size_t)nE * N, (size_t)nl * N);
-    launch_ntt_fwd(c, zh.get(), block_rows(c, 2 * R, nl), 2 * R * nl);
-  }
   std::vector<double*> outs;
   std::vector<const double*> adds;
   std::vector<uint64_t> gal;
@@ -213,6 +205,19 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
     outs.push_back(rq.out);
     adds.push_back(rq.add);
     gal.push_back(rq.g);
+  }
+  if (fused) {
+    launch_bridge(c, 0, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
+                  rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
+                  (size_t)nE * N, (size_t)nl * N);
+    launch_ntt_fwd_rows_md_finish(c, outs, adds, gal, acc.get(), zh.get(), nE, nl, T.d_md_pinv, T.d_md_tpinv,
+                                  add_mode);
+    return;
+  } else {
+    launch_bconv(c, zh.get(), rows_cached(c, "mdout:" + std::to_string(level), outr), nl, acc.get(),
+                 rows_cached(c, "mdin:" + std::to_string(level), inr), c.alpha, T.d_md_mult, T.d_md_mat, 2 * R,
+                 (size_t)nE * N, (size_t)nl * N);
+    launch_ntt_fwd(c, zh.get(), block_rows(c, 2 * R, nl), 2 * R * nl);
   }
   launch_md_finish2(c, outs, adds, gal, acc.get(), zh.get(), nE, nl, T.d_md_pinv, T.d_md_tpinv, add_mode);
 }

@@ -205,6 +205,18 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows);
 bool bridge_supported(const Context& c, int n_in);
 void launch_ntt_inv_rows(Context& c, double* base, const int2* rows, int nrows);
 void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows);
+// inverse row pass reading row r of job j from src[j] + r * src_stride + src_off (r < rpj), writing the
+// jobs' rows contiguously to dst; prime r, or prime_fixed when >= 0
+void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const double*>& src, int rpj,
+                                size_t src_stride, size_t src_off, int prime_fixed);
+// forward row pass of the ModDown rows w fused with the ModDown finish (as launch_md_finish2)
+void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
+                                   const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE,
+                                   int nl, const double* pinv, const double* tpinv, int add_mode);
+// forward row pass of the modulus-switch rows w fused with the switch's finish (as launch_ms_finish_multi)
+void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
+                                   const double* w, int np, int level, const double* tab,
+                                   const std::vector<const double*>* add, int add_np);
 // mode 0: fast base conversion (as launch_bconv); mode 1: modulus-switch lift of one row (mult = t^-1)
 void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
                    const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,

@@ -61,6 +61,16 @@ __device__ __forceinline__ double reduce_sym(double x, double q, double qinv) {
 }
 __device__ __forceinline__ double canon(double x, double q) { return x < 0.0 ? x + q : x; }
 
+// ------------------------------------------------------------------ automorphism (evaluation domain)
+// Slot k holds a(psi^e) with e = 2 bitrev(k) + 1.  sigma_g(a)(psi^e) = a(psi^(g e)), so the
+// output slot k reads the input slot holding exponent g e mod 2N.
+__device__ __forceinline__ uint32_t auto_src(uint32_t k, uint64_t g, int logN) {
+  uint32_t e = 2 * (__builtin_bitreverse32(k) >> (32 - logN)) + 1;
+  uint64_t ge = (g * e) & ((2ULL << logN) - 1);
+  uint32_t idx = (uint32_t)((ge - 1) >> 1);
+  return __builtin_bitreverse32(idx) >> (32 - logN);
+}
+
 // ------------------------------------------------------------------ NTT
 // Forward transform: Cooley-Tukey butterflies, natural-order input,
 // bit-reversed output.  Stage s (0-based, m = 2^s) pairs j and j + t with
@@ -395,6 +405,82 @@ __global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ ba
 // four radix-8 rounds (distances 2048/1024/512, 256/128/64, 32/16/8, 4/2/1) with three LDS exchanges.
 constexpr int kLdsTile4 = 4096 + 4096 / 16;
 
+// One 4096-element tile of the row pass, 512 threads x 8 registers, four radix-8 rounds with LDS
+// exchanges between them and one more so that global memory is always touched at t + 512 k (each
+// load or store instruction covers 512 consecutive bytes per wave).  Both directions read src[t + 512 k]
+// of the tile and leave the values of tile positions t + 512 k in x[k] (signed, not reduced).  gb0 is the
+// tile's first index in the row (twiddle groups).
+__device__ __forceinline__ void row4_fwd_tile(const double* __restrict__ src, size_t gb0, int S1, const DevPrime& pr,
+                                              double* sh, double x[8]) {
+  const int t = threadIdx.x;
+  const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
+  const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = src[jA + 512 * k];
+  radix8_ct(x, gb0 + jA, 512, mA, pr);
+  red8(x, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
+  radix8_ct(x, gb0 + jB, 64, mB, pr);
+  red8(x, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
+  radix8_ct(x, gb0 + jC, 8, mC, pr);
+  red8(x, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
+  radix8_ct(x, gb0 + jD, 1, mD, pr);
+  // each thread overwrites only the LDS words it just read
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 512 * k)];
+}
+
+__device__ __forceinline__ void row4_inv_tile(const double* __restrict__ src, size_t gb0, int S1, const DevPrime& pr,
+                                              double* sh, double x[8]) {
+  const int t = threadIdx.x;
+  const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
+  const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = src[jA + 512 * k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
+  radix8_gs(x, gb0 + jD, 1, mD, pr);
+  red8(x, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
+  radix8_gs(x, gb0 + jC, 8, mC, pr);
+  red8(x, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
+  radix8_gs(x, gb0 + jB, 64, mB, pr);
+  red8(x, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 512 * k)];
+  radix8_gs(x, gb0 + jA, 512, mA, pr);
+}
+
 template <bool kInverse>
 __global__ __launch_bounds__(512) void ntt_rowreg4_kernel(double* __restrict__ base, const int2* __restrict__ rows,
                                                          const DevPrime* __restrict__ P, int logN, int S1, int scale) {
@@ -402,71 +488,94 @@ __global__ __launch_bounds__(512) void ntt_rowreg4_kernel(double* __restrict__ b
   const int2 row = rows[blockIdx.y];
   const DevPrime pr = P[row.y];
   const size_t N = (size_t)1 << logN;
-  double* a = base + (size_t)row.x * N;
-  const int t = threadIdx.x;
   const size_t t0 = (size_t)blockIdx.x * 4096;
-  const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
+  double* a = base + (size_t)row.x * N + t0;
+  const int t = threadIdx.x;
   double x[8];
-  const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
   if (!kInverse) {
+    row4_fwd_tile(a, t0, S1, pr, sh, x);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = a[t0 + jA + 512 * k];
-    radix8_ct(x, t0 + jA, 512, mA, pr);
-    red8(x, pr);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = x[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
-    radix8_ct(x, t0 + jB, 64, mB, pr);
-    red8(x, pr);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
-    radix8_ct(x, t0 + jC, 8, mC, pr);
-    red8(x, pr);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
-    radix8_ct(x, t0 + jD, 1, mD, pr);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a[t0 + jD + k] = canon(reduce_sym(x[k], pr.q, pr.qinv), pr.q);
+    for (int k = 0; k < 8; ++k) a[t + 512 * k] = canon(reduce_sym(x[k], pr.q, pr.qinv), pr.q);
   } else {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = a[t0 + jD + k];
-    radix8_gs(x, t0 + jD, 1, mD, pr);
-    red8(x, pr);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
-    radix8_gs(x, t0 + jC, 8, mC, pr);
-    red8(x, pr);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
-    radix8_gs(x, t0 + jB, 64, mB, pr);
-    red8(x, pr);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 512 * k)];
-    radix8_gs(x, t0 + jA, 512, mA, pr);
+    row4_inv_tile(a, t0, S1, pr, sh, x);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       double v = x[k];
       if (scale) v = mul_lazy(v, pr.ninv, pr.q, pr.qinv);
       v = reduce_sym(v, pr.q, pr.qinv);
-      a[t0 + jA + 512 * k] = scale ? canon(v, pr.q) : v;
+      a[t + 512 * k] = scale ? canon(v, pr.q) : v;
     }
+  }
+}
+
+// Inverse row pass reading straight from ciphertexts (no gather copy): row r of the launch is row
+// r % rpj of job r / rpj, read from src.p[job] + (r % rpj) * src_stride + src_off and written to
+// dst + r * N; its prime is prime_fixed, or r % rpj when prime_fixed < 0.
+__global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restrict__ dst, Pack src, int rpj,
+                                                               size_t src_stride, size_t src_off, int prime_fixed,
+                                                               const DevPrime* __restrict__ P, int logN, int S1) {
+  __shared__ double sh[kLdsTile4];
+  const int r = blockIdx.y;
+  const int j = r / rpj, sub = r % rpj;
+  const DevPrime pr = P[prime_fixed >= 0 ? prime_fixed : sub];
+  const size_t N = (size_t)1 << logN;
+  const size_t t0 = (size_t)blockIdx.x * 4096;
+  const double* a = src.p[j] + (size_t)sub * src_stride + src_off + t0;
+  double x[8];
+  row4_inv_tile(a, t0, S1, pr, sh, x);
+  double* o = dst + (size_t)r * N + t0;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) o[t + 512 * k] = reduce_sym(x[k], pr.q, pr.qinv);
+}
+
+// Forward row pass fused with the end of a ModDown (kMode 1) or of a modulus switch (kMode 2).
+//   kMode 1: block (tile, i, z = job * 2 + k) transforms w row z * nl + i and writes
+//            out_job[k][i] = acc[z][i] P^-1 - w t P^-1  (+ add_job[k][i] when add_mode 1,
+//            + add_job[0][i] at the automorphism's source index when add_mode 2 and k = 0)
+//   kMode 2: block (tile, i, z = job * np + k) transforms w row z * l + i and writes
+//            out_job[k][i] = in_job[k][i] q_l^-1 - w t q_l^-1  (+ add_job[k][i] for k < add_np)
+// mul/tmul are P^-1 and t P^-1 per limb (kMode 1) or the modulus-switch table (q_l^-1 at 2 + 2 i,
+// t q_l^-1 at 3 + 2 i).  Outputs are canonical.
+template <int kMode>
+__global__ __launch_bounds__(512) void ntt_rowfwd_finish_kernel(MPack out, Pack in, Pack add, GPack gal,
+                                                               const double* __restrict__ acc,
+                                                               const double* __restrict__ w, int nE, int nl,
+                                                               int np, int add_mode, int add_np,
+                                                               const double* __restrict__ mul,
+                                                               const double* __restrict__ tmul,
+                                                               const DevPrime* __restrict__ P, int logN, int S1) {
+  __shared__ double sh[kLdsTile4];
+  const int i = blockIdx.y, z = blockIdx.z;
+  const DevPrime pr = P[i];
+  const size_t N = (size_t)1 << logN;
+  const size_t t0 = (size_t)blockIdx.x * 4096;
+  const int t = threadIdx.x;
+  double x[8];
+  row4_fwd_tile(w + ((size_t)z * nl + i) * N + t0, t0, S1, pr, sh, x);
+  const int j = kMode == 1 ? (z >> 1) : z / np, k = kMode == 1 ? (z & 1) : z % np;
+  const double m1 = kMode == 1 ? mul[i] : mul[2 + 2 * i];
+  const double m2 = kMode == 1 ? tmul[i] : mul[3 + 2 * i];
+  // kMode 2 writes l = nl limbs per poly below an input with nl + 1
+  const size_t orow = ((size_t)k * nl + i) * N;
+  const double* yrow = kMode == 1 ? acc + ((size_t)z * nE + i) * N : in.p[j] + ((size_t)k * (nl + 1) + i) * N;
+  const uint64_t g = kMode == 1 ? gal.g[j] : 1;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const size_t c = t0 + t + 512 * kk;
+    const double wv = reduce_sym(x[kk], pr.q, pr.qinv);
+    double v = mul_lazy(yrow[c], m1, pr.q, pr.qinv) - mul_lazy(wv, m2, pr.q, pr.qinv);
+    v = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
+    if (kMode == 1) {
+      if (add_mode == 1) v = mod_add(v, add.p[j][orow + c], pr.q);
+      if (add_mode == 2 && k == 0) {
+        const size_t src = g == 1 ? c : auto_src((uint32_t)c, g, logN);
+        v = mod_add(v, add.p[j][(size_t)i * N + src], pr.q);
+      }
+    } else if (k < add_np && add.p[j] != nullptr) {
+      v = mod_add(v, add.p[j][orow + c], pr.q);
+    }
+    out.p[j][orow + c] = v;
   }
 }
 
@@ -742,6 +851,75 @@ void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows) 
   }
 }
 
+void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const double*>& src, int rpj,
+                                size_t src_stride, size_t src_off, int prime_fixed) {
+  if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  const int per = std::max(1, std::min(kPack, kMaxGridY / std::max(1, rpj)));
+  for (size_t first = 0; first < src.size(); first += per) {
+    const int cnt = (int)std::min<size_t>(per, src.size() - first);
+    Pack pk;
+    for (int k = 0; k < cnt; ++k) pk.p[k] = src[first + k];
+    hipEvent_t ev;
+    prof_begin(c, 2, &ev);
+    hipLaunchKernelGGL(ntt_rowinv_gather_kernel, dim3((unsigned)(c.N / 4096), cnt * rpj), dim3(512), 0, c.stream,
+                       dst + first * rpj * c.N, pk, rpj, src_stride, src_off, prime_fixed, c.d_primes, (int)c.log_n,
+                       (int)c.log_n - 12);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 2, ev, (double)cnt * rpj);
+  }
+}
+
+void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
+                                   const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE,
+                                   int nl, const double* pinv, const double* tpinv, int add_mode) {
+  if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  for (size_t first = 0; first < out.size(); first += kPack) {
+    const int cnt = (int)std::min<size_t>(kPack, out.size() - first);
+    MPack po;
+    Pack pa, pin;
+    GPack pg;
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k];
+      pa.p[k] = add.empty() ? nullptr : add[first + k];
+      pg.g[k] = gal.empty() ? 1 : gal[first + k];
+      pin.p[k] = nullptr;
+    }
+    hipEvent_t ev;
+    prof_begin(c, 0, &ev);
+    hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<1>, dim3((unsigned)(c.N / 4096), nl, 2 * cnt), dim3(512), 0,
+                       c.stream, po, pin, pa, pg, acc + first * 2 * nE * c.N, w + first * 2 * nl * c.N, nE, nl, 2,
+                       add_mode, 0, pinv, tpinv, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 0, ev, 2.0 * nl * cnt);
+  }
+}
+
+void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
+                                   const double* w, int np, int level, const double* tab,
+                                   const std::vector<const double*>* add, int add_np) {
+  if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  const int per = std::max(1, std::min(kPack, kMaxGridY / np));
+  for (size_t first = 0; first < out.size(); first += per) {
+    const int cnt = (int)std::min<size_t>(per, out.size() - first);
+    MPack po;
+    Pack pi, pa;
+    GPack pg;
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k];
+      pi.p[k] = in[first + k];
+      pa.p[k] = add ? (*add)[first + k] : nullptr;
+      pg.g[k] = 1;
+    }
+    hipEvent_t ev;
+    prof_begin(c, 0, &ev);
+    hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<2>, dim3((unsigned)(c.N / 4096), level, np * cnt), dim3(512), 0,
+                       c.stream, po, pi, pa, pg, nullptr, w + first * np * level * c.N, 0, level, np, 0,
+                       add ? add_np : 0, tab, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 0, ev, (double)level * np * cnt);
+  }
+}
+
 // ------------------------------------------------------------------ elementwise
 // grid: x over coefficients (256 threads, 1 element each), y over rows
 #define EW_PROLOGUE                                          \
@@ -903,16 +1081,7 @@ void launch_add_const(Context& c, double* a, int nl, double v) {
   COPSE_HIP(hipGetLastError());
 }
 
-// ------------------------------------------------------------------ automorphism (evaluation domain)
-// Slot k holds a(psi^e) with e = 2 bitrev(k) + 1.  sigma_g(a)(psi^e) = a(psi^(g e)), so the
-// output slot k reads the input slot holding exponent g e mod 2N.
-__device__ __forceinline__ uint32_t auto_src(uint32_t k, uint64_t g, int logN) {
-  uint32_t e = 2 * (__builtin_bitreverse32(k) >> (32 - logN)) + 1;
-  uint64_t ge = (g * e) & ((2ULL << logN) - 1);
-  uint32_t idx = (uint32_t)((ge - 1) >> 1);
-  return __builtin_bitreverse32(idx) >> (32 - logN);
-}
-
+// out = sigma_g(in) on nl * npolys rows in the evaluation domain (index permutation auto_src)
 __global__ void automorphism_kernel(double* out, const double* in, uint64_t g, int logN) {
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
