@@ -136,3 +136,8 @@ def workload_inputs(w: Workload):
     text = gen_forest_text(s, w.seed_index)
     queries = gen_queries(w.n_queries, s.n_features, s.precision, 100 + w.seed_index)
     return text, queries, crypto_seed(f"COPSE-cfg-{w.seed_index}")
+
+
+# The serving mix: resident forests of the three sizes, one query per request, each request's
+# forest drawn uniformly (all three share the N = 32768, 16-bit-capable chain).
+SERVE_MIX = ("c5_serve_8x_d4", "c5_serve_32x_d6", "c5_serve_64x_d8")

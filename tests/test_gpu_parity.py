@@ -371,3 +371,32 @@ def test_workload_full_size_against_stored_oracle(C, name):
     assert h.hexdigest() == gold["sha256"]
     bits = ctx.decrypt_labels(keys, meta, res, nq)
     assert bits.tolist() == gold["labels"]
+
+
+# Full-size workloads whose oracle run is too long for a test: every decrypted label of the evaluated
+# queries against the plain forest (a property that holds at any size), in the batched launch
+# configuration the benchmark times; the decryption's noise check must pass too.
+@pytest.mark.parametrize("name,groups,batch", [("c3_batched_32x_d6", 64, 16), ("c4_encmodel_64x_d8", 2, 2)])
+def test_workload_full_size_labels(C, name, groups, batch):
+    w = synth.WORKLOADS[name]
+    text, queries, seed = synth.workload_inputs(w)
+    say("full-size labels", name, "groups", groups, "batch", batch)
+    ctx = C.Context(**w.chain)
+    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold)
+    keys = ctx.keygen(seed, C.compiled_rotations(meta))
+    evk = ctx.export_eval(keys)
+    if w.encrypted_model:
+        model = ctx.model_encode(comp, keys, encrypt=True, seed=seed)
+    else:
+        model = ctx.model_encode(comp)
+    qs = meta.queries_per_ct
+    assert groups * qs <= len(queries)
+    _, trees = F.parse_forest(text)
+    for g0 in range(0, groups, batch):
+        qsets = [queries[g * qs:(g + 1) * qs] for g in range(g0, min(groups, g0 + batch))]
+        cts = [ctx.query_encrypt(keys, meta, q, seed, group=g0 + i) for i, q in enumerate(qsets)]
+        res = ctx.evaluate_batch(model, evk, cts)
+        for q, r in zip(qsets, res):
+            bits = ctx.decrypt_labels(keys, meta, r, len(q))
+            assert (bits == np.array([F.evaluate(trees, list(x)) for x in q])).all()
+        say("groups", g0, "..", g0 + len(qsets) - 1, "ok")
