@@ -47,24 +47,30 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def measured_traffic(kernel: str, limbs_per_launch: float, N: int):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain
-    copy of known size), as bytes per limb times this run's limbs per launch;
-    None when the kernels' source changed since the counters were taken."""
+KIND_NAMES = {0: "ntt_fwd_rows", 1: "ntt_fwd_cols", 2: "ntt_inv_rows", 3: "ntt_inv_cols", 4: "ks_inner",
+              5: "bconv_colpass", 6: "elementwise", 7: "ntt_fwd_rows_moddown", 8: "ntt_fwd_rows_modswitch",
+              9: "matmul_inner", 10: "ntt_inv_rows_gather"}
+# kernel of each class (for the counter runs); class 6 is a family of small kernels and is not a roofline
+KIND_KERNELS = {0: "ntt_rowreg4_kernel<false>", 2: "ntt_rowreg4_kernel<true>", 4: "ks_inner2_kernel",
+                5: "ntt_bridge_kernel", 7: "ntt_rowfwd_finish_kernel<1>", 8: "ntt_rowfwd_finish_kernel<2>",
+                9: "mm_inner_kernel", 10: "ntt_rowinv_gather_kernel"}
+
+
+def measured_traffic(kind: str, workload: str):
+    """HBM bytes per launch of the roofline kernel from the committed counter runs
+    (profiles/hbm_bytes_<kind>_<workload>.json, written by paper_2104_09583_amd.pmc_traffic);
+    None when there is none or the kernels' source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "ntt_rowreg_c2_forest16_d5_hbm_bytes.json")
+    path = os.path.join(ROOT, "profiles", f"hbm_bytes_{kind}_{workload}.json")
     src = os.path.join(ROOT, "paper_2104_09583_amd", "csrc", "kernels.hip")
-    key = {"ntt_fwd_rows": "ntt_rowreg_kernel<false>", "ntt_inv_rows": "ntt_rowreg_kernel<true>"}.get(kernel)
-    if key is None or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         doc = json.load(f)
     with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != doc["kernels_hip_sha256"] or N != 32768:
+        if hashlib.sha256(f.read()).hexdigest() != doc["kernels_hip_sha256"]:
             return None
-    k = doc["kernels"].get(key)
-    return None if k is None else round(k["bytes_per_limb"] * limbs_per_launch)
+    return doc["bytes_per_dispatch"]
 
 
 def cpu_baseline(w, text, queries, seed, budget_s: float = 25.0):
@@ -264,6 +270,8 @@ def main():
     ap.add_argument("--plain", action="store_true",
                     help="the unbatched path: each group alone, one homomorphic operation per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="evaluate eagerly instead of replaying the captured evaluation (HIP graph)")
     ap.add_argument("--n1-r", type=int, default=0, help="baby steps of the reshuffle product (0: compiler default)")
     ap.add_argument("--n1-l", type=int, default=0, help="baby steps of the level products (0: compiler default)")
     ap.add_argument("--requests", type=int, default=240, help="serving mix: requests per offered rate")
@@ -313,12 +321,21 @@ def main():
         groups.append(ctx.query_encrypt(keys, meta, qi, seed, group=g))
     queries_per_step = nq_group * args.batch
 
-    def step():
+    ex = None
+    if not args.plain and not args.no_graph:
+        t2 = time.perf_counter()
+        ex = ctx.exec_create(model, evk, len(groups))
+        log(f"captured evaluation of {len(groups)} group(s) in {time.perf_counter() - t2:.1f}s")
+
+    def step_eager():
         if args.plain:
             return [ctx.evaluate_plain(model, evk, g) for g in groups]
         if args.batch == 1:
             return [ctx.evaluate(model, evk, groups[0])]
         return ctx.evaluate_batch(model, evk, groups)
+
+    def step():
+        return ex.run(groups) if ex is not None else step_eager()
 
     # the first warmup result is kept for the label check of the CPU-baseline leg
     res = step()
@@ -336,10 +353,11 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    # per-kernel timings need one event pair per launch: this loop runs the same schedule eagerly
     for _ in range(args.steps):
         with torch.cuda.stream(stream):
             ev0.record(stream)
-        step()
+        step_eager()
         with torch.cuda.stream(stream):
             ev1.record(stream)
         ev1.synchronize()
@@ -364,32 +382,26 @@ def main():
     # reference copy of known size for the byte counters of a separate --pmc run
     ctx.calib_copy(256 << 20)
 
-    # roofline of the dominant kernel class (by total time)
-    names = {0: "ntt_fwd_rows", 1: "ntt_fwd_cols", 2: "ntt_inv_rows", 3: "ntt_inv_cols", 4: "ks_inner",
-             5: "bconv", 6: "elementwise"}
-    dom = max(range(C.PROF_KINDS), key=lambda k: prof[k]["ms"])
-    N = 1 << w.log_n
+    # roofline of the dominant kernel (the class with the largest total time among the single-kernel
+    # classes): algorithmic bytes per launch / average launch time, both from the profiled loop
+    cands = [k for k in KIND_KERNELS if prof[k]["launches"] > 0]
+    dom = max(cands, key=lambda k: prof[k]["ms"])
     p = prof[dom]
-    # algorithmic bytes per limb row: a transform pass reads and writes each limb once (2 N 8 bytes);
-    # the key-switch inner product reads D digit rows and 2 D key rows and writes 2 rows per ext limb
-    if dom == 4:
-        D = math.ceil(ch["n_data_primes"] / ch["alpha"])
-        bytes_per_limb = (3 * D + 2) * N * 8
-    else:
-        bytes_per_limb = 2 * N * 8
     avg_ms = p["ms"] / max(1, p["launches"])
-    limbs_per_launch = p["limbs"] / max(1, p["launches"])
-    achieved = bytes_per_limb * limbs_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
+    bytes_per_launch = p["bytes"] / max(1, p["launches"])
+    achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(names[dom], limbs_per_launch, N),
-                "kernel": names[dom], "avg_launch_ms": round(avg_ms, 5),
-                "limbs_per_launch": round(limbs_per_launch, 2), "algorithmic_bytes_per_limb": bytes_per_limb,
+                "traffic": measured_traffic(KIND_NAMES[dom], w.name),
+                "kernel": KIND_KERNELS[dom], "class": KIND_NAMES[dom], "avg_launch_ms": round(avg_ms, 5),
+                "algorithmic_bytes_per_launch": round(bytes_per_launch),
                 "share_of_step": round(p["ms"] / sum(per_step), 3)}
-    kernels = {names[k]: {"launches_per_step": prof[k]["launches"] / args.steps,
-                          "ms_per_step": round(prof[k]["ms"] / args.steps, 3),
-                          "avg_launch_us": round(1000 * prof[k]["ms"] / max(1, prof[k]["launches"]), 2)}
-               for k in range(C.PROF_KINDS)}
+    kernels = {KIND_NAMES[k]: {"launches_per_step": prof[k]["launches"] / args.steps,
+                               "ms_per_step": round(prof[k]["ms"] / args.steps, 3),
+                               "avg_launch_us": round(1000 * prof[k]["ms"] / max(1, prof[k]["launches"]), 2),
+                               "algorithmic_bytes_per_launch": round(prof[k]["bytes"] / max(1, prof[k]["launches"])),
+                               "achieved_GBps": round(prof[k]["bytes"] / max(1e-9, prof[k]["ms"]) / 1e6, 1)}
+               for k in range(C.PROF_KINDS) if prof[k]["launches"] > 0}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -417,8 +429,9 @@ def main():
                    "features": w.shape.n_features, "precision": w.shape.precision, "classes": w.shape.n_classes,
                    "queries_per_step": queries_per_step, "query_groups_per_step": args.batch,
                    "path": "plain (one group per call, one operation per launch)" if args.plain else
-                           ("batched" if args.batch > 1 else "single group"),
-                   "N": N, "data_primes": ch["n_data_primes"], "special_primes": ch["alpha"],
+                           (("batched" if args.batch > 1 else "single group") +
+                            (", eager" if args.no_graph else ", captured graph")),
+                   "N": 1 << w.log_n, "data_primes": ch["n_data_primes"], "special_primes": ch["alpha"],
                    "model": "plaintext" if not w.encrypted_model else "encrypted",
                    "b": meta.b, "m": meta.m, "q": meta.q, "d": meta.d, "W": meta.block_w,
                    "n1_R": meta.n1_R, "n1_L": meta.n1_L},

@@ -234,6 +234,33 @@ int copse_evaluate_plain(copse_ctx* ctx, const copse_model* model, const copse_k
 int copse_evaluate_batch(copse_ctx* ctx, const copse_model* model, const copse_keys* keys,
                          const copse_cts* const* queries, size_t n_groups, copse_cts** results);
 
+/* ---------------------------------------------------------------- captured evaluation
+ * The batched evaluation (Algorithm 1, Section 4.3) of one model over a fixed
+ * number of query groups, recorded once as a HIP graph on the context's stream
+ * and replayed by each run, so that the hundreds of launches of one
+ * evaluation cost the host one graph launch.
+ *
+ * copse_exec_create: runs the schedule once eagerly (on buffers of its own)
+ *   and once under stream capture; the model and the evaluation keys must
+ *   stay alive while the executor lives.  The executor owns device memory for
+ *   the inputs, every temporary and the outputs of one evaluation (about one
+ *   batched evaluation's working set) until it is destroyed.  Synchronizes the
+ *   context's stream.  Errors: EINVAL (n_groups 0 or above 4096), ENOMEM,
+ *   EKEY, EDEVICE.
+ * copse_exec_run: queries[i] (n_groups of them, each p fresh encryptions at
+ *   the top level as from copse_query_encrypt) are copied in, the graph is
+ *   launched and results[i] receives a new ciphertext (level 0) owned by the
+ *   caller, bit-identical to copse_evaluate_batch on the same queries.  Work
+ *   is enqueued on the context's stream (no synchronization); runs of one
+ *   executor are ordered by that stream.  Errors: EINVAL (group count, plane
+ *   count or level differs from the capture).
+ */
+typedef struct copse_exec copse_exec;
+int copse_exec_create(copse_ctx* ctx, const copse_model* model, const copse_keys* eval_keys, size_t n_groups,
+                      copse_exec** out);
+int copse_exec_run(copse_exec* exec, const copse_cts* const* queries, size_t n_groups, copse_cts** results);
+void copse_exec_destroy(copse_exec* exec);
+
 /* ---------------------------------------------------------------- decrypt */
 /*
  * Data owner: decrypts a level-0 result, checks the noise (the centered
@@ -279,14 +306,20 @@ int copse_poly_mul(copse_ctx* ctx, int prime, const uint64_t* a, const uint64_t*
 
 /* ---------------------------------------------------------------- profiling */
 /* When on, the library brackets each launch of the named kernel class with
- * HIP events on the launching stream and accumulates the durations and the
- * number of limb rows processed.  kind: 0 = forward NTT row pass,
- * 1 = forward NTT column pass, 2 = inverse NTT row pass, 3 = inverse NTT
- * column pass, 4 = key-switch inner product, 5 = base conversion,
- * 6 = elementwise.  reset clears the counters. */
+ * HIP events on the launching stream and accumulates the launch count, the
+ * durations and the algorithmic bytes (every input and output row of the
+ * operation read or written once; key rows counted per key-switch job;
+ * twiddle tables not counted).  kind: 0 = forward NTT row pass, 1 = forward
+ * NTT column pass (unfused path), 2 = inverse NTT row pass, 3 = inverse NTT
+ * column pass (unfused path), 4 = key-switch inner product, 5 = base
+ * conversion (fused with the column passes where available), 6 = other
+ * elementwise kernels, 7 = forward row pass with the ModDown finish,
+ * 8 = forward row pass with the modulus-switch finish, 9 = MatMul inner sums,
+ * 10 = inverse row pass reading ciphertext rows in place.  reset clears the
+ * counters. */
 int copse_profile_enable(copse_ctx* ctx, int on);
 int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
-                       double* limbs, int reset);
+                       double* bytes, int reset);
 
 /* ---------------------------------------------------------------- serving */
 /*

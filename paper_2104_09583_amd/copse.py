@@ -28,8 +28,9 @@ COPSE_ETIMEOUT = -7
 OP_ADD, OP_SUB, OP_TENSOR, OP_RELIN, OP_MODSWITCH, OP_MUL, OP_ROTATE, OP_MUL_PLAIN, OP_ADD_PLAIN = range(1, 10)
 
 (PROF_NTT_FWD_ROWS, PROF_NTT_FWD_COLS, PROF_NTT_INV_ROWS, PROF_NTT_INV_COLS, PROF_KS_INNER, PROF_BCONV,
- PROF_ELEMENTWISE) = range(7)
-PROF_KINDS = 7
+ PROF_ELEMENTWISE, PROF_NTT_FWD_ROWS_MODDOWN, PROF_NTT_FWD_ROWS_MODSWITCH, PROF_MATMUL_INNER,
+ PROF_NTT_INV_ROWS_GATHER) = range(11)
+PROF_KINDS = 11
 
 
 class CopseError(RuntimeError):
@@ -92,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "copse_evaluate": [P, P, P, P, PP],
         "copse_evaluate_batch": [P, P, P, PP, sz, PP],
         "copse_evaluate_plain": [P, P, P, P, PP],
+        "copse_exec_create": [P, P, P, sz, PP],
+        "copse_exec_run": [P, PP, sz, PP],
         "copse_decrypt_labels": [P, P, ctypes.POINTER(Meta), P, sz, u8p, sz],
         "copse_encrypt_slots": [P, P, u64p, i32, u8p, u64, PP],
         "copse_decrypt_slots": [P, P, P, sz, u64p],
@@ -118,7 +121,7 @@ def lib() -> ctypes.CDLL:
         fn.argtypes = args
         fn.restype = ctypes.c_int
     for name in ("copse_ctx_destroy", "copse_compiled_destroy", "copse_keys_destroy", "copse_model_destroy",
-                 "copse_cts_destroy", "copse_server_destroy"):
+                 "copse_cts_destroy", "copse_server_destroy", "copse_exec_destroy"):
         getattr(L, name).argtypes = [P]
         getattr(L, name).restype = None
     L.copse_ctx_stream.argtypes = [P]
@@ -285,6 +288,14 @@ class Context(_Handle):
         check(lib().copse_evaluate_batch(self.ptr, model.ptr, keys.ptr, arr, n, out))
         return [Cts(ctypes.c_void_p(out[i]), self) for i in range(n)]
 
+    def exec_create(self, model: Model, keys: Keys, n_groups: int) -> "Exec":
+        h = ctypes.c_void_p()
+        check(lib().copse_exec_create(self.ptr, model.ptr, keys.ptr, n_groups, ctypes.byref(h)))
+        ex = Exec(h, self)
+        ex._keep = (model, keys)
+        ex.n_groups = n_groups
+        return ex
+
     def decrypt_labels(self, keys: Keys, meta: Meta, result: Cts, n_queries: int) -> np.ndarray:
         bits = np.zeros(n_queries * meta.m, dtype=np.uint8)
         check(lib().copse_decrypt_labels(self.ptr, keys.ptr, ctypes.byref(meta), result.ptr, n_queries,
@@ -363,10 +374,10 @@ class Context(_Handle):
     def profile_read(self, kind: int, reset: bool = False) -> dict:
         n = ctypes.c_uint64()
         ms = ctypes.c_double()
-        limbs = ctypes.c_double()
-        check(lib().copse_profile_read(self.ptr, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(limbs),
+        nbytes = ctypes.c_double()
+        check(lib().copse_profile_read(self.ptr, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(nbytes),
                                        int(reset)))
-        return dict(launches=n.value, ms=ms.value, limbs=limbs.value)
+        return dict(launches=n.value, ms=ms.value, bytes=nbytes.value)
 
 
 def forest_compile(text: str, n_features: int, precision: int, log_n: int, fold: bool = False,
@@ -415,6 +426,18 @@ def encode(log_n: int, slots: np.ndarray, t: int = 65537) -> np.ndarray:
     out = np.zeros(1 << log_n, dtype=np.int64)
     check(lib().copse_test_encode(log_n, t, _arr(s, ctypes.c_uint64), _arr(out, ctypes.c_int64)))
     return out
+
+
+class Exec(_Handle):
+    """Captured evaluation of one model over a fixed number of query groups (copse_exec_*)."""
+    _destroy = "copse_exec_destroy"
+
+    def run(self, queries: Sequence[Cts]) -> List[Cts]:
+        n = len(queries)
+        arr = (ctypes.c_void_p * n)(*[q.ptr.value for q in queries])
+        out = (ctypes.c_void_p * max(1, n))()
+        check(lib().copse_exec_run(self.ptr, arr, n, out))
+        return [Cts(ctypes.c_void_p(out[i]), self.owner) for i in range(n)]
 
 
 class Server(_Handle):

@@ -42,7 +42,7 @@ void prof_begin(Context& c, int kind, hipEvent_t* ev) {
   *ev = e;
   (void)kind;
 }
-void prof_end(Context& c, int kind, hipEvent_t ev, double limbs) {
+void prof_end(Context& c, int kind, hipEvent_t ev, double bytes) {
   if (!c.profiling || !ev) return;
   hipEvent_t e;
   if (!c.event_cache.empty()) { e = c.event_cache.back(); c.event_cache.pop_back(); }
@@ -50,7 +50,7 @@ void prof_end(Context& c, int kind, hipEvent_t ev, double limbs) {
   COPSE_HIP(hipEventRecord(e, c.stream));
   c.pending[kind].push_back({ev, e});
   c.prof[kind].launches += 1;
-  c.prof[kind].limbs += limbs;
+  c.prof[kind].bytes += bytes;
   if (c.pending[kind].size() > 4096) prof_collect(c);
 }
 void prof_collect(Context& c) {

@@ -324,6 +324,35 @@ int copse_evaluate(copse_ctx* ctx, const copse_model* model, const copse_keys* k
   });
 }
 
+int copse_exec_create(copse_ctx* ctx, const copse_model* model, const copse_keys* eval_keys, size_t n_groups,
+                      copse_exec** out) {
+  return guarded([&] {
+    NEED(ctx && model && eval_keys && out && n_groups > 0);
+    *out = nullptr;
+    *out = exec_create(*ctx->c, *model->m, *eval_keys->k, (int)std::min<size_t>(n_groups, 1u << 20)).release();
+  });
+}
+
+int copse_exec_run(copse_exec* exec, const copse_cts* const* queries, size_t n_groups, copse_cts** results) {
+  return guarded([&] {
+    NEED(exec && queries && results);
+    std::vector<std::vector<const Ct*>> groups;
+    for (size_t g = 0; g < n_groups; ++g) {
+      NEED(queries[g]);
+      groups.emplace_back();
+      for (auto& p : queries[g]->v) groups.back().push_back(p.get());
+    }
+    auto r = exec_run(*exec, groups);
+    for (size_t g = 0; g < r.size(); ++g) {
+      auto c = std::make_unique<copse_cts>();
+      c->v.push_back(std::move(r[g]));
+      results[g] = c.release();
+    }
+  });
+}
+
+void copse_exec_destroy(copse_exec* exec) { delete exec; }
+
 int copse_evaluate_plain(copse_ctx* ctx, const copse_model* model, const copse_keys* keys, const copse_cts* query,
                          copse_cts** result) {
   return guarded([&] {
@@ -599,14 +628,14 @@ int copse_profile_enable(copse_ctx* ctx, int on) {
   });
 }
 
-int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms, double* limbs, int reset) {
+int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms, double* bytes, int reset) {
   return guarded([&] {
     NEED(ctx && kind >= 0 && kind < kProfKinds);
     Context& c = *ctx->c;
     prof_collect(c);
     if (launches) *launches = c.prof[kind].launches;
     if (total_ms) *total_ms = c.prof[kind].ms;
-    if (limbs) *limbs = c.prof[kind].limbs;
+    if (bytes) *bytes = c.prof[kind].bytes;
     if (reset) c.prof[kind] = ProfSlot();
   });
 }

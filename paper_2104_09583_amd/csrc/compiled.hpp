@@ -106,3 +106,20 @@ struct copse_model {
 struct copse_cts {
   std::vector<copse::CtPtr> v;
 };
+// captured evaluation (graph.cpp)
+struct copse_exec {
+  copse::Context* c = nullptr;
+  const copse::Model* model = nullptr;
+  const copse::Keys* keys = nullptr;
+  int groups = 0;
+  std::shared_ptr<copse::Pool> arena;
+  std::vector<std::vector<copse::CtPtr>> inputs;   // [group][plane] at the top level
+  std::vector<copse::CtPtr> outputs;               // the captured results (level 0)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~copse_exec();
+};
+namespace copse {
+std::unique_ptr<copse_exec> exec_create(Context& c, const Model& model, const Keys& keys, int n_groups);
+std::vector<CtPtr> exec_run(copse_exec& e, const std::vector<std::vector<const Ct*>>& queries);
+}  // namespace copse

@@ -300,7 +300,7 @@ static void b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*
     for (int b = 0; b < G; ++b) {
       double* dst = B + ((size_t)u * G + b) * ps;
       if (g == 1) {
-        COPSE_HIP(hipMemcpyAsync(dst, v[b]->data(), ps * 8, hipMemcpyDeviceToDevice, c.stream));
+        launch_copy(c, dst, v[b]->data(), ps);
         continue;
       }
       auto it = k.rot.find(g);
@@ -333,7 +333,10 @@ static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, co
     ngs += (int)P->groups.size();
   }
   DBuf inner(&c, (size_t)ngs * G * (enc ? ps3 : ps2));
-  launch_mm_inner(c, inner.get(), B, tab, n_u, ngs, G, nl, (size_t)G * ps2, ps2, enc);
+  size_t nnz = 0;
+  for (auto* P : plans)
+    for (auto* d : P->tab) nnz += d != nullptr;
+  launch_mm_inner(c, inner.get(), B, tab, n_u, ngs, G, nl, (size_t)G * ps2, ps2, enc, nnz);
   std::vector<SCt> in2;   // encrypted model: per (group, b) relinearized inner sums
   if (enc) {
     std::vector<SCt> t3;
@@ -359,7 +362,7 @@ static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, co
         double* dst = rb.get() + (size_t)z * ps2;
         if (g == 0) {
           // group 0 needs no rotation: the plaintext-model sum reads it in place
-          if (enc) COPSE_HIP(hipMemcpyAsync(dst, ptr2(z), ps2 * 8, hipMemcpyDeviceToDevice, c.stream));
+          if (enc) launch_copy(c, dst, ptr2(z), ps2);
           continue;
         }
         const uint64_t gal = galois_of(c, (int64_t)g * P.n1);

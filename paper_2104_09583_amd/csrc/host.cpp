@@ -263,7 +263,7 @@ void* Pool::alloc(size_t bytes) {
     it->second.pop_back();
   } else {
     hipError_t e = hipMalloc(&p, sz);
-    if (e != hipSuccess) {
+    if (e != hipSuccess && !keep_cached_) {
       // release cached blocks and retry once
       for (auto& kv : cache_) {
         for (void* q : kv.second) { (void)hipFree(q); held_ -= kv.first; }
@@ -271,10 +271,10 @@ void* Pool::alloc(size_t bytes) {
       }
       (void)hipGetLastError();
       e = hipMalloc(&p, sz);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(COPSE_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
-      }
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(COPSE_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
     }
     held_ += sz;
   }
@@ -293,6 +293,7 @@ void Pool::free(void* p) {
 
 void Pool::trim() {
   std::lock_guard<std::mutex> lk(mu_);
+  if (keep_cached_) return;
   for (auto& kv : cache_) {
     for (void* q : kv.second) { (void)hipFree(q); held_ -= kv.first; }
     kv.second.clear();

@@ -82,7 +82,8 @@ using RowDesc = int2;
 // ------------------------------------------------------------------ memory pool
 class Pool {
  public:
-  explicit Pool(int device) : device_(device) {}
+  // keep_cached: never release cached blocks (a captured graph may still address them)
+  explicit Pool(int device, bool keep_cached = false) : device_(device), keep_cached_(keep_cached) {}
   ~Pool();
   void* alloc(size_t bytes);
   void free(void* p);
@@ -91,6 +92,7 @@ class Pool {
 
  private:
   int device_;
+  bool keep_cached_;
   std::map<size_t, std::vector<void*>> cache_;
   std::map<void*, size_t> live_;
   size_t held_ = 0;
@@ -137,11 +139,11 @@ using CtPtr = std::unique_ptr<Ct>;
 // Profiling counters per kernel class: 0 forward NTT (row pass), 1 forward NTT (column pass),
 // 2 inverse NTT (row pass), 3 inverse NTT (column pass), 4 key-switch inner product,
 // 5 base conversion, 6 elementwise.
-constexpr int kProfKinds = 7;
+constexpr int kProfKinds = 11;
 struct ProfSlot {
   uint64_t launches = 0;
   double ms = 0;
-  double limbs = 0;
+  double bytes = 0;   // algorithmic bytes
 };
 
 struct KSTables;  // per-level base-conversion constants (device)
@@ -304,7 +306,7 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
 // group s (plaintext [nl][N], or ciphertext [2][nl][N] when enc), null when that diagonal is zero.
 constexpr int kMmTabPad = 32;
 void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int n_groups,
-                     int G, int nl, size_t baby_slot, size_t baby_b, bool enc);
+                     int G, int nl, size_t baby_slot, size_t baby_b, bool enc, size_t nnz);
 void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
                       const double* first, size_t first_stride_b, int nl, int rows, int G);
 void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const std::vector<double*>& lt,
@@ -312,10 +314,13 @@ void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const st
                             const std::vector<const double*>& ts, int nl);
 
 void launch_calib_copy(Context& c, double* dst, const double* src, size_t n);
+// plain device copy of n doubles as a kernel (no copy-engine node when captured in a graph)
+inline void launch_copy(Context& c, double* dst, const double* src, size_t n) { launch_calib_copy(c, dst, src, n); }
 
-// profiling hooks
+// profiling hooks: prof_end adds the launch's algorithmic bytes (each input and output row of the
+// operation touched once; keys counted per job, twiddle tables not counted)
 void prof_begin(Context& c, int kind, hipEvent_t* ev);
-void prof_end(Context& c, int kind, hipEvent_t ev, double limbs);
+void prof_end(Context& c, int kind, hipEvent_t ev, double bytes);
 void prof_collect(Context& c);
 
 // ------------------------------------------------------------------ BGV operations (bgv.cpp)

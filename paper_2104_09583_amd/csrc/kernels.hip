@@ -618,13 +618,13 @@ void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows) {
     if (S1r > 0) {
       prof_begin(c, 1, &ev);
       launch_colreg<false>(c, base, rows, nrows, S1r, 0);
-      prof_end(c, 1, ev, nrows);
+      prof_end(c, 1, ev, 2.0 * nrows * (double)c.N * 8.0);
     }
     prof_begin(c, 0, &ev);
     hipLaunchKernelGGL(ntt_rowreg4_kernel<false>, dim3((unsigned)(N / 4096), nrows), dim3(512), 0, c.stream, base,
                        rows, c.d_primes, logN, S1r, 0);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 0, ev, nrows);
+    prof_end(c, 0, ev, 2.0 * nrows * (double)c.N * 8.0);
     return;
   }
   if (logN == 11) {
@@ -632,7 +632,7 @@ void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows) {
     hipLaunchKernelGGL(ntt_rowreg_kernel<false>, dim3(1, nrows), dim3(256), 0, c.stream, base, rows, c.d_primes,
                        logN, 0, 0);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 0, ev, nrows);
+    prof_end(c, 0, ev, 2.0 * nrows * (double)c.N * 8.0);
     return;
   }
   prof_begin(c, 0, &ev);
@@ -643,7 +643,7 @@ void launch_ntt_fwd(Context& c, double* base, const int2* rows, int nrows) {
   hipLaunchKernelGGL(ntt_rows_kernel<false>, dim3(tiles, nrows), dim3(kThreads), 0, c.stream, base, rows,
                      c.d_primes, logN, S1, 0);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 0, ev, nrows);
+  prof_end(c, 0, ev, 2.0 * nrows * (double)c.N * 8.0);
 }
 
 void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
@@ -663,11 +663,11 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
     hipLaunchKernelGGL(ntt_rowreg4_kernel<true>, dim3((unsigned)(N / 4096), nrows), dim3(512), 0, c.stream, base,
                        rows, c.d_primes, logN, S1r, S1r == 0 ? 1 : 0);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 2, ev, nrows);
+    prof_end(c, 2, ev, 2.0 * nrows * (double)c.N * 8.0);
     if (S1r > 0) {
       prof_begin(c, 3, &ev);
       launch_colreg<true>(c, base, rows, nrows, S1r, 1);
-      prof_end(c, 3, ev, nrows);
+      prof_end(c, 3, ev, 2.0 * nrows * (double)c.N * 8.0);
     }
     return;
   }
@@ -676,7 +676,7 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
     hipLaunchKernelGGL(ntt_rowreg_kernel<true>, dim3(1, nrows), dim3(256), 0, c.stream, base, rows, c.d_primes,
                        logN, 0, 1);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 2, ev, nrows);
+    prof_end(c, 2, ev, 2.0 * nrows * (double)c.N * 8.0);
     return;
   }
   prof_begin(c, 2, &ev);
@@ -687,7 +687,7 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
     hipLaunchKernelGGL(ntt_cols_kernel<true>, dim3((unsigned)((N >> S1) / (kTile >> S1)), nrows), dim3(kThreads),
                        0, c.stream, base, rows, c.d_primes, logN, S1, 1);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 2, ev, nrows);
+  prof_end(c, 2, ev, 2.0 * nrows * (double)c.N * 8.0);
 }
 
 // ------------------------------------------------------------------ fused column passes + base change
@@ -701,7 +701,8 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
 //   kMode 1 (modulus switch):       z = [x_0 mult_0]_{p_0} centered,  out_o = z mod q_o
 // The values handed to the forward stages are any representatives of the residues (|v| <= q/2), so the
 // transform's canonical output is the same as that of the unfused steps.
-// grid: x over column groups of 64, z over the batch (in_bs / out_bs apart).
+// grid: x over column groups of 64, y over chunks of ochunk outputs (small batches: more blocks, the
+// inputs' stages recomputed per chunk), z over the batch (in_bs / out_bs apart).
 constexpr int kBridgeIn = 4;
 template <int S1, int kMode>
 __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out_base, const int2* __restrict__ out_rows,
@@ -709,7 +710,7 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
                                                        const int2* __restrict__ in_rows, int n_in,
                                                        const double* __restrict__ mult, const double* __restrict__ mat,
                                                        const DevPrime* __restrict__ P, int logN, size_t in_bs,
-                                                       size_t out_bs) {
+                                                       size_t out_bs, int ochunk) {
   constexpr int R = 1 << S1;
   const size_t N = (size_t)1 << logN;
   const size_t C = N >> S1;
@@ -748,7 +749,8 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
       }
     }
   }
-  for (int o = 0; o < n_out; ++o) {
+  const int o1 = min(n_out, ((int)blockIdx.y + 1) * ochunk);
+  for (int o = (int)blockIdx.y * ochunk; o < o1; ++o) {
     const int2 orow = out_rows[o];
     const DevPrime& po = P[orow.y];
     double x[R];
@@ -790,16 +792,22 @@ void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows,
   if (mode == 1 && n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
   const int S1 = (int)c.log_n - 12;
   const unsigned C = (unsigned)(c.N >> S1);
+  // at least ~2048 workgroups when the batch is small, by splitting the outputs
+  const unsigned xb = (C + 63) / 64;
+  int chunks = 1;
+  while (chunks < n_out && (size_t)xb * batch * chunks < 2048) chunks *= 2;
+  const int ochunk = (n_out + chunks - 1) / chunks;
+  chunks = (n_out + ochunk - 1) / ochunk;
   hipEvent_t ev;
   prof_begin(c, 5, &ev);
   for (int first = 0; first < batch; first += kMaxGridY) {
     const int cnt = std::min(kMaxGridY, batch - first);
-    dim3 grid((C + 63) / 64, 1, cnt), blk(64);
+    dim3 grid(xb, chunks, cnt), blk(64);
     const double* ib = in_base + (size_t)first * in_bs;
     double* ob = out_base + (size_t)first * out_bs;
 #define COPSE_BRIDGE(S, M)                                                                                        \
   hipLaunchKernelGGL((ntt_bridge_kernel<S, M>), grid, blk, 0, c.stream, ob, out_rows, n_out, ib, in_rows, n_in, mult, \
-                     mat, c.d_primes, (int)c.log_n, in_bs, out_bs)
+                     mat, c.d_primes, (int)c.log_n, in_bs, out_bs, ochunk)
     if (mode == 0) {
       switch (S1) {
         case 1: COPSE_BRIDGE(1, 0); break;
@@ -818,7 +826,7 @@ void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows,
 #undef COPSE_BRIDGE
     COPSE_HIP(hipGetLastError());
   }
-  prof_end(c, 5, ev, (double)(n_out + n_in) * batch);
+  prof_end(c, 5, ev, (double)(n_out + n_in) * batch * (double)c.N * 8.0);   // inputs counted once
 }
 
 // row passes alone (the column passes are done by the bridge): inverse rows leave signed residues for
@@ -833,7 +841,7 @@ void launch_ntt_inv_rows(Context& c, double* base, const int2* rows, int nrows) 
     hipLaunchKernelGGL(ntt_rowreg4_kernel<true>, dim3((unsigned)(c.N / 4096), cnt), dim3(512), 0, c.stream, base,
                        rows + first, c.d_primes, (int)c.log_n, (int)c.log_n - 12, 0);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 2, ev, cnt);
+    prof_end(c, 2, ev, 2.0 * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -847,7 +855,7 @@ void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows) 
     hipLaunchKernelGGL(ntt_rowreg4_kernel<false>, dim3((unsigned)(c.N / 4096), cnt), dim3(512), 0, c.stream, base,
                        rows + first, c.d_primes, (int)c.log_n, (int)c.log_n - 12, 0);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 0, ev, cnt);
+    prof_end(c, 0, ev, 2.0 * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -860,12 +868,12 @@ void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const
     Pack pk;
     for (int k = 0; k < cnt; ++k) pk.p[k] = src[first + k];
     hipEvent_t ev;
-    prof_begin(c, 2, &ev);
+    prof_begin(c, 10, &ev);
     hipLaunchKernelGGL(ntt_rowinv_gather_kernel, dim3((unsigned)(c.N / 4096), cnt * rpj), dim3(512), 0, c.stream,
                        dst + first * rpj * c.N, pk, rpj, src_stride, src_off, prime_fixed, c.d_primes, (int)c.log_n,
                        (int)c.log_n - 12);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 2, ev, (double)cnt * rpj);
+    prof_end(c, 10, ev, 2.0 * cnt * rpj * (double)c.N * 8.0);
   }
 }
 
@@ -885,12 +893,12 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
       pin.p[k] = nullptr;
     }
     hipEvent_t ev;
-    prof_begin(c, 0, &ev);
+    prof_begin(c, 7, &ev);
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<1>, dim3((unsigned)(c.N / 4096), nl, 2 * cnt), dim3(512), 0,
                        c.stream, po, pin, pa, pg, acc + first * 2 * nE * c.N, w + first * 2 * nl * c.N, nE, nl, 2,
                        add_mode, 0, pinv, tpinv, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 0, ev, 2.0 * nl * cnt);
+    prof_end(c, 7, ev, (6.0 + (add_mode == 1 ? 2.0 : add_mode == 2 ? 1.0 : 0.0)) * nl * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -911,12 +919,12 @@ void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, 
       pg.g[k] = 1;
     }
     hipEvent_t ev;
-    prof_begin(c, 0, &ev);
+    prof_begin(c, 8, &ev);
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<2>, dim3((unsigned)(c.N / 4096), level, np * cnt), dim3(512), 0,
                        c.stream, po, pi, pa, pg, nullptr, w + first * np * level * c.N, 0, level, np, 0,
                        add ? add_np : 0, tab, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 0, ev, (double)level * np * cnt);
+    prof_end(c, 8, ev, (3.0 * np + (add ? add_np : 0)) * level * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -976,7 +984,7 @@ static dim3 ew_grid(const Context& c, int nrows) { return dim3((unsigned)((c.N +
     hipLaunchKernelGGL(kern, ew_grid(c, nrows), dim3(256), 0, c.stream, __VA_ARGS__, rows, c.d_primes, \
                        (int)c.log_n);                                                             \
     COPSE_HIP(hipGetLastError());                                                                 \
-    prof_end(c, 6, ev, nrows);                                                                    \
+    prof_end(c, 6, ev, 3.0 * nrows * (double)c.N * 8.0);                                                                    \
   } while (0)
 
 void launch_add(Context& c, double* out, const double* a, const double* b, const int2* rows, int nrows) {
@@ -1024,7 +1032,7 @@ void launch_mul_plain(Context& c, double* out, const double* a, const double* pt
   hipLaunchKernelGGL(mul_plain_kernel, ew_grid(c, nl), dim3(256), 0, c.stream, out, a, pt, nl, npolys, c.d_primes,
                      (int)c.log_n, 0);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, nl * npolys);
+  prof_end(c, 6, ev, (2.0 * npolys + 1) * nl * (double)c.N * 8.0);
 }
 void launch_mac_plain(Context& c, double* acc, const double* a, const double* pt, int npolys, int nl) {
   hipEvent_t ev;
@@ -1032,7 +1040,7 @@ void launch_mac_plain(Context& c, double* acc, const double* a, const double* pt
   hipLaunchKernelGGL(mul_plain_kernel, ew_grid(c, nl), dim3(256), 0, c.stream, acc, a, pt, nl, npolys, c.d_primes,
                      (int)c.log_n, 1);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, nl * npolys);
+  prof_end(c, 6, ev, (3.0 * npolys + 1) * nl * (double)c.N * 8.0);
 }
 
 // d = (a0 b0, a0 b1 + a1 b0, a1 b1), optionally accumulated into d
@@ -1064,7 +1072,7 @@ void launch_tensor(Context& c, double* d, const double* a, const double* b, int 
   hipLaunchKernelGGL(tensor_kernel, ew_grid(c, nl), dim3(256), 0, c.stream, d, a, b, nl, c.d_primes, (int)c.log_n,
                      accumulate ? 1 : 0);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, 3 * nl);
+  prof_end(c, 6, ev, 7.0 * nl * (double)c.N * 8.0);
 }
 
 __global__ void add_const_kernel(double* a, int nl, double v, const DevPrime* P, int logN) {
@@ -1152,7 +1160,7 @@ void launch_bconv(Context& c, double* out_base, const int2* out_rows, int n_out,
                      dim3(256), 0, c.stream, out_base, out_rows, n_out, in_base, in_rows, n_in, mult, mat,
                      c.d_primes, (int)c.log_n, in_bs, out_bs);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 5, ev, (double)n_out * batch);
+  prof_end(c, 5, ev, (double)(n_out + n_in) * batch * (double)c.N * 8.0);   // inputs counted once
 }
 
 // ------------------------------------------------------------------ key-switch inner product
@@ -1190,7 +1198,8 @@ void launch_ks_inner(Context& c, const KsJob* jobs, int njobs, int D, int nE, in
     hipLaunchKernelGGL(ks_inner_kernel, dim3((unsigned)((c.N + 255) / 256), nE, cnt), dim3(256), 0, c.stream, pack,
                        D, nE, level + 1, c.L, (int)c.log_n, key_ds, c.d_primes);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 4, ev, (double)nE * cnt);
+    // per job and extended row: D digit rows and 2 D key rows read, 2 rows written
+    prof_end(c, 4, ev, (3.0 * D + 2.0) * nE * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1239,7 +1248,7 @@ void launch_ms_finish(Context& c, double* out, const double* in, const double* w
   hipLaunchKernelGGL(ms_finish_kernel, dim3((unsigned)((c.N + 255) / 256), level, npolys), dim3(256), 0,
                      c.stream, out, in, w, npolys, level, tab, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, (double)level * npolys);
+  prof_end(c, 6, ev, 3.0 * level * npolys * (double)c.N * 8.0);
 }
 
 // ------------------------------------------------------------------ ModDown finish
@@ -1270,7 +1279,7 @@ void launch_moddown_finish(Context& c, double* out, const double* y, size_t ys, 
   hipLaunchKernelGGL(moddown_finish_kernel, dim3((unsigned)((c.N + 255) / 256), nl, npolys), dim3(256), 0,
                      c.stream, out, y, ys, w, nl, pinv, tpinv, add, adds, add_mode, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, (double)nl * npolys);
+  prof_end(c, 6, ev, 3.0 * nl * npolys * (double)c.N * 8.0);
 }
 
 }  // namespace copse
@@ -1335,7 +1344,7 @@ void launch_ew_multi(Context& c, int op, const std::vector<double*>& out, const 
     hipLaunchKernelGGL(ew_multi_kernel, dim3((unsigned)((c.N + 255) / 256), rows_per_job, cnt), dim3(256), 0,
                        c.stream, po, pa, pb, op, nl, b_rows, c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 6, ev, (double)rows_per_job * cnt);
+    prof_end(c, 6, ev, 3.0 * rows_per_job * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1393,7 +1402,7 @@ void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::v
     hipLaunchKernelGGL(tensor_multi_kernel, dim3((unsigned)((c.N + 255) / 256), nl, cnt), dim3(256), 0, c.stream,
                        pd, pa, pb, nl, c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 6, ev, 3.0 * nl * cnt);
+    prof_end(c, 6, ev, 6.0 * nl * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1434,7 +1443,7 @@ void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const s
                        c.stream, po, pi, pa, add ? add_np : 0, w + first * np * level * c.N, np, level, tab,
                        c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 6, ev, (double)level * np * cnt);
+    prof_end(c, 6, ev, (3.0 * np + (add ? add_np : 0)) * level * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1472,7 +1481,14 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
     hipLaunchKernelGGL(ks_inner2_kernel, dim3((unsigned)((c.N + 255) / 256), nE, cnt), dim3(256), 0, c.stream, pk, D,
                        nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 4, ev, (double)nE * cnt);
+    // per job and extended row: D digit rows read and 2 rows written; each distinct key's 2 D rows once
+    int keys = 0;
+    for (int k = 0; k < cnt; ++k) {
+      bool seen = false;
+      for (int k2 = 0; k2 < k; ++k2) seen |= pk.j[k2].kb == pk.j[k].kb;
+      keys += !seen;
+    }
+    prof_end(c, 4, ev, ((D + 2.0) * cnt + 2.0 * D * keys) * nE * (double)c.N * 8.0);
   }
 }
 
@@ -1517,7 +1533,7 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
                        po, pa, pg, acc + first * 2 * nE * c.N, w + first * 2 * nl * c.N, nE, nl, pinv, tpinv,
                        add_mode, c.d_primes, (int)c.log_n);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 6, ev, 2.0 * nl * cnt);
+    prof_end(c, 6, ev, (6.0 + (add_mode == 1 ? 2.0 : add_mode == 2 ? 1.0 : 0.0)) * nl * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1630,12 +1646,12 @@ static void mm_inner_launch(Context& c, double* out, const double* baby, const d
 }
 
 void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng, int G,
-                     int nl, size_t baby_slot, size_t baby_b, bool enc) {
+                     int nl, size_t baby_slot, size_t baby_b, bool enc, size_t nnz) {
   if (ng <= 0 || G <= 0) return;
   if ((size_t)((c.N + kMmLanes - 1) / kMmLanes) * (size_t)((G + kMmWaves - 1) / kMmWaves) > 0x7fffffffu)
     fail(COPSE_EINVAL, "MatMul batch too large");
   hipEvent_t ev;
-  prof_begin(c, 6, &ev);
+  prof_begin(c, 9, &ev);
   // giant groups in chunks of at most 24 (12 with three accumulators each), split evenly
   const int cap = enc ? 12 : 24;   // at most 165 VGPRs: three waves per SIMD
   const int chunks = (ng + cap - 1) / cap;
@@ -1652,7 +1668,9 @@ void launch_mm_inner(Context& c, double* out, const double* baby, const double* 
   else if (per <= 24) run(std::integral_constant<int, 24>());
   else run(std::integral_constant<int, 32>());
   COPSE_HIP(hipGetLastError());
-  prof_end(c, 6, ev, (enc ? 3.0 : 2.0) * nl * ng * G);
+  // every baby step, every nonzero diagonal and every output read or written once
+  prof_end(c, 9, ev, ((double)n_u * G * 2 + (double)nnz * (enc ? 2 : 1) + (double)ng * G * (enc ? 3 : 2)) * nl *
+                         (double)c.N * 8.0);
 }
 
 // out_b = sum_{p < nparts} parts[p * stride_p + b * stride_b]  over rows (row r has prime r % nl);
@@ -1722,7 +1740,9 @@ __global__ void calib_copy_kernel(double* __restrict__ dst, const double* __rest
     dst[i] = src[i];
 }
 void launch_calib_copy(Context& c, double* dst, const double* src, size_t n) {
-  hipLaunchKernelGGL(calib_copy_kernel, dim3(4096), dim3(256), 0, c.stream, dst, src, n);
+  if (n == 0) return;
+  const unsigned blocks = (unsigned)std::min<size_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(calib_copy_kernel, dim3(blocks), dim3(256), 0, c.stream, dst, src, n);
   COPSE_HIP(hipGetLastError());
 }
 }  // namespace copse

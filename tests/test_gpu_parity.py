@@ -371,6 +371,53 @@ def test_workload_full_size_against_stored_oracle(C, name):
     assert h.hexdigest() == gold["sha256"]
     bits = ctx.decrypt_labels(keys, meta, res, nq)
     assert bits.tolist() == gold["labels"]
+    # the captured evaluation the benchmark times gives the same bits, replay after replay
+    ex = ctx.exec_create(model, ctx.export_eval(keys), 1)
+    for rep in range(2):
+        got = ctx.export(ex.run([qct])[0])[0]
+        hg = hashlib.sha256()
+        for p in got["polys"]:
+            hg.update(np.ascontiguousarray(p, dtype="<u8").tobytes())
+        assert hg.hexdigest() == gold["sha256"], f"replay {rep}"
+        ctx.evaluate(model, ctx.export_eval(keys), qct)   # eager work between replays
+    ex.close()
+
+
+def test_captured_evaluation_replays_match_batch(C):
+    """The HIP-graph executor: several replays on different queries, with eager evaluations and
+    synchronizations in between, each bit-identical to evaluate_batch on the same queries."""
+    shape = synth.ForestShape(4, 4, 0.7, 4, 4, 3)
+    text = synth.gen_forest_text(shape, 33)
+    oc = OC.compile_forest(text, 4, 4)
+    need = CI.seccomp_depth(4) + 2 + math.ceil(math.log2(oc.d))
+    ch = dict(log_n=13, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=3, special_max=1 << 49)
+    ctx = C.Context(**ch)
+    comp, meta = C.forest_compile(text, 4, 4, 13)
+    kseed = b"\x45" * 32
+    keys = ctx.keygen(kseed, C.compiled_rotations(meta))
+    evk = ctx.export_eval(keys)
+    model = ctx.model_encode(comp)
+    G = 3
+    say("captured evaluation, groups", G)
+    ex = ctx.exec_create(model, evk, G)
+    _, trees = F.parse_forest(text)
+    for rep in range(3):
+        qsets = [synth.gen_queries(meta.queries_per_ct, 4, 4, 500 + 10 * rep + g) for g in range(G)]
+        groups = [ctx.query_encrypt(keys, meta, qsets[g], kseed, group=10 * rep + g) for g in range(G)]
+        got = ex.run(groups)
+        ctx.sync()
+        want = ctx.evaluate_batch(model, evk, groups)
+        ctx.sync()
+        for g in range(G):
+            eg, ew = ctx.export(got[g])[0], ctx.export(want[g])[0]
+            assert eg["level"] == ew["level"]
+            assert all((a == b).all() for a, b in zip(eg["polys"], ew["polys"])), f"replay {rep} group {g}"
+            bits = ctx.decrypt_labels(keys, meta, got[g], len(qsets[g]))
+            assert (bits == np.array([F.evaluate(trees, list(x)) for x in qsets[g]])).all()
+    with pytest.raises(C.CopseError) as e:
+        ex.run(groups[:2])
+    assert e.value.code == C.COPSE_EINVAL
+    ex.close()
 
 
 # Full-size workloads whose oracle run is too long for a test: every decrypted label of the evaluated
