@@ -113,7 +113,8 @@ struct copse_exec {
   const copse::Keys* keys = nullptr;
   int groups = 0;
   std::shared_ptr<copse::Pool> arena;
-  std::vector<std::vector<copse::CtPtr>> inputs;   // [group][plane] at the top level
+  std::vector<std::vector<copse::CtPtr>> inputs;   // [group][plane] at the top level, one block
+  double* input_base = nullptr;
   std::vector<copse::CtPtr> outputs;               // the captured results (level 0)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

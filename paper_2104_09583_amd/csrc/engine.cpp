@@ -137,10 +137,15 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
     // inverse row pass read straight from the inputs, then per digit the fused column passes with the
     // base conversion, then the forward row pass of every new row
     launch_ntt_inv_rows_gather(c, cf.get(), inputs, nl, N, 0, -1);
+    // all digits in one launch (up to four per launch)
+    std::vector<BridgeDesc> ds;
     for (int j = 0; j < D; ++j) {
       auto& dg = T.digits[j];
-      launch_bridge(c, 0, ext.get(), dg.d_out_rows, (int)dg.targets.size(), cf.get(), dg.d_in_rows, dg.count,
-                    dg.d_mult, dg.d_mat, I, (size_t)nl * N, (size_t)D * nE * N);
+      ds.push_back(BridgeDesc{dg.d_out_rows, dg.d_in_rows, dg.d_mult, dg.d_mat, (int)dg.targets.size(), dg.count, 0, 0});
+      if ((int)ds.size() == BridgeSet::kMax || j == D - 1) {
+        launch_bridge_set(c, 0, ext.get(), cf.get(), ds, I, (size_t)nl * N, (size_t)D * nE * N);
+        ds.clear();
+      }
     }
   } else {
     launch_ntt_inv(c, cf.get(), block_rows(c, I, nl), I * nl);
@@ -417,16 +422,15 @@ static std::vector<SCt> b_sum_all(Context& c, const std::vector<std::vector<SCt>
     size_t T = terms_per_b[kv.second[0]].size();
     for (int b : kv.second)
       if (terms_per_b[b].size() != T) fail(COPSE_EINVAL, "internal: ragged sums");
-    for (size_t t = 1; t < T; ++t) {
+    if (T > 1) {
       std::vector<double*> o;
-      std::vector<const double*> a, bb;
+      std::vector<const double*> terms;
       for (size_t q = 0; q < kv.second.size(); ++q) {
-        int b = kv.second[q];
+        const int b = kv.second[q];
         o.push_back(acc[q]->data());
-        a.push_back(t == 1 ? flat[start[b]]->data() : acc[q]->data());
-        bb.push_back(flat[start[b] + t]->data());
+        for (size_t t = 0; t < T; ++t) terms.push_back(flat[start[b] + t]->data());
       }
-      launch_ew_multi(c, 0, o, a, bb, nl, 2 * nl, 2 * nl);
+      launch_sum_terms(c, o, terms, (int)T, nl, 2 * nl);
     }
     for (size_t q = 0; q < kv.second.size(); ++q) out[kv.second[q]] = T == 1 ? flat[start[kv.second[q]]] : acc[q];
   }

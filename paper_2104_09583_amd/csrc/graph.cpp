@@ -52,14 +52,23 @@ std::unique_ptr<copse_exec> exec_create(Context& c, const Model& model, const Ke
   e->arena = std::make_shared<Pool>(c.device, true);
   ArenaScope scope(c, e->arena);
   const int p = (int)model.meta.precision;
+  // all input planes in one block, so that a run fills them with one gather launch
+  const size_t words = (size_t)2 * (c.L + 1) * c.N;
+  auto store = std::make_shared<DBuf>(&c, words * n_groups * p);
+  COPSE_HIP(hipMemsetAsync(store->get(), 0, words * n_groups * p * sizeof(double), c.stream));
   for (int g = 0; g < n_groups; ++g) {
     e->inputs.emplace_back();
     for (int k = 0; k < p; ++k) {
-      e->inputs.back().push_back(ct_alloc(c, c.L, 2));
-      Ct& ct = *e->inputs.back().back();
-      COPSE_HIP(hipMemsetAsync(ct.data(), 0, ct.words() * sizeof(double), c.stream));
+      auto ct = std::make_unique<Ct>();
+      ct->level = c.L;
+      ct->npolys = 2;
+      ct->n = c.N;
+      ct->store = store;
+      ct->ptr = store->get() + words * ((size_t)g * p + k);
+      e->inputs.back().push_back(std::move(ct));
     }
   }
+  e->input_base = store->get();
   const auto planes = plane_ptrs(e->inputs);
   // warm-up: fills the arena's cache and every lookup table the schedule uses
   { auto warm = evaluate_groups(c, model, keys, planes); }
@@ -87,16 +96,30 @@ std::vector<CtPtr> exec_run(copse_exec& e, const std::vector<std::vector<const C
       if (!q || q->level != c.L || q->npolys != 2 || q->n != c.N)
         fail(COPSE_EINVAL, "query planes must be fresh encryptions at the top level");
   }
+  std::vector<const double*> src;
   for (size_t g = 0; g < queries.size(); ++g)
-    for (size_t k = 0; k < e.inputs[g].size(); ++k)
-      launch_copy(c, e.inputs[g][k]->data(), queries[g][k]->data(), e.inputs[g][k]->words());
+    for (const Ct* q : queries[g]) src.push_back(q->data());
+  launch_gather(c, e.input_base, src, 2 * (c.L + 1));
   COPSE_HIP(hipGraphLaunch(e.exec, c.stream));
+  // results: one block, filled by one gather launch
+  const Ct& o0 = *e.outputs[0];
+  const size_t words = o0.words();
+  auto store = std::make_shared<DBuf>(&c, words * e.groups);
+  std::vector<const double*> res;
   std::vector<CtPtr> out;
   for (int g = 0; g < e.groups; ++g) {
-    const Ct& src = *e.outputs[g];
-    out.push_back(ct_alloc(c, src.level, src.npolys));
-    launch_copy(c, out.back()->data(), src.data(), src.words());
+    const Ct& o = *e.outputs[g];
+    if (o.level != o0.level || o.npolys != o0.npolys) fail(COPSE_EINVAL, "internal: results differ in shape");
+    res.push_back(o.data());
+    auto ct = std::make_unique<Ct>();
+    ct->level = o.level;
+    ct->npolys = o.npolys;
+    ct->n = c.N;
+    ct->store = store;
+    ct->ptr = store->get() + words * g;
+    out.push_back(std::move(ct));
   }
+  launch_gather(c, store->get(), res, o0.npolys * (o0.level + 1));
   return out;
 }
 

@@ -219,6 +219,25 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
 void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
                                    const double* w, int np, int level, const double* tab,
                                    const std::vector<const double*>* add, int add_np);
+// One coefficient map of the fused column pass: rows of the input block (index, prime), rows of the
+// output block, per-input multipliers and the [n_in][n_out] matrix (mode 0).  chunk0 / ochunk are set by
+// the launcher.  Several maps over the same input and output blocks (the digits of a ModUp) run as one
+// launch.
+struct BridgeDesc {
+  const int2* out_rows;
+  const int2* in_rows;
+  const double* mult;
+  const double* mat;
+  int n_out, n_in;
+  int chunk0, ochunk;
+};
+struct BridgeSet {
+  static constexpr int kMax = 4;
+  BridgeDesc d[kMax];
+  int n;
+};
+void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_base, std::vector<BridgeDesc> descs,
+                       int batch, size_t in_bs, size_t out_bs);
 // mode 0: fast base conversion (as launch_bconv); mode 1: modulus-switch lift of one row (mult = t^-1)
 void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
                    const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,
@@ -307,6 +326,9 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
 constexpr int kMmTabPad = 32;
 void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int n_groups,
                      int G, int nl, size_t baby_slot, size_t baby_b, bool enc, size_t nnz);
+// out_j = sum of terms[j * T .. j * T + T - 1] (canonical, exact)
+void launch_sum_terms(Context& c, const std::vector<double*>& out, const std::vector<const double*>& terms, int T,
+                      int nl, int rows_per_job);
 void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
                       const double* first, size_t first_stride_b, int nl, int rows, int G);
 void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const std::vector<double*>& lt,

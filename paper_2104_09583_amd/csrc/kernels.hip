@@ -705,24 +705,28 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
 // inputs' stages recomputed per chunk), z over the batch (in_bs / out_bs apart).
 constexpr int kBridgeIn = 4;
 template <int S1, int kMode>
-__global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out_base, const int2* __restrict__ out_rows,
-                                                       int n_out, const double* __restrict__ in_base,
-                                                       const int2* __restrict__ in_rows, int n_in,
-                                                       const double* __restrict__ mult, const double* __restrict__ mat,
-                                                       const DevPrime* __restrict__ P, int logN, size_t in_bs,
-                                                       size_t out_bs, int ochunk) {
+__global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out_base, const double* __restrict__ in_base,
+                                                       BridgeSet set, const DevPrime* __restrict__ P, int logN,
+                                                       size_t in_bs, size_t out_bs) {
   constexpr int R = 1 << S1;
   const size_t N = (size_t)1 << logN;
   const size_t C = N >> S1;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
+  // the conversion (digit) this block belongs to: set.d[k] owns grid rows [chunk0, next chunk0)
+  int di = 0;
+#pragma unroll
+  for (int k = 1; k < BridgeSet::kMax; ++k)
+    if (k < set.n && (int)blockIdx.y >= set.d[k].chunk0) di = k;
+  const BridgeDesc& d = set.d[di];
+  const int n_in = d.n_in, n_out = d.n_out;
   const double* in = in_base + (size_t)blockIdx.z * in_bs;
   double* out = out_base + (size_t)blockIdx.z * out_bs;
   double y[kBridgeIn][R];
 #pragma unroll
   for (int k = 0; k < kBridgeIn; ++k) {
     if (k < n_in) {
-      const int2 irow = in_rows[k];
+      const int2 irow = d.in_rows[k];
       const DevPrime& pk = P[irow.y];
       const double* a = in + (size_t)irow.x * N;
       double x[R];
@@ -738,7 +742,7 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
           for (int o = 0; o < half; ++o) bfly_gs(x[g * 2 * half + o], x[g * 2 * half + o + half], w, pk.q, pk.qinv);
         }
       }
-      const double mk = mult[k];
+      const double mk = d.mult[k];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         // coefficient in [0, p_k), then [coef * mult_k]_{p_k} in [0, p_k)
@@ -749,9 +753,10 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
       }
     }
   }
-  const int o1 = min(n_out, ((int)blockIdx.y + 1) * ochunk);
-  for (int o = (int)blockIdx.y * ochunk; o < o1; ++o) {
-    const int2 orow = out_rows[o];
+  const int o0 = ((int)blockIdx.y - d.chunk0) * d.ochunk;
+  const int o1 = min(n_out, o0 + d.ochunk);
+  for (int o = o0; o < o1; ++o) {
+    const int2 orow = d.out_rows[o];
     const DevPrime& po = P[orow.y];
     double x[R];
 #pragma unroll
@@ -760,7 +765,7 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kBridgeIn; ++k)
-          if (k < n_in) acc += mul_lazy(y[k][r], mat[k * n_out + o], po.q, po.qinv);
+          if (k < n_in) acc += mul_lazy(y[k][r], d.mat[k * n_out + o], po.q, po.qinv);
         x[r] = reduce_sym(acc, po.q, po.qinv);
       } else {
         x[r] = reduce_sym(y[0][r], po.q, po.qinv);
@@ -784,30 +789,42 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
 
 bool bridge_supported(const Context& c, int n_in) { return c.log_n >= 13 && c.log_n <= 16 && n_in <= kBridgeIn; }
 
-void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
-                   const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,
-                   size_t out_bs) {
-  if (n_out <= 0 || batch <= 0) return;
-  if (!bridge_supported(c, n_in)) fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
-  if (mode == 1 && n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
+void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_base, std::vector<BridgeDesc> descs,
+                       int batch, size_t in_bs, size_t out_bs) {
+  if (batch <= 0 || descs.empty()) return;
+  if ((int)descs.size() > BridgeSet::kMax) fail(COPSE_EINVAL, "internal: too many conversions in one launch");
   const int S1 = (int)c.log_n - 12;
   const unsigned C = (unsigned)(c.N >> S1);
-  // at least ~2048 workgroups when the batch is small, by splitting the outputs
   const unsigned xb = (C + 63) / 64;
-  int chunks = 1;
-  while (chunks < n_out && (size_t)xb * batch * chunks < 2048) chunks *= 2;
-  const int ochunk = (n_out + chunks - 1) / chunks;
-  chunks = (n_out + ochunk - 1) / ochunk;
+  BridgeSet set{};
+  set.n = (int)descs.size();
+  int rows_y = 0;
+  double bytes = 0;
+  for (int k = 0; k < set.n; ++k) {
+    BridgeDesc d = descs[k];
+    if (!bridge_supported(c, d.n_in)) fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
+    if (mode == 1 && d.n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
+    if (d.n_out <= 0) fail(COPSE_EINVAL, "internal: conversion without outputs");
+    // at least ~2048 workgroups when the batch is small, by splitting the outputs
+    int chunks = 1;
+    while (chunks < d.n_out && (size_t)xb * batch * chunks * set.n < 2048) chunks *= 2;
+    d.ochunk = (d.n_out + chunks - 1) / chunks;
+    chunks = (d.n_out + d.ochunk - 1) / d.ochunk;
+    d.chunk0 = rows_y;
+    rows_y += chunks;
+    set.d[k] = d;
+    bytes += (double)(d.n_out + d.n_in) * batch * (double)c.N * 8.0;   // inputs counted once
+  }
   hipEvent_t ev;
   prof_begin(c, 5, &ev);
   for (int first = 0; first < batch; first += kMaxGridY) {
     const int cnt = std::min(kMaxGridY, batch - first);
-    dim3 grid(xb, chunks, cnt), blk(64);
+    dim3 grid(xb, rows_y, cnt), blk(64);
     const double* ib = in_base + (size_t)first * in_bs;
     double* ob = out_base + (size_t)first * out_bs;
-#define COPSE_BRIDGE(S, M)                                                                                        \
-  hipLaunchKernelGGL((ntt_bridge_kernel<S, M>), grid, blk, 0, c.stream, ob, out_rows, n_out, ib, in_rows, n_in, mult, \
-                     mat, c.d_primes, (int)c.log_n, in_bs, out_bs, ochunk)
+#define COPSE_BRIDGE(S, M)                                                                                       \
+  hipLaunchKernelGGL((ntt_bridge_kernel<S, M>), grid, blk, 0, c.stream, ob, ib, set, c.d_primes, (int)c.log_n, \
+                     in_bs, out_bs)
     if (mode == 0) {
       switch (S1) {
         case 1: COPSE_BRIDGE(1, 0); break;
@@ -826,7 +843,15 @@ void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows,
 #undef COPSE_BRIDGE
     COPSE_HIP(hipGetLastError());
   }
-  prof_end(c, 5, ev, (double)(n_out + n_in) * batch * (double)c.N * 8.0);   // inputs counted once
+  prof_end(c, 5, ev, bytes);
+}
+
+void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
+                   const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,
+                   size_t out_bs) {
+  if (n_out <= 0 || batch <= 0) return;
+  launch_bridge_set(c, mode, out_base, in_base, {BridgeDesc{out_rows, in_rows, mult, mat, n_out, n_in, 0, 0}}, batch,
+                    in_bs, out_bs);
 }
 
 // row passes alone (the column passes are done by the bridge): inverse rows leave signed residues for
@@ -1695,6 +1720,40 @@ void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, 
   hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((c.N + 255) / 256), rows, G), dim3(256), 0, c.stream, out,
                      parts, nparts, stride_p, stride_b, first, first_stride_b, nl, rows, c.d_primes, (int)c.log_n);
   COPSE_HIP(hipGetLastError());
+}
+
+// out_j = sum_{t < T} terms[j T + t] over rows_per_job rows (row r has prime r % nl)
+__global__ void sum_terms_kernel(MPack out, Pack terms, int T, int nl, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int r = blockIdx.y, j = blockIdx.z;
+  const DevPrime& pr = P[r % nl];
+  const size_t o = (size_t)r * N + i;
+  double acc = terms.p[j * T][o];
+  for (int t = 1; t < T; ++t) acc = mod_add(acc, terms.p[j * T + t][o], pr.q);
+  out.p[j][o] = acc;
+}
+
+void launch_sum_terms(Context& c, const std::vector<double*>& out, const std::vector<const double*>& terms, int T,
+                      int nl, int rows_per_job) {
+  if (T <= 0 || T > kPack) fail(COPSE_EINVAL, "internal: sum of too many terms");
+  const int per = kPack / T;
+  for (size_t first = 0; first < out.size(); first += per) {
+    const int cnt = (int)std::min<size_t>(per, out.size() - first);
+    MPack po;
+    Pack pt;
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k];
+      for (int t = 0; t < T; ++t) pt.p[k * T + t] = terms[(first + k) * T + t];
+    }
+    hipEvent_t ev;
+    prof_begin(c, 6, &ev);
+    hipLaunchKernelGGL(sum_terms_kernel, dim3((unsigned)((c.N + 255) / 256), rows_per_job, cnt), dim3(256), 0,
+                       c.stream, po, pt, T, nl, c.d_primes, (int)c.log_n);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 6, ev, (T + 1.0) * rows_per_job * cnt * (double)c.N * 8.0);
+  }
 }
 
 // encrypted comparison combine: eq = 2u - xs - ts + 1 (if want_eq), lt = ts - u
