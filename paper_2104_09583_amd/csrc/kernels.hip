@@ -704,15 +704,20 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
 // grid: x over column groups of 64, y over chunks of ochunk outputs (small batches: more blocks, the
 // inputs' stages recomputed per chunk), z over the batch (in_bs / out_bs apart).
 constexpr int kBridgeIn = 4;
+// A workgroup is 64 columns x 4 waves: wave k runs the inverse stages of input row k (k < n_in) and
+// leaves [coef * mult_k] in LDS; then the four waves take the outputs of the block's chunk in turn.
 template <int S1, int kMode>
-__global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out_base, const double* __restrict__ in_base,
-                                                       BridgeSet set, const DevPrime* __restrict__ P, int logN,
-                                                       size_t in_bs, size_t out_bs) {
+__global__ __launch_bounds__(256) void ntt_bridge_kernel(double* __restrict__ out_base, const double* __restrict__ in_base,
+                                                        BridgeSet set, const DevPrime* __restrict__ P, int logN,
+                                                        size_t in_bs, size_t out_bs) {
   constexpr int R = 1 << S1;
+  __shared__ double ys[kBridgeIn][R][64];
   const size_t N = (size_t)1 << logN;
   const size_t C = N >> S1;
-  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const size_t c = (size_t)blockIdx.x * 64 + lane;
+  const bool active = c < C;
   // the conversion (digit) this block belongs to: set.d[k] owns grid rows [chunk0, next chunk0)
   int di = 0;
 #pragma unroll
@@ -722,40 +727,38 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
   const int n_in = d.n_in, n_out = d.n_out;
   const double* in = in_base + (size_t)blockIdx.z * in_bs;
   double* out = out_base + (size_t)blockIdx.z * out_bs;
-  double y[kBridgeIn][R];
+  if (wv < n_in && active) {
+    const int2 irow = d.in_rows[wv];
+    const DevPrime& pk = P[irow.y];
+    const double* a = in + (size_t)irow.x * N;
+    double x[R];
 #pragma unroll
-  for (int k = 0; k < kBridgeIn; ++k) {
-    if (k < n_in) {
-      const int2 irow = d.in_rows[k];
-      const DevPrime& pk = P[irow.y];
-      const double* a = in + (size_t)irow.x * N;
-      double x[R];
+    for (int r = 0; r < R; ++r) x[r] = a[r * C + c];
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[r] = a[r * C + c];
+    for (int s = S1 - 1; s >= 0; --s) {
+      const int half = R >> (s + 1);
 #pragma unroll
-      for (int s = S1 - 1; s >= 0; --s) {
-        const int half = R >> (s + 1);
+      for (int g = 0; g < (1 << s); ++g) {
+        const double w = pk.inv[(1 << s) + g];
 #pragma unroll
-        for (int g = 0; g < (1 << s); ++g) {
-          const double w = pk.inv[(1 << s) + g];
-#pragma unroll
-          for (int o = 0; o < half; ++o) bfly_gs(x[g * 2 * half + o], x[g * 2 * half + o + half], w, pk.q, pk.qinv);
-        }
-      }
-      const double mk = d.mult[k];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        // coefficient in [0, p_k), then [coef * mult_k]_{p_k} in [0, p_k)
-        const double cf = canon(reduce_sym(mul_lazy(x[r], pk.ninv, pk.q, pk.qinv), pk.q, pk.qinv), pk.q);
-        double v = canon(mul_lazy(cf, mk, pk.q, pk.qinv), pk.q);
-        if (kMode == 1 && v > (pk.q - 1.0) * 0.5) v -= pk.q;
-        y[k][r] = v;
+        for (int o = 0; o < half; ++o) bfly_gs(x[g * 2 * half + o], x[g * 2 * half + o + half], w, pk.q, pk.qinv);
       }
     }
+    const double mk = d.mult[wv];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      // coefficient in [0, p_k), then [coef * mult_k]_{p_k} in [0, p_k)
+      const double cf = canon(reduce_sym(mul_lazy(x[r], pk.ninv, pk.q, pk.qinv), pk.q, pk.qinv), pk.q);
+      double v = canon(mul_lazy(cf, mk, pk.q, pk.qinv), pk.q);
+      if (kMode == 1 && v > (pk.q - 1.0) * 0.5) v -= pk.q;
+      ys[wv][r][lane] = v;
+    }
   }
+  __syncthreads();
+  if (!active) return;
   const int o0 = ((int)blockIdx.y - d.chunk0) * d.ochunk;
   const int o1 = min(n_out, o0 + d.ochunk);
-  for (int o = o0; o < o1; ++o) {
+  for (int o = o0 + wv; o < o1; o += 4) {
     const int2 orow = d.out_rows[o];
     const DevPrime& po = P[orow.y];
     double x[R];
@@ -765,10 +768,10 @@ __global__ __launch_bounds__(64) void ntt_bridge_kernel(double* __restrict__ out
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kBridgeIn; ++k)
-          if (k < n_in) acc += mul_lazy(y[k][r], d.mat[k * n_out + o], po.q, po.qinv);
+          if (k < n_in) acc += mul_lazy(ys[k][r][lane], d.mat[k * n_out + o], po.q, po.qinv);
         x[r] = reduce_sym(acc, po.q, po.qinv);
       } else {
-        x[r] = reduce_sym(y[0][r], po.q, po.qinv);
+        x[r] = reduce_sym(ys[0][r][lane], po.q, po.qinv);
       }
     }
 #pragma unroll
@@ -805,9 +808,10 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
     if (!bridge_supported(c, d.n_in)) fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
     if (mode == 1 && d.n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
     if (d.n_out <= 0) fail(COPSE_EINVAL, "internal: conversion without outputs");
-    // at least ~2048 workgroups when the batch is small, by splitting the outputs
+    // at least ~512 workgroups (2048 waves) when the batch is small, by splitting the outputs into chunks
+    // of at least 4 (one per wave)
     int chunks = 1;
-    while (chunks < d.n_out && (size_t)xb * batch * chunks * set.n < 2048) chunks *= 2;
+    while (chunks * 8 <= d.n_out && (size_t)xb * batch * chunks * set.n < 512) chunks *= 2;
     d.ochunk = (d.n_out + chunks - 1) / chunks;
     chunks = (d.n_out + d.ochunk - 1) / d.ochunk;
     d.chunk0 = rows_y;
@@ -819,7 +823,7 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
   prof_begin(c, 5, &ev);
   for (int first = 0; first < batch; first += kMaxGridY) {
     const int cnt = std::min(kMaxGridY, batch - first);
-    dim3 grid(xb, rows_y, cnt), blk(64);
+    dim3 grid(xb, rows_y, cnt), blk(256);
     const double* ib = in_base + (size_t)first * in_bs;
     double* ob = out_base + (size_t)first * out_bs;
 #define COPSE_BRIDGE(S, M)                                                                                       \
