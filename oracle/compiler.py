@@ -182,6 +182,65 @@ def compile_trees(trees: List[Node], n_features: int, precision: int) -> Compile
     return c
 
 
+class _Draws:
+    """Sequential bounded draws from one SHAKE-256 stream: an 8-byte little-endian word masked to
+    bitlen(bound) bits, accepted if below bound (the uniform sampler of the key material)."""
+
+    def __init__(self, seed: bytes, domain: str):
+        from .sampling import stream
+        self._get = lambda n: stream(seed, domain, 0, 0, n)
+        self._buf = self._get(4096)
+        self._pos = 0
+
+    def word(self) -> int:
+        if self._pos + 8 > len(self._buf):
+            self._buf = self._get(2 * len(self._buf))
+        w = int.from_bytes(self._buf[self._pos:self._pos + 8], "little")
+        self._pos += 8
+        return w
+
+    def below(self, bound: int) -> int:
+        mask = (1 << bound.bit_length()) - 1
+        while True:
+            w = self.word() & mask
+            if w < bound:
+                return w
+
+
+def privatize(c: Compiled, seed: bytes, n_pad: int, n_classes: int) -> Compiled:
+    """Result privacy (Section 6, "Returning classification bitvectors"): the server shuffles the
+    result bitvector and the codebook by one random permutation and pads both with n_pad extra labels
+    that are never selected.  Folded into the level products: slot s of every level matrix, mask and
+    the codebook takes original row arr[s], where arr is the identity on m + n_pad rows shuffled by
+    Fisher-Yates (for i from m + n_pad - 1 down to 1: swap arr[i] with arr[j], j drawn below i + 1);
+    a row arr[s] >= m is a padding row (all-zero matrix row, mask 0: its level results and product
+    are 0) whose codebook label is drawn below n_classes (the forest's label count), in increasing
+    arr[s] order,
+    after the permutation.  All draws come from the SHAKE-256 stream of domain "res.perm"."""
+    import copy
+    if n_pad < 0:
+        raise ValueError("negative padding")
+    m, mp = c.m, c.m + n_pad
+    dr = _Draws(seed, "res.perm")
+    arr = list(range(mp))
+    for i in range(mp - 1, 0, -1):
+        j = dr.below(i + 1)
+        arr[i], arr[j] = arr[j], arr[i]
+    pad_label = [dr.below(n_classes) for _ in range(n_pad)]
+    out = copy.copy(c)
+    out.m = mp
+    out.L = [np.stack([A[r] if r < m else np.zeros(c.b, dtype=np.int64) for r in arr]) for A in c.L]
+    out.masks = [np.array([mk[r] if r < m else 0 for r in arr], dtype=np.int64) for mk in c.masks]
+    out.Lfold = [(1 - 2 * mk)[:, None] * A for A, mk in zip(out.L, out.masks)]
+    out.selected = [[sel[r] if r < m else None for r in arr] for sel in c.selected]
+    out.codebook = [c.codebook[r] if r < m else pad_label[r - m] for r in arr]
+    out.tree_of_label = [c.tree_of_label[r] if r < m else -1 for r in arr]
+    out.meta = dict(c.meta, perm=list(arr))
+    out.B_in = mp + c.b + c.q - 2
+    out.W = next_pow2(out.B_in)
+    return out
+
+
 def generalized_diagonal(A: np.ndarray, k: int) -> np.ndarray:
     """d_k[j] = A[j][(j + k) mod n], j < rows (Section 4.1)."""
     rows, n = A.shape

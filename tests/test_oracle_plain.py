@@ -215,3 +215,39 @@ def test_parse_errors():
     for bad in ["", "a b\nB 0 1 L 0", "a\nL 3", "a b\nX 1", "a b\nL 0 L 1"]:
         with pytest.raises(F.ParseError):
             F.parse_forest(bad)
+
+
+# ---------------------------------------------------------------- result privacy (shuffle + padding)
+@pytest.mark.parametrize("seed,n_pad", [(0, 0), (1, 3), (2, 7), (3, 1)])
+@pytest.mark.parametrize("fold", [False, True])
+def test_privatized_result_is_shuffled_tree_walk(seed, n_pad, fold):
+    """Shuffled and padded result: slot s holds the tree walk's bit of label arr[s] (0 for padding),
+    arr is a permutation, the codebook follows it, padding labels are valid classes, and the decoded
+    label multiset equals the tree walk's."""
+    text, shape = _random_forest(40 + seed, trees=3, depth=4, feats=3, prec=4, classes=4)
+    names, trees = F.parse_forest(text)
+    c0 = C.compile_forest(text, shape.n_features, shape.precision)
+    c = C.privatize(c0, bytes([seed]) * 32, n_pad, len(names))
+    arr = c.meta["perm"]
+    assert sorted(arr) == list(range(c0.m + n_pad)) and c.m == c0.m + n_pad
+    assert all(c.codebook[s] == c0.codebook[r] for s, r in enumerate(arr) if r < c0.m)
+    assert all(0 <= c.codebook[s] < len(names) for s in range(c.m))
+    lay_slots = max(64, 4 * c.W)
+    queries = synth.gen_queries(lay_slots // c.W, shape.n_features, shape.precision, 2000 + seed)
+    res = S.run(c, queries, n_slots=lay_slots, fold_reshuffle=fold)
+    for k, x in enumerate(queries):
+        plain = F.evaluate(trees, list(x))
+        got = list(res["per_query"][k])
+        assert got == [plain[r] if r < c0.m else 0 for r in arr]
+        assert sorted(c.codebook[s] for s in range(c.m) if got[s]) == \
+            sorted(c0.codebook[i] for i in range(c0.m) if plain[i])
+
+
+def test_privatize_is_deterministic_and_seeded():
+    text, shape = _random_forest(77, trees=2, depth=4, feats=2, prec=4, classes=3)
+    c0 = C.compile_forest(text, 2, 4)
+    a = C.privatize(c0, b"\x05" * 32, 4, 3)
+    b = C.privatize(c0, b"\x05" * 32, 4, 3)
+    d = C.privatize(c0, b"\x06" * 32, 4, 3)
+    assert a.meta["perm"] == b.meta["perm"] and a.codebook == b.codebook
+    assert a.meta["perm"] != d.meta["perm"]
