@@ -50,6 +50,7 @@ def percentile(xs, p):
 KIND_NAMES = {0: "ntt_fwd_rows", 1: "ntt_fwd_cols", 2: "ntt_inv_rows", 3: "ntt_inv_cols", 4: "ks_inner",
               5: "bconv_colpass", 6: "elementwise", 7: "ntt_fwd_rows_moddown", 8: "ntt_fwd_rows_modswitch",
               9: "matmul_inner", 10: "ntt_inv_rows_gather"}
+STAGE_NAMES = ("comparison", "reshuffle", "levels", "aggregation")
 # kernel of each class (for the counter runs); class 6 is a family of small kernels and is not a roofline
 KIND_KERNELS = {0: "ntt_rowreg4_kernel<false>", 2: "ntt_rowreg4_kernel<true>", 4: "ks_inner2_kernel",
                 5: "ntt_bridge_kernel", 7: "ntt_rowfwd_finish_kernel<1>", 8: "ntt_rowfwd_finish_kernel<2>",
@@ -260,6 +261,82 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
+def micro_bench(args):
+    """Table 6 microbenchmarks: per forest, the median time of each stage of one evaluation
+    (comparison, reshuffle, levels, aggregation) over the timed steps, one encrypted query."""
+    import torch
+
+    from paper_2104_09583_amd import copse as C
+    from paper_2104_09583_amd import synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    stream = torch.cuda.Stream()
+    ctxs = {}
+    results = {}
+    for i, mf in enumerate(synth.TABLE6):
+        ch = synth.micro_chain(mf)
+        key = tuple(sorted(ch.items()))
+        if key not in ctxs:
+            ctxs[key] = C.Context(**ch)
+            ctxs[key].set_stream(stream.cuda_stream)
+        ctx = ctxs[key]
+        text = synth.gen_forest_exact(mf, 600 + i)
+        seed = synth.crypto_seed(f"COPSE-micro-{mf.name}")
+        comp, meta = C.forest_compile(text, mf.n_features, mf.precision, ch["log_n"])
+        keys = ctx.keygen(seed, C.compiled_rotations(meta))
+        evk = ctx.export_eval(keys)
+        model = ctx.model_encode(comp)
+        q = synth.gen_queries(1, mf.n_features, mf.precision, 700 + i)
+        qct = ctx.query_encrypt(keys, meta, q, seed, group=0)
+        for _ in range(args.warmup):
+            ctx.evaluate(model, evk, qct)
+        ctx.sync()
+        per_stage = {n: [] for n in STAGE_NAMES}
+        totals = []
+        ctx.profile_enable(True)
+        for _ in range(args.steps):
+            for k in range(C.PROF_KINDS):
+                ctx.profile_read(k, reset=True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.evaluate(model, evk, qct)
+            e1.record(stream)
+            e1.synchronize()
+            totals.append(e0.elapsed_time(e1))
+            for j, n in enumerate(STAGE_NAMES):
+                per_stage[n].append(ctx.profile_read(C.PROF_KERNEL_KINDS + j)["ms"])
+        ctx.profile_enable(False)
+        results[mf.name] = {"max_depth": mf.max_depth, "precision": mf.precision, "trees": len(mf.branches),
+                            "branches": sum(mf.branches), "b": meta.b, "q": meta.q, "d": meta.d,
+                            "median_ms": round(percentile(totals, 50), 3),
+                            "stages_median_ms": {n: round(percentile(v, 50), 3) for n, v in per_stage.items()}}
+        log(mf.name, results[mf.name])
+        for h in (qct, model, evk, keys, comp):
+            h.close()
+    # the paper's trends, as measured ratios
+    r = results
+    trends = {
+        "comparison_depth6_over_depth4": round(r["depth6"]["stages_median_ms"]["comparison"] /
+                                               r["depth4"]["stages_median_ms"]["comparison"], 3),
+        "levels_depth6_over_depth4": round(r["depth6"]["stages_median_ms"]["levels"] /
+                                           r["depth4"]["stages_median_ms"]["levels"], 3),
+        "levels_width677_over_width55": round(r["width677"]["stages_median_ms"]["levels"] /
+                                              r["width55"]["stages_median_ms"]["levels"], 3),
+        "reshuffle_width677_over_width55": round(r["width677"]["stages_median_ms"]["reshuffle"] /
+                                                 r["width55"]["stages_median_ms"]["reshuffle"], 3),
+        "comparison_prec16_over_prec8": round(r["prec16"]["stages_median_ms"]["comparison"] /
+                                              r["prec8"]["stages_median_ms"]["comparison"], 3),
+    }
+    tot = sum(v["median_ms"] for v in results.values())
+    out = {"metric": METRIC, "value": round(1000.0 * len(results) / tot, 3), "unit": "queries/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot / len(results), 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "f2_table6", "forests": [m.name for m in synth.TABLE6], "features": 2,
+                      "labels": 3, "queries_per_step": 1, "path": "single group, eager, stage events"},
+           "per_forest": results, "trends": trends, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +351,8 @@ def main():
                     help="evaluate eagerly instead of replaying the captured evaluation (HIP graph)")
     ap.add_argument("--n1-r", type=int, default=0, help="baby steps of the reshuffle product (0: compiler default)")
     ap.add_argument("--n1-l", type=int, default=0, help="baby steps of the level products (0: compiler default)")
+    ap.add_argument("--result-pad", type=int, default=-1,
+                    help="result privacy: shuffle the result slots and pad them with this many labels (-1: off)")
     ap.add_argument("--requests", type=int, default=240, help="serving mix: requests per offered rate")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.25, 0.5, 0.75, 1.0, 1.25],
                     help="serving mix: offered rates as fractions of the burst capacity")
@@ -285,6 +364,8 @@ def main():
 
     if args.workload == "c5_serve_mix":
         return serve_bench(args)
+    if args.workload == "f2_table6":
+        return micro_bench(args)
 
     import torch
 
@@ -300,8 +381,14 @@ def main():
     ctx = C.Context(**ch)
     stream = torch.cuda.Stream()
     ctx.set_stream(stream.cuda_stream)
-    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
-                                  n1_R=args.n1_r, n1_L=args.n1_l)
+    if args.result_pad < 0:
+        comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
+                                      n1_R=args.n1_r, n1_L=args.n1_l)
+    else:
+        # result privacy: shuffled result slots and codebook, padded with never-selected labels
+        comp, meta = C.forest_compile_private(text, w.shape.n_features, w.shape.precision, w.log_n,
+                                              synth.crypto_seed(f"COPSE-shuffle-{w.seed_index}"), args.result_pad,
+                                              fold=w.fold, n1_R=args.n1_r, n1_L=args.n1_l)
     rots = C.compiled_rotations(meta)
     keys = ctx.keygen(seed, rots)
     evk = ctx.export_eval(keys)
@@ -401,15 +488,25 @@ def main():
                                "avg_launch_us": round(1000 * prof[k]["ms"] / max(1, prof[k]["launches"]), 2),
                                "algorithmic_bytes_per_launch": round(prof[k]["bytes"] / max(1, prof[k]["launches"])),
                                "achieved_GBps": round(prof[k]["bytes"] / max(1e-9, prof[k]["ms"]) / 1e6, 1)}
-               for k in range(C.PROF_KINDS) if prof[k]["launches"] > 0}
+               for k in range(C.PROF_KERNEL_KINDS) if prof[k]["launches"] > 0}
+    stages = {STAGE_NAMES[k - C.PROF_KERNEL_KINDS]: round(prof[k]["ms"] / args.steps, 3)
+              for k in range(C.PROF_KERNEL_KINDS, C.PROF_KINDS) if prof[k]["launches"] > 0}
 
     cpu = None
     if not args.no_cpu_baseline:
-        # the oracle's plain forest evaluation checks the labels of what was timed
+        # the oracle's plain forest evaluation checks the labels of what was timed (decoded through the
+        # codebook, so that shuffled and padded results compare too)
         from oracle import forest as F
         _, trees = F.parse_forest(text)
-        want = np.array([F.evaluate(trees, list(x)) for x in queries[:nq_group]])
-        assert (first_bits == want).all(), "decrypted labels differ from plain evaluation"
+        book = C.compiled_codebook(comp)
+        oracle_book = F.codebook(trees)
+        for x, bits in zip(queries[:nq_group], first_bits):
+            plain = F.evaluate(trees, list(x))
+            if args.result_pad < 0:
+                assert list(bits) == list(plain), "decrypted labels differ from plain evaluation"
+            else:
+                assert sorted(book[s] for s in range(len(book)) if bits[s]) == \
+                    sorted(oracle_book[i] for i in range(len(plain)) if plain[i]), "decrypted labels differ"
         cpu = cpu_baseline(w, text, queries, seed)
 
     out = {
@@ -434,11 +531,13 @@ def main():
                    "N": 1 << w.log_n, "data_primes": ch["n_data_primes"], "special_primes": ch["alpha"],
                    "model": "plaintext" if not w.encrypted_model else "encrypted",
                    "b": meta.b, "m": meta.m, "q": meta.q, "d": meta.d, "W": meta.block_w,
+                   "result_pad": args.result_pad,
                    "n1_R": meta.n1_R, "n1_L": meta.n1_L},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "profiled_mean": round(sum(per_step) / len(per_step), 3)},
         "roofline": roofline,
         "kernels": kernels,
+        "stages_ms_per_step": stages,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

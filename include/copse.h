@@ -141,6 +141,21 @@ size_t copse_ctx_device_bytes(const copse_ctx* ctx);
 int copse_forest_compile(const char* text, size_t len, uint32_t n_features, uint32_t precision,
                          uint32_t log_n, int fold, uint32_t n1_R, uint32_t n1_L,
                          copse_compiled** out, copse_public_meta* meta);
+/* Result privacy (Section 6, "Returning classification bitvectors"): as
+ * copse_forest_compile, then the result slots are shuffled by a permutation
+ * drawn from `seed` (32 bytes, the model owner's) and padded with n_pad
+ * labels that are never selected, folded into the level matrices and masks
+ * (no extra homomorphic work, meta->m = labels + n_pad).  The client decodes
+ * with copse_compiled_codebook, which the model owner hands over instead of
+ * the forest's preorder label order.  Errors: as copse_forest_compile.
+ */
+int copse_forest_compile_private(const char* text, size_t len, uint32_t n_features, uint32_t precision,
+                                 uint32_t log_n, int fold, uint32_t n1_R, uint32_t n1_L, const uint8_t seed[32],
+                                 uint32_t n_pad, copse_compiled** out, copse_public_meta* meta);
+/* Class index (position in the label-name line) of each of the meta.m result
+ * slots, in slot order; *n receives meta.m; out may be null to query n.
+ * Errors: EINVAL (null, cap < m). */
+int copse_compiled_codebook(const copse_compiled* compiled, uint32_t* out, size_t cap, size_t* n);
 void copse_compiled_destroy(copse_compiled* c);
 /* Left rotations (slot offsets) whose Galois keys evaluation needs. */
 int copse_compiled_rotations(const copse_public_meta* meta, int32_t* out, size_t cap, size_t* n);
@@ -315,8 +330,10 @@ int copse_poly_mul(copse_ctx* ctx, int prime, const uint64_t* a, const uint64_t*
  * conversion (fused with the column passes where available), 6 = other
  * elementwise kernels, 7 = forward row pass with the ModDown finish,
  * 8 = forward row pass with the modulus-switch finish, 9 = MatMul inner sums,
- * 10 = inverse row pass reading ciphertext rows in place.  reset clears the
- * counters. */
+ * 10 = inverse row pass reading ciphertext rows in place; 11..14 = the
+ * stages of an evaluation (comparison, reshuffle product, level products with
+ * masks, product tree with the final switch: the breakdown of Section 8),
+ * bracketed on the evaluating stream, bytes 0.  reset clears the counters. */
 int copse_profile_enable(copse_ctx* ctx, int on);
 int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
                        double* bytes, int reset);

@@ -29,8 +29,10 @@ OP_ADD, OP_SUB, OP_TENSOR, OP_RELIN, OP_MODSWITCH, OP_MUL, OP_ROTATE, OP_MUL_PLA
 
 (PROF_NTT_FWD_ROWS, PROF_NTT_FWD_COLS, PROF_NTT_INV_ROWS, PROF_NTT_INV_COLS, PROF_KS_INNER, PROF_BCONV,
  PROF_ELEMENTWISE, PROF_NTT_FWD_ROWS_MODDOWN, PROF_NTT_FWD_ROWS_MODSWITCH, PROF_MATMUL_INNER,
- PROF_NTT_INV_ROWS_GATHER) = range(11)
-PROF_KINDS = 11
+ PROF_NTT_INV_ROWS_GATHER, PROF_STAGE_COMPARISON, PROF_STAGE_RESHUFFLE, PROF_STAGE_LEVELS,
+ PROF_STAGE_AGGREGATION) = range(15)
+PROF_KERNEL_KINDS = 11
+PROF_KINDS = 15
 
 
 class CopseError(RuntimeError):
@@ -85,6 +87,9 @@ def lib() -> ctypes.CDLL:
         "copse_ctx_sync": [P],
         "copse_forest_compile": [ctypes.c_char_p, sz, u32, u32, u32, i32, u32, u32, PP, ctypes.POINTER(Meta)],
         "copse_compiled_rotations": [ctypes.POINTER(Meta), i32p, sz, ctypes.POINTER(sz)],
+        "copse_forest_compile_private": [ctypes.c_char_p, sz, u32, u32, u32, i32, u32, u32, u8p, u32, PP,
+                                         ctypes.POINTER(Meta)],
+        "copse_compiled_codebook": [P, u32p, sz, ctypes.POINTER(sz)],
         "copse_keygen": [P, u8p, i32p, sz, i32, PP],
         "copse_keys_export_eval": [P, P, PP],
         "copse_model_encode": [P, P, P, i32, u8p, PP],
@@ -388,6 +393,24 @@ def forest_compile(text: str, n_features: int, precision: int, log_n: int, fold:
     check(lib().copse_forest_compile(raw, len(raw), n_features, precision, log_n, int(fold), n1_R, n1_L,
                                      ctypes.byref(h), ctypes.byref(meta)))
     return Compiled(h), meta
+
+
+def forest_compile_private(text: str, n_features: int, precision: int, log_n: int, seed: bytes, n_pad: int,
+                           fold: bool = False, n1_R: int = 0, n1_L: int = 0):
+    raw = text.encode()
+    h = ctypes.c_void_p()
+    meta = Meta()
+    check(lib().copse_forest_compile_private(raw, len(raw), n_features, precision, log_n, int(fold), n1_R, n1_L,
+                                             _u8(seed), n_pad, ctypes.byref(h), ctypes.byref(meta)))
+    return Compiled(h), meta
+
+
+def compiled_codebook(compiled: Compiled) -> List[int]:
+    n = ctypes.c_size_t()
+    check(lib().copse_compiled_codebook(compiled.ptr, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(1, n.value), dtype=np.uint32)
+    check(lib().copse_compiled_codebook(compiled.ptr, _arr(out, ctypes.c_uint32), out.size, ctypes.byref(n)))
+    return [int(x) for x in out[:n.value]]
 
 
 def compiled_rotations(meta: Meta) -> List[int]:

@@ -198,6 +198,33 @@ int copse_forest_compile(const char* text, size_t len, uint32_t n_features, uint
   });
 }
 
+int copse_forest_compile_private(const char* text, size_t len, uint32_t n_features, uint32_t precision,
+                                 uint32_t log_n, int fold, uint32_t n1_R, uint32_t n1_L, const uint8_t seed[32],
+                                 uint32_t n_pad, copse_compiled** out, copse_public_meta* meta) {
+  return guarded([&] {
+    NEED(text && out && seed);
+    *out = nullptr;
+    if (log_n < 4 || log_n > 17) fail(COPSE_EINVAL, "log_n must be in [4, 17]");
+    auto cc = std::make_unique<copse_compiled>();
+    cc->c = compile_forest(text, len, n_features, precision, log_n, fold, n1_R, n1_L);
+    privatize(*cc->c, seed, n_pad);
+    if (meta) *meta = cc->c->meta;
+    *out = cc.release();
+  });
+}
+
+int copse_compiled_codebook(const copse_compiled* compiled, uint32_t* out, size_t cap, size_t* n) {
+  return guarded([&] {
+    NEED(compiled && n);
+    const auto& book = compiled->c->codebook;
+    *n = book.size();
+    if (out) {
+      if (cap < book.size()) fail(COPSE_EINVAL, "buffer too small");
+      for (size_t i = 0; i < book.size(); ++i) out[i] = (uint32_t)book[i];
+    }
+  });
+}
+
 void copse_compiled_destroy(copse_compiled* c) { delete c; }
 
 int copse_compiled_rotations(const copse_public_meta* meta, int32_t* out, size_t cap, size_t* n) {

@@ -193,7 +193,65 @@ std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t 
   while ((1u << tree) < d) ++tree;
   M.depth = seccomp + (fold ? 1 : 2) + tree;
   C->B_in = B_in;
+  for (int ln : C->label_nodes) C->codebook.push_back(nodes[ln].label);
+  for (uint32_t i = 0; i < m; ++i) C->perm.push_back((int)i);
   return C;
+}
+
+// Result privacy (Section 6, "Returning classification bitvectors"): the server shuffles the result
+// bitvector and the codebook by one random permutation and pads both with n_pad labels that are never
+// selected; here the shuffle is folded into the level products by permuting the rows of every level
+// matrix and mask (a padding row is all zero with mask 0, so its level results and its product are 0),
+// at no extra homomorphic cost.  Slot s takes original row arr[s]: arr starts as the identity on
+// m + n_pad rows and is shuffled by Fisher-Yates (i from m + n_pad - 1 down to 1: swap arr[i] with
+// arr[j], j drawn below i + 1); then one class is drawn per padding row (increasing row order) below
+// the number of label names.  Draws: 8-byte little-endian words of the SHAKE-256 stream of domain
+// "res.perm" (object 0, limb 0), masked to the bound's bit length and rejected at or above it.
+void privatize(Compiled& C, const uint8_t seed[32], uint32_t n_pad) {
+  auto& M = C.meta;
+  const uint32_t m = M.m, mp = m + n_pad;
+  if ((uint64_t)mp + M.b + M.q > (1ULL << 31)) fail(COPSE_EINVAL, "padding too large");
+  ShakeStream st(seed, "res.perm", 0, 0);
+  auto below = [&](uint64_t bound) -> uint64_t {
+    int bits = 64 - __builtin_clzll(bound);
+    const uint64_t mask = bits >= 64 ? ~0ULL : ((1ULL << bits) - 1);
+    while (true) {
+      uint8_t b[8];
+      st.read(b, 8);
+      uint64_t w = 0;
+      for (int k = 0; k < 8; ++k) w |= (uint64_t)b[k] << (8 * k);
+      w &= mask;
+      if (w < bound) return w;
+    }
+  };
+  std::vector<int> arr(mp);
+  for (uint32_t i = 0; i < mp; ++i) arr[i] = (int)i;
+  for (uint32_t i = mp - 1; i >= 1 && mp > 1; --i) std::swap(arr[i], arr[below(i + 1)]);
+  const uint64_t classes = std::max<size_t>(1, C.label_names.size());
+  std::vector<int> pad_label(n_pad);
+  for (uint32_t r = 0; r < n_pad; ++r) pad_label[r] = (int)below(classes);
+  std::vector<std::vector<int>> sel(C.sel.size(), std::vector<int>(mp)), mask(C.mask.size(), std::vector<int>(mp));
+  std::vector<int> book(mp), perm(mp);
+  for (uint32_t s = 0; s < mp; ++s) {
+    const int r = arr[s];
+    for (size_t l = 0; l < C.sel.size(); ++l) {
+      sel[l][s] = r < (int)m ? C.sel[l][r] : -1;
+      mask[l][s] = r < (int)m ? C.mask[l][r] : 0;
+    }
+    book[s] = r < (int)m ? C.codebook[r] : pad_label[r - m];
+    perm[s] = r < (int)m ? C.perm[r] : r;
+  }
+  C.sel = std::move(sel);
+  C.mask = std::move(mask);
+  C.codebook = std::move(book);
+  C.perm = std::move(perm);
+  M.m = mp;
+  C.B_in = mp + M.b + M.q - 2;
+  M.block_w = pow2_ceil(C.B_in);
+  const uint64_t N = 1ULL << M.log_n;
+  if (M.block_w > N / 2) fail(COPSE_ECAPACITY, "query block of " + std::to_string(M.block_w) +
+                                                  " slots exceeds a slot row of " + std::to_string(N / 2));
+  M.queries_per_ct = (uint32_t)(N / M.block_w);
 }
 
 std::vector<int32_t> needed_rotations(const copse_public_meta& M) {

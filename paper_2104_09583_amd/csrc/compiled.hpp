@@ -27,6 +27,8 @@ struct Compiled {
   std::vector<int> padded;                  // padded slot -> branch index or -1
   std::vector<std::vector<int>> sel;        // [level-1][label] -> branch index or -1
   std::vector<std::vector<int>> mask;       // [level-1][label]
+  std::vector<int> codebook;                // class of each result slot
+  std::vector<int> perm;                    // result slot -> original label row (>= labels: padding)
   uint32_t B_in = 0;
 };
 
@@ -34,6 +36,8 @@ uint32_t pow2_ceil(uint32_t x);
 uint32_t baby_steps(uint32_t n);
 std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t F, uint32_t prec, uint32_t log_n,
                                          int fold, uint32_t n1R, uint32_t n1L);
+// result privacy: shuffle the result slots and pad them with never-selected labels (see compile.cpp)
+void privatize(Compiled& C, const uint8_t seed[32], uint32_t n_pad);
 std::vector<int32_t> needed_rotations(const copse_public_meta& M);
 void replicate_blocks(const copse_public_meta& M, size_t N, const std::vector<int64_t>& vec,
                       std::vector<uint64_t>& slots, uint64_t t);

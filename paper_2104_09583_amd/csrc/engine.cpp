@@ -49,12 +49,67 @@ static const int2* block_rows(Context& c, int np, int nl) {
 std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in,
                              const std::vector<const double*>* adds = nullptr, int add_np = 0) {
   std::vector<SCt> out(in.size());
+  const size_t N = c.N;
+  for (const Ct* x : in)
+    if (x->level == 0) fail(COPSE_ECAPACITY, "modulus chain exhausted");
+  if (bridge_supported(c, 1)) {
+    // one set of launches per level and polynomial count (the kernels also take mixed levels, which
+    // measured no faster: the small switches are latency-bound either way)
+    std::map<std::pair<int, int>, std::vector<size_t>> by_np;
+    for (size_t i = 0; i < in.size(); ++i) by_np[{-in[i]->level, in[i]->npolys}].push_back(i);
+    for (auto& kv : by_np) {
+      const int np = kv.first.second;
+      std::vector<size_t> idx = kv.second;
+      const int J = (int)idx.size();
+      size_t wrows = 0;
+      for (size_t j : idx) wrows += (size_t)np * in[j]->level;
+      DBuf top(&c, (size_t)J * np * N);
+      DBuf w(&c, wrows * N);
+      std::vector<double*> po;
+      std::vector<const double*> pi, pa, pw, tabs;
+      std::vector<int> lv;
+      std::vector<BridgeDesc> ds;
+      size_t woff = 0;
+      for (int j0 = 0; j0 < J;) {
+        const int l = in[idx[j0]]->level;
+        int j1 = j0;
+        while (j1 < J && in[idx[j1]]->level == l) ++j1;
+        KSTables& T = c.kstab(l);
+        auto outs = alloc_batch(c, j1 - j0, l - 1, np);
+        std::vector<int2> ir{make_int2(0, l)}, orr;
+        for (int i = 0; i < l; ++i) orr.push_back(make_int2(i, i));
+        BridgeDesc d{rows_cached(c, "msout:" + std::to_string(l), orr), rows_cached(c, "msin:" + std::to_string(l), ir),
+                     T.d_ms + 1, nullptr, l, 1, 0, 0};
+        d.in = top.get() + (size_t)j0 * np * N;
+        d.out = w.get() + woff * N;
+        d.in_bs = N;
+        d.out_bs = (size_t)l * N;
+        d.nz = (j1 - j0) * np;
+        ds.push_back(d);
+        for (int j = j0; j < j1; ++j) {
+          const size_t g = idx[j];
+          po.push_back(outs[j - j0]->data());
+          pi.push_back(in[g]->data());
+          if (adds) pa.push_back((*adds)[g]);
+          pw.push_back(w.get() + woff * N);
+          tabs.push_back(T.d_ms);
+          lv.push_back(l);
+          out[g] = outs[j - j0];
+          woff += (size_t)np * l;
+        }
+        j0 = j1;
+      }
+      // top rows read in place by the inverse row pass; the forward row pass ends the switch
+      launch_ntt_inv_rows_gather(c, top.get(), pi, np, 0, 0, -2, &lv);
+      launch_bridge_set(c, 1, nullptr, nullptr, ds, 0, 0, 0);
+      launch_ntt_fwd_rows_ms_finish(c, po, pi, pw, lv, tabs, np, adds ? &pa : nullptr, add_np);
+    }
+    return out;
+  }
   std::map<std::pair<int, int>, std::vector<size_t>> groups;
   for (size_t i = 0; i < in.size(); ++i) groups[{in[i]->level, in[i]->npolys}].push_back(i);
-  const size_t N = c.N;
   for (auto& kv : groups) {
     const int l = kv.first.first, np = kv.first.second;
-    if (l == 0) fail(COPSE_ECAPACITY, "modulus chain exhausted");
     const auto& idx = kv.second;
     const int J = (int)idx.size();
     KSTables& T = c.kstab(l);
@@ -69,29 +124,16 @@ std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in,
       if (adds) pa.push_back((*adds)[idx[j]]);
       out[idx[j]] = outs[j];
     }
-    if (bridge_supported(c, 1)) {
-      // top rows read in place by the inverse row pass; the forward row pass ends the switch
-      std::vector<int2> ir{make_int2(0, l)}, orr;
-      for (int i = 0; i < l; ++i) orr.push_back(make_int2(i, i));
-      launch_ntt_inv_rows_gather(c, top.get(), pi, np, (size_t)(l + 1) * N, (size_t)l * N, l);
-      launch_bridge(c, 1, w.get(), rows_cached(c, "msout:" + std::to_string(l), orr), l, top.get(),
-                    rows_cached(c, "msin:" + std::to_string(l), ir), 1, T.d_ms + 1, nullptr, J * np, N,
-                    (size_t)l * N);
-      launch_ntt_fwd_rows_ms_finish(c, po, pi, w.get(), np, l, T.d_ms, adds ? &pa : nullptr, add_np);
-      continue;
-    }
-    {
-      std::vector<const double*> src;
-      for (size_t j : idx)
-        for (int k = 0; k < np; ++k) src.push_back(in[j]->poly(k, N) + (size_t)l * N);
-      launch_gather(c, top.get(), src, 1);
-      std::vector<int2> tr;
-      for (int z = 0; z < J * np; ++z) tr.push_back(make_int2(z, l));
-      const int2* trows = rows_cached(c, "top:" + std::to_string(J * np) + ":" + std::to_string(l), tr);
-      launch_ntt_inv(c, top.get(), trows, J * np);
-      launch_ms_prep(c, w.get(), top.get(), J * np, l, T.d_ms);
-      launch_ntt_fwd(c, w.get(), block_rows(c, J * np, l), J * np * l);
-    }
+    std::vector<const double*> src;
+    for (size_t j : idx)
+      for (int k = 0; k < np; ++k) src.push_back(in[j]->poly(k, N) + (size_t)l * N);
+    launch_gather(c, top.get(), src, 1);
+    std::vector<int2> tr;
+    for (int z = 0; z < J * np; ++z) tr.push_back(make_int2(z, l));
+    const int2* trows = rows_cached(c, "top:" + std::to_string(J * np) + ":" + std::to_string(l), tr);
+    launch_ntt_inv(c, top.get(), trows, J * np);
+    launch_ms_prep(c, w.get(), top.get(), J * np, l, T.d_ms);
+    launch_ntt_fwd(c, w.get(), block_rows(c, J * np, l), J * np * l);
     launch_ms_finish_multi(c, po, pi, w.get(), np, l, T.d_ms, adds ? &pa : nullptr, add_np);
   }
   return out;
@@ -449,7 +491,16 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
       if (x->npolys != 2 || x->level != c.L) fail(COPSE_EINVAL, "query ciphertexts must be fresh (top level)");
   }
   auto view = [](const Ct* x) { return SCt(const_cast<Ct*>(x), [](Ct*) {}); };
+  // stage timings for the profiler (comparison, reshuffle, levels, aggregation; Section 8's breakdown)
+  hipEvent_t stage_ev = nullptr;
+  int stage = -1;
+  auto next_stage = [&](int s) {
+    if (stage >= 0) prof_end(c, kProfStage0 + stage, stage_ev, 0.0);
+    stage = s;
+    if (s >= 0) prof_begin(c, kProfStage0 + s, &stage_ev);
+  };
   // 1. comparison
+  next_stage(0);
   std::vector<std::vector<SCt>> eq(p, std::vector<SCt>(G)), lt(p, std::vector<SCt>(G));
   if (!M.encrypted) {
     const int L = c.L, nl = L + 1;
@@ -533,6 +584,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
   for (auto& x : dec)
     if (x->level != M.dec_level) fail(COPSE_EINVAL, "internal: comparison ended at an unexpected level");
   // 2. reshuffle
+  next_stage(1);
   std::vector<SCt> src = dec;
   if (!M.meta.fold) {
     const MatPlan& P = M.plan_R;
@@ -544,6 +596,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
     src = b_matmul_many(c, k, {&P}, P.d_tab, (int)P.rots.size(), B.get(), G, l)[0];
   }
   // 3. levels: one set of hoisted baby rotations shared by every level
+  next_stage(2);
   std::vector<std::vector<SCt>> lv(M.meta.d);
   {
     const int l = src[0]->level;
@@ -566,6 +619,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
                        M.masks[0].ct ? 2 : 1);
   }
   // 4. product tree
+  next_stage(3);
   while (lv.size() > 1) {
     std::vector<std::pair<SCt, SCt>> pairs;
     for (size_t i = 0; i + 1 < lv.size(); i += 2)
@@ -581,6 +635,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
     lv = std::move(nxt);
   }
   std::vector<SCt> res = b_down(c, lv[0], std::vector<int>(G, 0));
+  next_stage(-1);
   std::vector<CtPtr> out;
   for (int b = 0; b < G; ++b) out.push_back(std::make_unique<Ct>(*res[b]));   // shares the storage
   return out;

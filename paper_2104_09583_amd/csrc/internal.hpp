@@ -139,7 +139,9 @@ using CtPtr = std::unique_ptr<Ct>;
 // Profiling counters per kernel class: 0 forward NTT (row pass), 1 forward NTT (column pass),
 // 2 inverse NTT (row pass), 3 inverse NTT (column pass), 4 key-switch inner product,
 // 5 base conversion, 6 elementwise.
-constexpr int kProfKinds = 11;
+// kernel classes 0..10; 11..14: the evaluation's stages (comparison, reshuffle, levels, aggregation)
+constexpr int kProfStage0 = 11;
+constexpr int kProfKinds = 15;
 struct ProfSlot {
   uint64_t launches = 0;
   double ms = 0;
@@ -208,16 +210,20 @@ bool bridge_supported(const Context& c, int n_in);
 void launch_ntt_inv_rows(Context& c, double* base, const int2* rows, int nrows);
 void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows);
 // inverse row pass reading row r of job j from src[j] + r * src_stride + src_off (r < rpj), writing the
-// jobs' rows contiguously to dst; prime r, or prime_fixed when >= 0
+// jobs' rows contiguously to dst; prime r, or prime_fixed when >= 0; prime_fixed -2: row r is the top
+// limb (levels[j]) of polynomial r of job j
 void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const double*>& src, int rpj,
-                                size_t src_stride, size_t src_off, int prime_fixed);
+                                size_t src_stride, size_t src_off, int prime_fixed,
+                                const std::vector<int>* levels = nullptr);
 // forward row pass of the ModDown rows w fused with the ModDown finish (as launch_md_finish2)
 void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
                                    const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE,
                                    int nl, const double* pinv, const double* tpinv, int add_mode);
-// forward row pass of the modulus-switch rows w fused with the switch's finish (as launch_ms_finish_multi)
+// forward row pass of the modulus-switch rows fused with the switch's finish; job j switches from
+// levels[j], its rows w[j] = [np][levels[j]][N], its table tabs[j] (as launch_ms_finish_multi)
 void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
-                                   const double* w, int np, int level, const double* tab,
+                                   const std::vector<const double*>& w, const std::vector<int>& levels,
+                                   const std::vector<const double*>& tabs, int np,
                                    const std::vector<const double*>* add, int add_np);
 // One coefficient map of the fused column pass: rows of the input block (index, prime), rows of the
 // output block, per-input multipliers and the [n_in][n_out] matrix (mode 0).  chunk0 / ochunk are set by
@@ -230,6 +236,11 @@ struct BridgeDesc {
   const double* mat;
   int n_out, n_in;
   int chunk0, ochunk;
+  // set by launch_bridge_set when left empty: the blocks and batch of this map
+  const double* in = nullptr;
+  double* out = nullptr;
+  size_t in_bs = 0, out_bs = 0;
+  int nz = -1;
 };
 struct BridgeSet {
   static constexpr int kMax = 4;
@@ -294,6 +305,7 @@ constexpr int kPack = 64;
 struct Pack { const double* p[kPack]; };
 struct MPack { double* p[kPack]; };
 struct GPack { uint64_t g[kPack]; };
+struct IPack { int v[kPack]; };
 struct KsJob2 {
   const double* in;      // input poly (NTT form, nl limbs): the digit's own limbs
   const double* ext;     // [D][nE][N] ModUp output (target rows only)

@@ -511,16 +511,21 @@ __global__ __launch_bounds__(512) void ntt_rowreg4_kernel(double* __restrict__ b
 // Inverse row pass reading straight from ciphertexts (no gather copy): row r of the launch is row
 // r % rpj of job r / rpj, read from src.p[job] + (r % rpj) * src_stride + src_off and written to
 // dst + r * N; its prime is prime_fixed, or r % rpj when prime_fixed < 0.
-__global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restrict__ dst, Pack src, int rpj,
+__global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restrict__ dst, Pack src, IPack lv, int rpj,
                                                                size_t src_stride, size_t src_off, int prime_fixed,
                                                                const DevPrime* __restrict__ P, int logN, int S1) {
   __shared__ double sh[kLdsTile4];
   const int r = blockIdx.y;
   const int j = r / rpj, sub = r % rpj;
-  const DevPrime pr = P[prime_fixed >= 0 ? prime_fixed : sub];
   const size_t N = (size_t)1 << logN;
+  // prime_fixed -2: the top limb of job j's polynomial sub, job j at level lv[j]
+  const int top = lv.v[j];
+  const int prime = prime_fixed == -2 ? top : prime_fixed >= 0 ? prime_fixed : sub;
+  const size_t stride = prime_fixed == -2 ? (size_t)(top + 1) * N : src_stride;
+  const size_t off = prime_fixed == -2 ? (size_t)top * N : src_off;
+  const DevPrime pr = P[prime];
   const size_t t0 = (size_t)blockIdx.x * 4096;
-  const double* a = src.p[j] + (size_t)sub * src_stride + src_off + t0;
+  const double* a = src.p[j] + (size_t)sub * stride + off + t0;
   double x[8];
   row4_inv_tile(a, t0, S1, pr, sh, x);
   double* o = dst + (size_t)r * N + t0;
@@ -538,25 +543,30 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
 // mul/tmul are P^-1 and t P^-1 per limb (kMode 1) or the modulus-switch table (q_l^-1 at 2 + 2 i,
 // t q_l^-1 at 3 + 2 i).  Outputs are canonical.
 template <int kMode>
-__global__ __launch_bounds__(512) void ntt_rowfwd_finish_kernel(MPack out, Pack in, Pack add, GPack gal,
+__global__ __launch_bounds__(512) void ntt_rowfwd_finish_kernel(MPack out, Pack in, Pack add, GPack gal, Pack ws,
+                                                               Pack tabs, IPack lvs,
                                                                const double* __restrict__ acc,
-                                                               const double* __restrict__ w, int nE, int nl,
+                                                               const double* __restrict__ w, int nE, int nl_,
                                                                int np, int add_mode, int add_np,
                                                                const double* __restrict__ mul,
                                                                const double* __restrict__ tmul,
                                                                const DevPrime* __restrict__ P, int logN, int S1) {
   __shared__ double sh[kLdsTile4];
   const int i = blockIdx.y, z = blockIdx.z;
+  const int j = kMode == 1 ? (z >> 1) : z / np, k = kMode == 1 ? (z & 1) : z % np;
+  // kMode 2: job j switches from level lv[j]: it writes nl = lv[j] limbs per poly below an input with nl + 1
+  const int nl = kMode == 1 ? nl_ : lvs.v[j];
+  if (i >= nl) return;   // uniform per workgroup, before any barrier
   const DevPrime pr = P[i];
   const size_t N = (size_t)1 << logN;
   const size_t t0 = (size_t)blockIdx.x * 4096;
   const int t = threadIdx.x;
   double x[8];
-  row4_fwd_tile(w + ((size_t)z * nl + i) * N + t0, t0, S1, pr, sh, x);
-  const int j = kMode == 1 ? (z >> 1) : z / np, k = kMode == 1 ? (z & 1) : z % np;
-  const double m1 = kMode == 1 ? mul[i] : mul[2 + 2 * i];
-  const double m2 = kMode == 1 ? tmul[i] : mul[3 + 2 * i];
-  // kMode 2 writes l = nl limbs per poly below an input with nl + 1
+  const double* wrow = kMode == 1 ? w + ((size_t)z * nl + i) * N : ws.p[j] + ((size_t)k * nl + i) * N;
+  row4_fwd_tile(wrow + t0, t0, S1, pr, sh, x);
+  const double* tab = kMode == 1 ? nullptr : tabs.p[j];
+  const double m1 = kMode == 1 ? mul[i] : tab[2 + 2 * i];
+  const double m2 = kMode == 1 ? tmul[i] : tab[3 + 2 * i];
   const size_t orow = ((size_t)k * nl + i) * N;
   const double* yrow = kMode == 1 ? acc + ((size_t)z * nE + i) * N : in.p[j] + ((size_t)k * (nl + 1) + i) * N;
   const uint64_t g = kMode == 1 ? gal.g[j] : 1;
@@ -707,9 +717,7 @@ constexpr int kBridgeIn = 4;
 // A workgroup is 64 columns x 4 waves: wave k runs the inverse stages of input row k (k < n_in) and
 // leaves [coef * mult_k] in LDS; then the four waves take the outputs of the block's chunk in turn.
 template <int S1, int kMode>
-__global__ __launch_bounds__(256) void ntt_bridge_kernel(double* __restrict__ out_base, const double* __restrict__ in_base,
-                                                        BridgeSet set, const DevPrime* __restrict__ P, int logN,
-                                                        size_t in_bs, size_t out_bs) {
+__global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const DevPrime* __restrict__ P, int logN) {
   constexpr int R = 1 << S1;
   __shared__ double ys[kBridgeIn][R][64];
   const size_t N = (size_t)1 << logN;
@@ -724,9 +732,10 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(double* __restrict__ ou
   for (int k = 1; k < BridgeSet::kMax; ++k)
     if (k < set.n && (int)blockIdx.y >= set.d[k].chunk0) di = k;
   const BridgeDesc& d = set.d[di];
+  if ((int)blockIdx.z >= d.nz) return;   // uniform per workgroup, before the barrier
   const int n_in = d.n_in, n_out = d.n_out;
-  const double* in = in_base + (size_t)blockIdx.z * in_bs;
-  double* out = out_base + (size_t)blockIdx.z * out_bs;
+  const double* in = d.in + (size_t)blockIdx.z * d.in_bs;
+  double* out = d.out + (size_t)blockIdx.z * d.out_bs;
   if (wv < n_in && active) {
     const int2 irow = d.in_rows[wv];
     const DevPrime& pk = P[irow.y];
@@ -794,41 +803,45 @@ bool bridge_supported(const Context& c, int n_in) { return c.log_n >= 13 && c.lo
 
 void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_base, std::vector<BridgeDesc> descs,
                        int batch, size_t in_bs, size_t out_bs) {
-  if (batch <= 0 || descs.empty()) return;
-  if ((int)descs.size() > BridgeSet::kMax) fail(COPSE_EINVAL, "internal: too many conversions in one launch");
+  if (descs.empty()) return;
   const int S1 = (int)c.log_n - 12;
   const unsigned C = (unsigned)(c.N >> S1);
   const unsigned xb = (C + 63) / 64;
-  BridgeSet set{};
-  set.n = (int)descs.size();
-  int rows_y = 0;
-  double bytes = 0;
-  for (int k = 0; k < set.n; ++k) {
-    BridgeDesc d = descs[k];
-    if (!bridge_supported(c, d.n_in)) fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
-    if (mode == 1 && d.n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
-    if (d.n_out <= 0) fail(COPSE_EINVAL, "internal: conversion without outputs");
-    // at least ~512 workgroups (2048 waves) when the batch is small, by splitting the outputs into chunks
-    // of at least 4 (one per wave)
-    int chunks = 1;
-    while (chunks * 8 <= d.n_out && (size_t)xb * batch * chunks * set.n < 512) chunks *= 2;
-    d.ochunk = (d.n_out + chunks - 1) / chunks;
-    chunks = (d.n_out + d.ochunk - 1) / d.ochunk;
-    d.chunk0 = rows_y;
-    rows_y += chunks;
-    set.d[k] = d;
-    bytes += (double)(d.n_out + d.n_in) * batch * (double)c.N * 8.0;   // inputs counted once
-  }
-  hipEvent_t ev;
-  prof_begin(c, 5, &ev);
-  for (int first = 0; first < batch; first += kMaxGridY) {
-    const int cnt = std::min(kMaxGridY, batch - first);
-    dim3 grid(xb, rows_y, cnt), blk(256);
-    const double* ib = in_base + (size_t)first * in_bs;
-    double* ob = out_base + (size_t)first * out_bs;
-#define COPSE_BRIDGE(S, M)                                                                                       \
-  hipLaunchKernelGGL((ntt_bridge_kernel<S, M>), grid, blk, 0, c.stream, ob, ib, set, c.d_primes, (int)c.log_n, \
-                     in_bs, out_bs)
+  for (size_t first = 0; first < descs.size(); first += BridgeSet::kMax) {
+    BridgeSet set{};
+    set.n = (int)std::min<size_t>(BridgeSet::kMax, descs.size() - first);
+    int rows_y = 0, zmax = 0;
+    double bytes = 0;
+    for (int k = 0; k < set.n; ++k) {
+      BridgeDesc d = descs[first + k];
+      if (d.nz < 0) {
+        d.in = in_base;
+        d.out = out_base;
+        d.in_bs = in_bs;
+        d.out_bs = out_bs;
+        d.nz = batch;
+      }
+      if (d.nz > kMaxGridY) fail(COPSE_EINVAL, "internal: batch too large for one fused column pass");
+      if (!bridge_supported(c, d.n_in)) fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
+      if (mode == 1 && d.n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
+      if (d.n_out <= 0) fail(COPSE_EINVAL, "internal: conversion without outputs");
+      // at least ~512 workgroups (2048 waves) when the batch is small, by splitting the outputs into chunks
+      // of at least 4 (one per wave)
+      int chunks = 1;
+      while (chunks * 8 <= d.n_out && (size_t)xb * d.nz * chunks * set.n < 512) chunks *= 2;
+      d.ochunk = (d.n_out + chunks - 1) / chunks;
+      chunks = (d.n_out + d.ochunk - 1) / d.ochunk;
+      d.chunk0 = rows_y;
+      rows_y += chunks;
+      zmax = std::max(zmax, d.nz);
+      set.d[k] = d;
+      bytes += (double)(d.n_out + d.n_in) * d.nz * (double)c.N * 8.0;   // inputs counted once
+    }
+    if (zmax == 0) continue;
+    hipEvent_t ev;
+    prof_begin(c, 5, &ev);
+    dim3 grid(xb, rows_y, zmax), blk(256);
+#define COPSE_BRIDGE(S, M) hipLaunchKernelGGL((ntt_bridge_kernel<S, M>), grid, blk, 0, c.stream, set, c.d_primes, (int)c.log_n)
     if (mode == 0) {
       switch (S1) {
         case 1: COPSE_BRIDGE(1, 0); break;
@@ -846,16 +859,24 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
     }
 #undef COPSE_BRIDGE
     COPSE_HIP(hipGetLastError());
+    prof_end(c, 5, ev, bytes);
   }
-  prof_end(c, 5, ev, bytes);
 }
 
 void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
                    const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,
                    size_t out_bs) {
   if (n_out <= 0 || batch <= 0) return;
-  launch_bridge_set(c, mode, out_base, in_base, {BridgeDesc{out_rows, in_rows, mult, mat, n_out, n_in, 0, 0}}, batch,
-                    in_bs, out_bs);
+  // batches beyond one launch's z range run in slices
+  for (int first = 0; first < batch; first += kMaxGridY) {
+    BridgeDesc d{out_rows, in_rows, mult, mat, n_out, n_in, 0, 0};
+    d.in = in_base + (size_t)first * in_bs;
+    d.out = out_base + (size_t)first * out_bs;
+    d.in_bs = in_bs;
+    d.out_bs = out_bs;
+    d.nz = std::min(kMaxGridY, batch - first);
+    launch_bridge_set(c, mode, out_base, in_base, {d}, batch, in_bs, out_bs);
+  }
 }
 
 // row passes alone (the column passes are done by the bridge): inverse rows leave signed residues for
@@ -889,17 +910,22 @@ void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows) 
 }
 
 void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const double*>& src, int rpj,
-                                size_t src_stride, size_t src_off, int prime_fixed) {
+                                size_t src_stride, size_t src_off, int prime_fixed, const std::vector<int>* levels) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  if (prime_fixed == -2 && (!levels || levels->size() != src.size())) fail(COPSE_EINVAL, "internal: levels");
   const int per = std::max(1, std::min(kPack, kMaxGridY / std::max(1, rpj)));
   for (size_t first = 0; first < src.size(); first += per) {
     const int cnt = (int)std::min<size_t>(per, src.size() - first);
     Pack pk;
-    for (int k = 0; k < cnt; ++k) pk.p[k] = src[first + k];
+    IPack lv{};
+    for (int k = 0; k < cnt; ++k) {
+      pk.p[k] = src[first + k];
+      lv.v[k] = levels ? (*levels)[first + k] : 0;
+    }
     hipEvent_t ev;
     prof_begin(c, 10, &ev);
     hipLaunchKernelGGL(ntt_rowinv_gather_kernel, dim3((unsigned)(c.N / 4096), cnt * rpj), dim3(512), 0, c.stream,
-                       dst + first * rpj * c.N, pk, rpj, src_stride, src_off, prime_fixed, c.d_primes, (int)c.log_n,
+                       dst + first * rpj * c.N, pk, lv, rpj, src_stride, src_off, prime_fixed, c.d_primes, (int)c.log_n,
                        (int)c.log_n - 12);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 10, ev, 2.0 * cnt * rpj * (double)c.N * 8.0);
@@ -923,37 +949,49 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
     }
     hipEvent_t ev;
     prof_begin(c, 7, &ev);
+    Pack none{};
+    IPack nolv{};
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<1>, dim3((unsigned)(c.N / 4096), nl, 2 * cnt), dim3(512), 0,
-                       c.stream, po, pin, pa, pg, acc + first * 2 * nE * c.N, w + first * 2 * nl * c.N, nE, nl, 2,
-                       add_mode, 0, pinv, tpinv, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
+                       c.stream, po, pin, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
+                       w + first * 2 * nl * c.N, nE, nl, 2, add_mode, 0, pinv, tpinv, c.d_primes, (int)c.log_n,
+                       (int)c.log_n - 12);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 7, ev, (6.0 + (add_mode == 1 ? 2.0 : add_mode == 2 ? 1.0 : 0.0)) * nl * cnt * (double)c.N * 8.0);
   }
 }
 
 void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
-                                   const double* w, int np, int level, const double* tab,
+                                   const std::vector<const double*>& w, const std::vector<int>& levels,
+                                   const std::vector<const double*>& tabs, int np,
                                    const std::vector<const double*>* add, int add_np) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
   const int per = std::max(1, std::min(kPack, kMaxGridY / np));
   for (size_t first = 0; first < out.size(); first += per) {
     const int cnt = (int)std::min<size_t>(per, out.size() - first);
     MPack po;
-    Pack pi, pa;
+    Pack pi, pa, pw, pt;
     GPack pg;
+    IPack lv{};
+    int lmax = 0;
+    double bytes = 0;
     for (int k = 0; k < cnt; ++k) {
       po.p[k] = out[first + k];
       pi.p[k] = in[first + k];
       pa.p[k] = add ? (*add)[first + k] : nullptr;
+      pw.p[k] = w[first + k];
+      pt.p[k] = tabs[first + k];
       pg.g[k] = 1;
+      lv.v[k] = levels[first + k];
+      lmax = std::max(lmax, lv.v[k]);
+      bytes += (3.0 * np + (add ? add_np : 0)) * lv.v[k] * (double)c.N * 8.0;
     }
     hipEvent_t ev;
     prof_begin(c, 8, &ev);
-    hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<2>, dim3((unsigned)(c.N / 4096), level, np * cnt), dim3(512), 0,
-                       c.stream, po, pi, pa, pg, nullptr, w + first * np * level * c.N, 0, level, np, 0,
-                       add ? add_np : 0, tab, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
+    hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<2>, dim3((unsigned)(c.N / 4096), lmax, np * cnt), dim3(512), 0,
+                       c.stream, po, pi, pa, pg, pw, pt, lv, nullptr, nullptr, 0, 0, np, 0, add ? add_np : 0,
+                       nullptr, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
     COPSE_HIP(hipGetLastError());
-    prof_end(c, 8, ev, (3.0 * np + (add ? add_np : 0)) * level * cnt * (double)c.N * 8.0);
+    prof_end(c, 8, ev, bytes);
   }
 }
 

@@ -141,3 +141,91 @@ def workload_inputs(w: Workload):
 # The serving mix: resident forests of the three sizes, one query per request, each request's
 # forest drawn uniformly (all three share the N = 32768, 16-bit-capable chain).
 SERVE_MIX = ("c5_serve_8x_d4", "c5_serve_32x_d6", "c5_serve_64x_d8")
+
+
+# ---------------------------------------------------------------- microbenchmark forests (Table 6)
+# Eight forests over 2 features and 3 labels that differ in one property at a time: maximum depth
+# (depth4/5/6), branch count and tree count (width55, width78, width677: the digits of the name are the
+# branches per tree) and threshold precision (prec8/16).  "# of branches" 15 over 2 trees is split
+# 7 + 8 (the width78 split).
+@dataclass(frozen=True)
+class MicroForest:
+    name: str
+    branches: tuple        # branches per tree
+    max_depth: int
+    precision: int
+    n_features: int = 2
+    n_classes: int = 3
+
+
+TABLE6 = (
+    MicroForest("depth4", (7, 8), 4, 8),
+    MicroForest("depth5", (7, 8), 5, 8),
+    MicroForest("depth6", (7, 8), 6, 8),
+    MicroForest("width55", (5, 5), 5, 8),
+    MicroForest("width78", (7, 8), 5, 8),
+    MicroForest("width677", (6, 7, 7), 5, 8),
+    MicroForest("prec8", (7, 8), 5, 8),
+    MicroForest("prec16", (7, 8), 5, 16),
+)
+
+
+def gen_forest_exact(mf: MicroForest, seed: int) -> str:
+    """A random forest with exactly ``mf.branches[i]`` branches in tree i and maximum depth exactly
+    ``mf.max_depth`` (branches at depths 0 .. max_depth - 1, leaves at depth <= max_depth).
+
+    Tree 0 first grows a chain of ``max_depth`` branches from its root (its direction at each step
+    drawn uniformly); every tree then turns uniformly drawn leaves above the maximum depth into
+    branches until it has its branch count.  Features ~ U[0, F), thresholds ~ U[0, 2^p), labels
+    ~ U[0, C), drawn in preorder when the tree is written out."""
+    rng = np.random.default_rng(seed)
+    if mf.branches[0] < mf.max_depth:
+        raise ValueError("the first tree must hold the chain to the maximum depth")
+    lines = [" ".join(f"c{i}" for i in range(mf.n_classes))]
+    for t, nb in enumerate(mf.branches):
+        if nb > (1 << mf.max_depth) - 1:
+            raise ValueError("more branches than a tree of that depth holds")
+        # node: [is_branch, left, right, depth]; node 0 is the root
+        nodes = [[False, -1, -1, 0]]
+
+        def grow(i):
+            nodes[i][0] = True
+            d = nodes[i][3]
+            nodes[i][1] = len(nodes)
+            nodes.append([False, -1, -1, d + 1])
+            nodes[i][2] = len(nodes)
+            nodes.append([False, -1, -1, d + 1])
+
+        count = 0
+        if t == 0:
+            cur = 0
+            for _ in range(mf.max_depth):
+                grow(cur)
+                count += 1
+                cur = nodes[cur][1 + int(rng.integers(0, 2))]
+        else:
+            grow(0)
+            count = 1
+        while count < nb:
+            leaves = [i for i, n in enumerate(nodes) if not n[0] and n[3] < mf.max_depth]
+            grow(leaves[int(rng.integers(0, len(leaves)))])
+            count += 1
+        toks: list = []
+
+        def emit(i):
+            if nodes[i][0]:
+                toks.extend(["B", str(int(rng.integers(0, mf.n_features))),
+                             str(int(rng.integers(0, 1 << mf.precision)))])
+                emit(nodes[i][1])
+                emit(nodes[i][2])
+            else:
+                toks.extend(["L", str(int(rng.integers(0, mf.n_classes)))])
+
+        emit(0)
+        lines.append(" ".join(toks))
+    return "\n".join(lines) + "\n"
+
+
+def micro_chain(mf: MicroForest) -> dict:
+    """The N = 32768 chain of the configured workloads with enough levels for the forest."""
+    return CHAIN_32K_P16 if mf.precision > 8 else CHAIN_32K_P8

@@ -232,14 +232,28 @@ def test_key_switch_and_modswitch_across_rings(C, ring):
 
 # ---------------------------------------------------------------- end to end
 def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
-    text = synth.gen_forest_text(shape, seed)
+    return _e2e_text(C, synth.gen_forest_text(shape, seed), shape.n_features, shape.precision, seed, log_n, fold,
+                     enc, alpha, n_queries)
+
+
+def _e2e_text(C, text, n_features, precision, seed, log_n, fold, enc, alpha=3, n_queries=None, private=None):
+    shape = synth.ForestShape(0, 0, 0.0, n_features, precision, 0)
     oc = OC.compile_forest(text, shape.n_features, shape.precision)
+    names, _ = F.parse_forest(text)
+    m_plain = oc.m
+    if private is not None:
+        oc = OC.privatize(oc, private[0], private[1], len(names))
     need = CI.seccomp_depth(shape.precision) + (1 if fold else 2) + (math.ceil(math.log2(oc.d)) if oc.d > 1 else 0)
     chain = dict(log_n=log_n, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=alpha,
                  special_max=1 << 49)
     ctx = C.Context(**chain)
     sc = B.BGV(nt.make_chain(log_n, T, need + 1, 1 << 49, 1 << 42, alpha, 1 << 49))
-    comp, meta = C.forest_compile(text, shape.n_features, shape.precision, log_n, fold=fold)
+    if private is None:
+        comp, meta = C.forest_compile(text, shape.n_features, shape.precision, log_n, fold=fold)
+    else:
+        comp, meta = C.forest_compile_private(text, shape.n_features, shape.precision, log_n, private[0],
+                                              private[1], fold=fold)
+        assert C.compiled_codebook(comp) == oc.codebook
     pl = CI.make_plan(oc, sc.N, sc.L, fold=fold, encrypted_model=enc)
     kseed = bytes([seed % 256]) * 32
     say("e2e", shape, "log_n", log_n, "fold", fold, "enc", enc)
@@ -262,6 +276,9 @@ def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
     bits = ctx.decrypt_labels(keys, meta, res, nq)
     _, trees = F.parse_forest(text)
     want = np.array([F.evaluate(trees, list(x)) for x in queries])
+    if private is not None:
+        perm = oc.meta["perm"]
+        want = np.array([[w[r] if r < m_plain else 0 for r in perm] for w in want])
     assert (bits == want).all()
     return ctx
 
@@ -271,6 +288,47 @@ def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
 def test_end_to_end_small(C, seed, fold, enc):
     shape = synth.ForestShape(3, 4, 0.7, 3, 4, 3)
     _e2e(C, shape, seed, 10, fold, enc)
+
+
+@pytest.mark.parametrize("fold,enc,n_pad", [(False, False, 5), (True, False, 0), (False, True, 3)])
+def test_result_privacy_bit_exact(C, fold, enc, n_pad):
+    """Shuffled and padded result slots: ciphertext = oracle's (privatized compiler), decrypted bits =
+    the tree walk's bits moved by the permutation, zero on padding."""
+    shape = synth.ForestShape(3, 4, 0.7, 3, 4, 3)
+    text = synth.gen_forest_text(shape, 61)
+    _e2e_text(C, text, 3, 4, 61, 11, fold, enc, private=(b"\x5a" * 32, n_pad))
+
+
+@pytest.mark.parametrize("name", ["depth4", "width677", "prec16"])
+def test_table6_forest_oracle_parity(C, name):
+    """Microbenchmark forests (exact branch counts): result ciphertext = oracle's, labels = tree walk."""
+    i = [m.name for m in synth.TABLE6].index(name)
+    mf = synth.TABLE6[i]
+    _e2e_text(C, synth.gen_forest_exact(mf, 600 + i), mf.n_features, mf.precision, 40 + i, 12, False, False,
+              alpha=4, n_queries=16)
+
+
+def test_table6_forests_full_size_labels(C):
+    """All eight microbenchmark forests in the benchmark's configuration (N = 32768 chains): labels of
+    64 queries per forest against the tree walk."""
+    ctxs = {}
+    for i, mf in enumerate(synth.TABLE6):
+        ch = synth.micro_chain(mf)
+        key = tuple(sorted(ch.items()))
+        if key not in ctxs:
+            ctxs[key] = C.Context(**ch)
+        ctx = ctxs[key]
+        text = synth.gen_forest_exact(mf, 600 + i)
+        seed = synth.crypto_seed(f"COPSE-micro-{mf.name}")
+        comp, meta = C.forest_compile(text, mf.n_features, mf.precision, ch["log_n"])
+        keys = ctx.keygen(seed, C.compiled_rotations(meta))
+        model = ctx.model_encode(comp)
+        q = synth.gen_queries(64, mf.n_features, mf.precision, 700 + i)
+        say("table 6 forest", mf.name)
+        res = ctx.evaluate(model, ctx.export_eval(keys), ctx.query_encrypt(keys, meta, q, seed, group=0))
+        _, trees = F.parse_forest(text)
+        bits = ctx.decrypt_labels(keys, meta, res, len(q))
+        assert (bits == np.array([F.evaluate(trees, list(x)) for x in q])).all(), mf.name
 
 
 def test_end_to_end_partial_group_and_deeper(C):

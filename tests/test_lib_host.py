@@ -121,3 +121,21 @@ def test_compiler_errors():
     with pytest.raises(C.CopseError) as e:
         C.forest_compile(text, 16, 8, 10)
     assert e.value.code == C.COPSE_ECAPACITY
+
+
+@pytest.mark.parametrize("seed,n_pad", [(0, 0), (1, 5), (2, 17)])
+def test_private_compile_matches_oracle(seed, n_pad):
+    """The library's shuffled and padded result layout equals the oracle's: slot count, block width
+    and the codebook (which encodes the permutation and the padding labels)."""
+    from oracle import compiler as OC
+    from oracle import forest as F
+    shape = synth.ForestShape(3, 5, 0.7, 4, 6, 5)
+    text = synth.gen_forest_text(shape, 90 + seed)
+    names, _ = F.parse_forest(text)
+    key = bytes([seed + 1]) * 32
+    comp, meta = C.forest_compile_private(text, 4, 6, 13, key, n_pad)
+    oc = OC.privatize(OC.compile_forest(text, 4, 6), key, n_pad, len(names))
+    assert meta.m == oc.m and meta.block_w == oc.W and meta.b == oc.b and meta.q == oc.q
+    assert C.compiled_codebook(comp) == oc.codebook
+    _, pmeta = C.forest_compile(text, 4, 6, 13)
+    assert pmeta.m + n_pad == meta.m
