@@ -63,9 +63,15 @@ class Plan:
     encrypted_model: bool
     L: int
     levels: Dict[str, int] = field(default_factory=dict)
+    n1_F: int = 1
+    server_rep: bool = False
 
     def rotations(self) -> List[int]:
         rs = set()
+        if self.server_rep:
+            n = self.c.n_features
+            rs |= set(range(1, self.n1_F))
+            rs |= {g * self.n1_F for g in range(1, -(-n // self.n1_F))}
         if not self.fold:
             n = self.c.q
             rs |= set(range(1, self.n1_R))
@@ -86,11 +92,17 @@ def make_plan(c: Compiled, N: int, L: int, fold: bool = False, encrypted_model: 
     n1_R = n1_R or bsgs_n1(c.q)
     n1_L = n1_L or bsgs_n1(c.q if fold else c.b)
     pl = Plan(c, lay, n1_R, n1_L, fold, encrypted_model, L)
-    dec = L - seccomp_depth(c.precision)
+    # server-side replication: one plaintext product (and its switch) before the comparison
+    pl.server_rep = bool(c.meta.get("server_rep", False))
+    if pl.server_rep and encrypted_model:
+        raise ValueError("server-side replication is for a server-held (plaintext) model")
+    pl.n1_F = bsgs_n1(c.n_features)
+    top = L - 1 if pl.server_rep else L
+    dec = top - seccomp_depth(c.precision)
     br = dec if fold else dec - 1
     lvl = br - 1
     final = lvl - math.ceil(math.log2(c.d)) if c.d > 1 else lvl
-    pl.levels = dict(dec=dec, branches=br, levels=lvl, labels=final)
+    pl.levels = dict(top=top, dec=dec, branches=br, levels=lvl, labels=final)
     if final < 0:
         raise ValueError(f"circuit needs {L - final} levels, chain has {L}")
     return pl
@@ -106,6 +118,7 @@ class PlainModel:
     rdiag: List[Optional[np.ndarray]]
     ldiag: List[List[Optional[np.ndarray]]]
     masks: List[np.ndarray]
+    rep: List[Optional[np.ndarray]] = field(default_factory=list)   # replication diagonals
 
 
 @dataclass
@@ -137,7 +150,11 @@ def encode_model(sc: BGV, pl: Plan) -> PlainModel:
         rdiag = enc_all(_diag_slots(pl, extended_reshuffle(c), pl.n1_R, t))
         ldiag = [enc_all(_diag_slots(pl, c.Lfold[l], pl.n1_L, t)) for l in range(c.d)]
     masks = [sc.encode(pl.layout.replicate(mk)) for mk in c.masks]
-    return PlainModel(E, Cc, G, TH, rdiag, ldiag, masks)
+    rep = []
+    if pl.server_rep:
+        from .compiler import replication_matrix
+        rep = enc_all(_diag_slots(pl, replication_matrix(c), pl.n1_F, t))
+    return PlainModel(E, Cc, G, TH, rdiag, ldiag, masks, rep)
 
 
 def encrypt_model(sc: BGV, keys: Keys, pl: Plan, seed: bytes) -> EncModel:
@@ -259,6 +276,9 @@ class Evaluator:
 
     def run(self, X: List[Ciphertext], model) -> Dict[str, object]:
         sc, pl = self.sc, self.pl
+        if pl.server_rep:
+            # each plane: the replication product (hoisted babies, giants, one switch)
+            X = [self.matmul(x, model.rep, pl.n1_F) for x in X]
         dec = self.seccomp(X, model)
         assert dec.level == pl.levels["dec"], (dec.level, pl.levels)
         levels = []

@@ -241,6 +241,28 @@ def privatize(c: Compiled, seed: bytes, n_pad: int, n_classes: int) -> Compiled:
     return out
 
 
+def server_replicated(c: Compiled) -> Compiled:
+    """Server-side feature replication (Section 6, the alternative to Diane replicating her features):
+    the query holds each feature once, cyclically extended with period F (block slot s < B_in + F - 1
+    holds feature s mod F), so that no multiplicity is revealed; the server maps it onto the padded
+    layout by one plaintext matrix product with replication_matrix(c).  The block must hold the
+    longer input: W = next power of two >= B_in + F - 1."""
+    import copy
+    out = copy.copy(c)
+    out.meta = dict(c.meta, server_rep=True)
+    out.W = next_pow2(c.B_in + c.n_features - 1)
+    return out
+
+
+def replication_matrix(c: Compiled) -> np.ndarray:
+    """Rep (B_in x F): Rep[s][f] = 1 iff padded slot s mod q belongs to feature f (slot j of the
+    padded vector holds feature j div K, Section 4.2)."""
+    Rep = np.zeros((c.B_in, c.n_features), dtype=np.int64)
+    s = np.arange(c.B_in)
+    Rep[s, (s % c.q) // c.K] = 1
+    return Rep
+
+
 def generalized_diagonal(A: np.ndarray, k: int) -> np.ndarray:
     """d_k[j] = A[j][(j + k) mod n], j < rows (Section 4.1)."""
     rows, n = A.shape

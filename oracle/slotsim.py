@@ -77,11 +77,16 @@ def query_planes(c: Compiled, lay: Layout, queries: np.ndarray) -> List[np.ndarr
     cyclically extended features (slot s of a block holds padded position
     s mod q for s < B_in).  k = p-1 is the most significant bit."""
     planes = []
+    server_rep = c.meta.get("server_rep", False)
     for k in range(c.precision):
         per_block = []
         for x in queries:
-            rep = np.array(replicate_features(list(x), c.K), dtype=np.int64)
-            ext = rep[np.arange(c.B_in) % c.q]
+            if server_rep:
+                # each feature once, cyclically extended with period F (server-side replication)
+                ext = np.array(list(x), dtype=np.int64)[np.arange(c.B_in + c.n_features - 1) % c.n_features]
+            else:
+                rep = np.array(replicate_features(list(x), c.K), dtype=np.int64)
+                ext = rep[np.arange(c.B_in) % c.q]
             per_block.append((ext >> k) & 1)
         planes.append(lay.place(per_block))
     return planes
@@ -175,6 +180,11 @@ def run(c: Compiled, queries: np.ndarray, n_slots: int, t: int = 65537,
     if len(queries) > lay.Qs:
         raise ValueError("more queries than blocks")
     xp = query_planes(c, lay, queries)
+    if c.meta.get("server_rep", False):
+        from .compiler import replication_matrix
+        n1_F = bsgs_n1(c.n_features)
+        rd = prerotated_diagonals(replication_matrix(c), lay, n1_F)
+        xp = [matmul_bsgs(x, rd, n1_F, t) for x in xp]
     tp = threshold_planes(c, lay)
     dec = seccomp_slots(xp, tp, t)
     Rext = extended_reshuffle(c)

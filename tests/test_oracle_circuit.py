@@ -100,3 +100,30 @@ def test_single_leaf_tree_and_full_block():
     lab = CI.decrypt_labels(sc, keys, pl, out["result"], len(queries))
     _, trees = F.parse_forest(text)
     assert (lab == np.array([F.evaluate(trees, list(x)) for x in queries])).all()
+
+
+@pytest.mark.parametrize("seed,fold", [(11, False), (12, True)])
+def test_server_replication_encrypted(seed, fold):
+    """Queries holding each feature once; the server's replication product before the comparison
+    (one more level): decrypted labels = tree walk, and every intermediate = the slot simulator."""
+    shape = synth.ForestShape(3, 4, 0.7, 3, 4, 3)
+    text = synth.gen_forest_text(shape, seed)
+    c = C.server_replicated(C.compile_forest(text, 3, 4))
+    need = 1 + CI.seccomp_depth(4) + (1 if fold else 2) + math.ceil(math.log2(c.d))
+    sc = B.BGV(nt.make_chain(9, T, n_data=need + 1, q0_max=1 << 49, data_max=1 << 40, alpha=3,
+                             special_max=1 << 49))
+    pl = CI.make_plan(c, sc.N, sc.L, fold=fold)
+    assert pl.server_rep and pl.levels["labels"] == 0 and pl.levels["top"] == sc.L - 1
+    kseed = bytes([seed]) * 32
+    keys = sc.keygen(kseed, rotations=pl.rotations())
+    queries = synth.gen_queries(pl.layout.Qs, 3, 4, 70 + seed)
+    X = CI.encrypt_queries(sc, keys, pl, queries, kseed, 0)
+    out = CI.Evaluator(sc, keys, pl).run(X, CI.encode_model(sc, pl))
+    _, trees = F.parse_forest(text)
+    lab = CI.decrypt_labels(sc, keys, pl, out["result"], len(queries))
+    assert (lab == np.array([F.evaluate(trees, list(x)) for x in queries])).all()
+    sim = S.run(c, queries, n_slots=sc.N, fold_reshuffle=fold, n1_R=pl.n1_R, n1_L=pl.n1_L)
+    assert (sc.decrypt_slots(keys, out["dec"]) == sim["dec"]).all()
+    assert sc.margin_bits(keys, out["result"]) > 10
+    with pytest.raises(ValueError):
+        CI.make_plan(c, sc.N, sc.L, encrypted_model=True)

@@ -251,3 +251,28 @@ def test_privatize_is_deterministic_and_seeded():
     d = C.privatize(c0, b"\x06" * 32, 4, 3)
     assert a.meta["perm"] == b.meta["perm"] and a.codebook == b.codebook
     assert a.meta["perm"] != d.meta["perm"]
+
+
+# ---------------------------------------------------------------- server-side feature replication
+def test_replication_matrix_rebuilds_the_padded_layout():
+    """Rep applied to the feature vector (each feature once) is the client's replicated, cyclically
+    extended vector (Section 3.3, Step 0)."""
+    text, shape = _random_forest(5, trees=3, depth=4, feats=4, prec=5, classes=3)
+    c = C.compile_forest(text, shape.n_features, shape.precision)
+    x = np.array([3, 17, 9, 30])
+    want = np.array(C.replicate_features(list(x), c.K))[np.arange(c.B_in) % c.q]
+    assert (C.replication_matrix(c) @ x == want).all()
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("fold", [False, True])
+def test_server_replication_equals_tree_walk(seed, fold):
+    text, shape = _random_forest(60 + seed, trees=3, depth=4, feats=3 + seed % 3, prec=4, classes=3)
+    c = C.server_replicated(C.compile_forest(text, shape.n_features, shape.precision))
+    _, trees = F.parse_forest(text)
+    assert c.W >= c.B_in + c.n_features - 1
+    lay_slots = max(64, 4 * c.W)
+    queries = synth.gen_queries(lay_slots // c.W, shape.n_features, shape.precision, 3000 + seed)
+    res = S.run(c, queries, n_slots=lay_slots, fold_reshuffle=fold)
+    for k, x in enumerate(queries):
+        assert list(res["per_query"][k]) == F.evaluate(trees, list(x))
