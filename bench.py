@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--n1-l", type=int, default=0, help="baby steps of the level products (0: compiler default)")
     ap.add_argument("--result-pad", type=int, default=-1,
                     help="result privacy: shuffle the result slots and pad them with this many labels (-1: off)")
+    ap.add_argument("--server-rep", action="store_true",
+                    help="queries hold each feature once and the server replicates them (one more prime)")
     ap.add_argument("--requests", type=int, default=240, help="serving mix: requests per offered rate")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.25, 0.5, 0.75, 1.0, 1.25],
                     help="serving mix: offered rates as fractions of the burst capacity")
@@ -375,13 +377,22 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     w = synth.WORKLOADS[args.workload]
     text, queries, seed = synth.workload_inputs(w)
-    ch = w.chain
+    ch = dict(w.chain)
+    if args.server_rep:
+        ch["n_data_primes"] += 1   # the replication product takes one level
     log("workload", w.name, "chain", ch)
     t0 = time.perf_counter()
     ctx = C.Context(**ch)
     stream = torch.cuda.Stream()
     ctx.set_stream(stream.cuda_stream)
-    if args.result_pad < 0:
+    if args.server_rep:
+        # queries hold each feature once; the server replicates them (one more level)
+        comp, meta = C.forest_compile_ex(
+            text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold, n1_R=args.n1_r, n1_L=args.n1_l,
+            server_replication=True,
+            privacy_seed=synth.crypto_seed(f"COPSE-shuffle-{w.seed_index}") if args.result_pad >= 0 else None,
+            n_pad=max(0, args.result_pad))
+    elif args.result_pad < 0:
         comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
                                       n1_R=args.n1_r, n1_L=args.n1_l)
     else:
@@ -531,7 +542,7 @@ def main():
                    "N": 1 << w.log_n, "data_primes": ch["n_data_primes"], "special_primes": ch["alpha"],
                    "model": "plaintext" if not w.encrypted_model else "encrypted",
                    "b": meta.b, "m": meta.m, "q": meta.q, "d": meta.d, "W": meta.block_w,
-                   "result_pad": args.result_pad,
+                   "result_pad": args.result_pad, "server_replication": bool(args.server_rep),
                    "n1_R": meta.n1_R, "n1_L": meta.n1_L},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "profiled_mean": round(sum(per_step) / len(per_step), 3)},

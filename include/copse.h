@@ -103,6 +103,8 @@ typedef struct {
   uint32_t fold;         /* 1: level matrices composed with R (one product less) */
   uint32_t depth;        /* modulus switches the evaluation consumes */
   uint32_t log_n;        /* ring the layout was made for */
+  uint32_t server_rep;   /* 1: queries hold each feature once; the server replicates (Section 6) */
+  uint32_t n1_F;         /* baby steps of the replication product */
 } copse_public_meta;
 
 /* ---------------------------------------------------------------- context */
@@ -141,6 +143,24 @@ size_t copse_ctx_device_bytes(const copse_ctx* ctx);
 int copse_forest_compile(const char* text, size_t len, uint32_t n_features, uint32_t precision,
                          uint32_t log_n, int fold, uint32_t n1_R, uint32_t n1_L,
                          copse_compiled** out, copse_public_meta* meta);
+/* All compile options at once (the calls above and below are shorthands).
+ * server_replication (Section 6, alternative to replicated queries): queries
+ * hold each feature once, extended with period F over B_in + F - 1 slots, so
+ * the feature multiplicity K is not revealed; the server maps them onto the
+ * padded layout with one plaintext matrix product before the comparison (one
+ * more level; plaintext models only, W = next pow2 >= B_in + F - 1).
+ * n1_F = 0 chooses 2^ceil(log2 sqrt F).  result_privacy: see
+ * copse_forest_compile_private. */
+typedef struct {
+  int fold;
+  uint32_t n1_R, n1_L, n1_F;
+  int server_replication;
+  int result_privacy;
+  uint8_t privacy_seed[32];
+  uint32_t n_pad;
+} copse_compile_options;
+int copse_forest_compile_ex(const char* text, size_t len, uint32_t n_features, uint32_t precision, uint32_t log_n,
+                            const copse_compile_options* opts, copse_compiled** out, copse_public_meta* meta);
 /* Result privacy (Section 6, "Returning classification bitvectors"): as
  * copse_forest_compile, then the result slots are shuffled by a permutation
  * drawn from `seed` (32 bytes, the model owner's) and padded with n_pad

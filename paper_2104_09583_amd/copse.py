@@ -47,10 +47,16 @@ class Params(ctypes.Structure):
                 ("special_max", ctypes.c_uint64), ("device", ctypes.c_int)]
 
 
+class CompileOptions(ctypes.Structure):
+    _fields_ = [("fold", ctypes.c_int), ("n1_R", ctypes.c_uint32), ("n1_L", ctypes.c_uint32),
+                ("n1_F", ctypes.c_uint32), ("server_replication", ctypes.c_int), ("result_privacy", ctypes.c_int),
+                ("privacy_seed", ctypes.c_uint8 * 32), ("n_pad", ctypes.c_uint32)]
+
+
 class Meta(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n_features", "precision", "K", "q", "b", "m", "d", "n_trees", "block_w", "queries_per_ct",
-        "n1_R", "n1_L", "fold", "depth", "log_n")]
+        "n1_R", "n1_L", "fold", "depth", "log_n", "server_rep", "n1_F")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -90,6 +96,8 @@ def lib() -> ctypes.CDLL:
         "copse_forest_compile_private": [ctypes.c_char_p, sz, u32, u32, u32, i32, u32, u32, u8p, u32, PP,
                                          ctypes.POINTER(Meta)],
         "copse_compiled_codebook": [P, u32p, sz, ctypes.POINTER(sz)],
+        "copse_forest_compile_ex": [ctypes.c_char_p, sz, u32, u32, u32, ctypes.POINTER(CompileOptions), PP,
+                                    ctypes.POINTER(Meta)],
         "copse_keygen": [P, u8p, i32p, sz, i32, PP],
         "copse_keys_export_eval": [P, P, PP],
         "copse_model_encode": [P, P, P, i32, u8p, PP],
@@ -402,6 +410,24 @@ def forest_compile_private(text: str, n_features: int, precision: int, log_n: in
     meta = Meta()
     check(lib().copse_forest_compile_private(raw, len(raw), n_features, precision, log_n, int(fold), n1_R, n1_L,
                                              _u8(seed), n_pad, ctypes.byref(h), ctypes.byref(meta)))
+    return Compiled(h), meta
+
+
+def forest_compile_ex(text: str, n_features: int, precision: int, log_n: int, fold: bool = False,
+                      n1_R: int = 0, n1_L: int = 0, n1_F: int = 0, server_replication: bool = False,
+                      privacy_seed: Optional[bytes] = None, n_pad: int = 0):
+    raw = text.encode()
+    o = CompileOptions()
+    o.fold, o.n1_R, o.n1_L, o.n1_F = int(fold), n1_R, n1_L, n1_F
+    o.server_replication = int(server_replication)
+    if privacy_seed is not None:
+        o.result_privacy = 1
+        o.privacy_seed[:] = list(privacy_seed)
+        o.n_pad = n_pad
+    h = ctypes.c_void_p()
+    meta = Meta()
+    check(lib().copse_forest_compile_ex(raw, len(raw), n_features, precision, log_n, ctypes.byref(o),
+                                        ctypes.byref(h), ctypes.byref(meta)))
     return Compiled(h), meta
 
 

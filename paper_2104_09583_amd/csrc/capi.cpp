@@ -198,6 +198,21 @@ int copse_forest_compile(const char* text, size_t len, uint32_t n_features, uint
   });
 }
 
+int copse_forest_compile_ex(const char* text, size_t len, uint32_t n_features, uint32_t precision, uint32_t log_n,
+                            const copse_compile_options* opts, copse_compiled** out, copse_public_meta* meta) {
+  return guarded([&] {
+    NEED(text && out && opts);
+    *out = nullptr;
+    if (log_n < 4 || log_n > 17) fail(COPSE_EINVAL, "log_n must be in [4, 17]");
+    auto cc = std::make_unique<copse_compiled>();
+    cc->c = compile_forest(text, len, n_features, precision, log_n, opts->fold, opts->n1_R, opts->n1_L);
+    if (opts->result_privacy) privatize(*cc->c, opts->privacy_seed, opts->n_pad);
+    if (opts->server_replication) server_replicate(*cc->c, opts->n1_F);
+    if (meta) *meta = cc->c->meta;
+    *out = cc.release();
+  });
+}
+
 int copse_forest_compile_private(const char* text, size_t len, uint32_t n_features, uint32_t precision,
                                  uint32_t log_n, int fold, uint32_t n1_R, uint32_t n1_L, const uint8_t seed[32],
                                  uint32_t n_pad, copse_compiled** out, copse_public_meta* meta) {

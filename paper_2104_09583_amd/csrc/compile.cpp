@@ -192,6 +192,8 @@ std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t 
   uint32_t tree = 0;
   while ((1u << tree) < d) ++tree;
   M.depth = seccomp + (fold ? 1 : 2) + tree;
+  M.server_rep = 0;
+  M.n1_F = baby_steps(F);
   C->B_in = B_in;
   for (int ln : C->label_nodes) C->codebook.push_back(nodes[ln].label);
   for (uint32_t i = 0; i < m; ++i) C->perm.push_back((int)i);
@@ -247,7 +249,24 @@ void privatize(Compiled& C, const uint8_t seed[32], uint32_t n_pad) {
   C.perm = std::move(perm);
   M.m = mp;
   C.B_in = mp + M.b + M.q - 2;
-  M.block_w = pow2_ceil(C.B_in);
+  set_block(C);
+}
+
+// Server-side feature replication (Section 6): the query holds feature s mod F in block slot s for
+// s < B_in + F - 1; the server multiplies by Rep (B_in x F, Rep[s][f] = 1 iff padded slot s mod q
+// belongs to feature f) with the diagonal method before the comparison: one more level.
+void server_replicate(Compiled& C, uint32_t n1F) {
+  auto& M = C.meta;
+  M.server_rep = 1;
+  M.n1_F = n1F ? n1F : baby_steps(M.n_features);
+  M.depth += 1;
+  set_block(C);
+}
+
+void set_block(Compiled& C) {
+  auto& M = C.meta;
+  const uint32_t span = C.B_in + (M.server_rep ? M.n_features - 1 : 0);
+  M.block_w = pow2_ceil(std::max<uint32_t>(span, 1));
   const uint64_t N = 1ULL << M.log_n;
   if (M.block_w > N / 2) fail(COPSE_ECAPACITY, "query block of " + std::to_string(M.block_w) +
                                                   " slots exceeds a slot row of " + std::to_string(N / 2));
@@ -262,6 +281,7 @@ std::vector<int32_t> needed_rotations(const copse_public_meta& M) {
   };
   if (!M.fold) add(M.q, M.n1_R);
   add(M.fold ? M.q : M.b, M.n1_L);
+  if (M.server_rep) add(M.n_features, M.n1_F);
   std::sort(r.begin(), r.end());
   r.erase(std::unique(r.begin(), r.end()), r.end());
   return r;
@@ -290,12 +310,19 @@ void query_plane_slots(const copse_public_meta& M, size_t N, const uint32_t* fea
                        std::vector<uint64_t>& slots) {
   slots.assign(N, 0);
   uint32_t B_in = M.m + M.b + M.q - 2;
-  for (size_t k = 0; k < nq; ++k)
+  for (size_t k = 0; k < nq; ++k) {
+    if (M.server_rep) {
+      // each feature once, extended with period F over B_in + F - 1 slots
+      for (uint32_t s = 0; s < B_in + M.n_features - 1; ++s)
+        slots[slot_index(M, N, (uint32_t)k, s)] = (feats[k * M.n_features + s % M.n_features] >> plane) & 1u;
+      continue;
+    }
     for (uint32_t s = 0; s < B_in; ++s) {
       uint32_t pos = s % M.q;
       uint32_t f = pos / M.K;
       slots[slot_index(M, N, (uint32_t)k, s)] = (feats[k * M.n_features + f] >> plane) & 1u;
     }
+  }
 }
 
 // Generalized diagonal k of A (rows x n), pre-rotated to block offset g*n1, replicated per block.

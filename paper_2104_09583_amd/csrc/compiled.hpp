@@ -38,6 +38,10 @@ std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t 
                                          int fold, uint32_t n1R, uint32_t n1L);
 // result privacy: shuffle the result slots and pad them with never-selected labels (see compile.cpp)
 void privatize(Compiled& C, const uint8_t seed[32], uint32_t n_pad);
+// server-side feature replication (queries hold each feature once; see compile.cpp)
+void server_replicate(Compiled& C, uint32_t n1F);
+// block width and queries per ciphertext from B_in (and the replication input span)
+void set_block(Compiled& C);
 std::vector<int32_t> needed_rotations(const copse_public_meta& M);
 void replicate_blocks(const copse_public_meta& M, size_t N, const std::vector<int64_t>& vec,
                       std::vector<uint64_t>& slots, uint64_t t);
@@ -73,7 +77,10 @@ struct Model {
   DBuf lcat_buf;                                // the level plans' tables side by side: [lvl_rots][sum of groups]
   const double* const* d_lcat = nullptr;
   bool encrypted = false;
+  int top_level = 0;                            // level of the query planes the comparison reads
   int dec_level = 0, br_level = 0, lvl_level = 0;
+  MatPlan plan_F;                               // server-side replication product (meta.server_rep)
+  std::vector<Operand> fdiag;
   // comparison operands: plaintext thresholds -> E, C, G, TH plaintexts; encrypted -> TH ciphertexts
   std::vector<Operand> E, C, G, TH;
   std::vector<Operand> rdiag;                   // q diagonals of R_ext (empty when folded)

@@ -501,9 +501,26 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
   };
   // 1. comparison
   next_stage(0);
+  // server-side replication: every plane of every group through the replication product first
+  std::vector<std::vector<SCt>> rep_planes;
+  std::vector<std::vector<const Ct*>> planes_in = groups;
+  if (M.meta.server_rep) {
+    std::vector<const Ct*> all;
+    for (auto& g : groups)
+      for (auto* x : g) all.push_back(x);
+    const MatPlan& P = M.plan_F;
+    const int GP = (int)all.size();
+    DBuf B(&c, P.rots.size() * GP * 2 * (size_t)(c.L + 1) * N);
+    b_rotate_into(c, k, all, P.rots, B.get());
+    auto r = b_matmul_many(c, k, {&P}, P.d_tab, (int)P.rots.size(), B.get(), GP, c.L)[0];
+    for (int b = 0; b < G; ++b) {
+      rep_planes.emplace_back(r.begin() + (size_t)b * p, r.begin() + (size_t)(b + 1) * p);
+      for (int kb = 0; kb < p; ++kb) planes_in[b][kb] = rep_planes[b][kb].get();
+    }
+  }
   std::vector<std::vector<SCt>> eq(p, std::vector<SCt>(G)), lt(p, std::vector<SCt>(G));
   if (!M.encrypted) {
-    const int L = c.L, nl = L + 1;
+    const int L = M.top_level, nl = L + 1;
     const int J = (2 * p - 1) * G;
     auto raw = alloc_batch(c, J, L, 2);
     std::vector<double*> out;
@@ -514,7 +531,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
       for (int e = (kb >= 1 ? 1 : 0); e >= 0; --e)
         for (int b = 0; b < G; ++b) {
           out.push_back(raw[z++]->data());
-          a.push_back(groups[b][kb]->data());
+          a.push_back(planes_in[b][kb]->data());
           mul.push_back(e ? M.E[kb].pt->buf.get() : M.G[kb].pt->buf.get());
           add.push_back(e ? M.C[kb].pt->buf.get() : M.TH[kb].pt->buf.get());
           where.push_back({kb, e});
@@ -530,12 +547,12 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
   } else {
     std::vector<std::pair<SCt, SCt>> pairs;
     for (int kb = 0; kb < p; ++kb)
-      for (int b = 0; b < G; ++b) pairs.push_back({view(groups[b][kb]), view(M.TH[kb].ct.get())});
+      for (int b = 0; b < G; ++b) pairs.push_back({view(planes_in[b][kb]), view(M.TH[kb].ct.get())});
     auto u = b_mul(c, k, pairs);
     std::vector<const Ct*> xin, tin;
     for (int kb = 0; kb < p; ++kb) {
       tin.push_back(M.TH[kb].ct.get());
-      for (int b = 0; b < G; ++b) xin.push_back(groups[b][kb]);
+      for (int b = 0; b < G; ++b) xin.push_back(planes_in[b][kb]);
     }
     auto xs = b_modswitch(c, xin);
     auto ts = b_modswitch(c, tin);

@@ -45,8 +45,12 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
   auto M = std::make_unique<Model>();
   M->meta = meta;
   M->encrypted = encrypt_model;
+  if (meta.server_rep && encrypt_model) fail(COPSE_EINVAL, "server-side replication is for a server-held model");
   const int L = c.L;
-  M->dec_level = L - seccomp_depth(meta.precision);
+  // with server-side replication the comparison reads the replicated planes one level down
+  const int top = meta.server_rep ? L - 1 : L;
+  M->top_level = top;
+  M->dec_level = top - seccomp_depth(meta.precision);
   M->br_level = meta.fold ? M->dec_level : M->dec_level - 1;
   M->lvl_level = M->br_level - 1;
   int tree = 0;
@@ -87,7 +91,7 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
     for (uint32_t s = 0; s < B_in; ++s) th[s] = (thr_ext[s] >> kb) & 1;
     if (encrypt_model) {
       replicate_blocks(meta, N, th, slots, t);
-      M->TH.push_back(make_operand(slots, L, obj_id(2, 0, kb), false));
+      M->TH.push_back(make_operand(slots, top, obj_id(2, 0, kb), false));
       M->E.emplace_back(); M->C.emplace_back(); M->G.emplace_back();
     } else {
       // slots outside B_in have th = 0: E = -1, C = 1 there, as the formula gives
@@ -101,10 +105,10 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
         sG[i] = v ? t - 1 : 0;
         sT[i] = v;
       }
-      M->E.push_back(make_operand(sE, L, 0, false));
-      M->C.push_back(make_operand(sC, L, 0, false));
-      M->G.push_back(make_operand(sG, L, 0, false));
-      M->TH.push_back(make_operand(sT, L, 0, false));
+      M->E.push_back(make_operand(sE, top, 0, false));
+      M->C.push_back(make_operand(sC, top, 0, false));
+      M->G.push_back(make_operand(sG, top, 0, false));
+      M->TH.push_back(make_operand(sT, top, 0, false));
     }
   }
   // column of each branch in the padded vector
@@ -121,6 +125,13 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
       out.push_back(make_operand(slots, level, obj_id(kind, lidx, kd), true));
     }
   };
+  if (meta.server_rep) {
+    // Rep (B_in x F): padded slot s mod q holds feature (s mod q) / K
+    const uint32_t F = meta.n_features;
+    std::vector<std::vector<int64_t>> Rep(B_in, std::vector<int64_t>(F, 0));
+    for (uint32_t s = 0; s < B_in; ++s) Rep[s][(s % q) / meta.K] = 1;
+    add_diags(Rep, meta.n1_F, L, 6, 0, M->fdiag);
+  }
   if (!meta.fold) {
     std::vector<std::vector<int64_t>> Rext(m + b - 1, std::vector<int64_t>(q, 0));
     for (uint32_t j = 0; j < m + b - 1; ++j) Rext[j][col[j % b]] = 1;
@@ -146,6 +157,7 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
   }
   // matrix-product plans; the level products share one set of baby rotations
   if (!meta.fold) build_plan(c, M->plan_R, M->rdiag, meta.n1_R, encrypt_model, nullptr);
+  if (meta.server_rep) build_plan(c, M->plan_F, M->fdiag, meta.n1_F, false, nullptr);
   {
     std::set<int32_t> used;
     for (auto& dl : M->ldiag)

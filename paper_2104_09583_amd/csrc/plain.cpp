@@ -125,7 +125,14 @@ struct Plain1 {
     if (X.size() != M.meta.precision) fail(COPSE_EINVAL, "query group must hold one ciphertext per bit plane");
     for (auto* x : X)
       if (x->npolys != 2 || x->level != c.L) fail(COPSE_EINVAL, "query ciphertexts must be fresh (top level)");
-    SCt dec = seccomp(X);
+    std::vector<SCt> rep;
+    std::vector<const Ct*> planes = X;
+    if (M.meta.server_rep) {
+      // server-side replication: each plane through the replication product first
+      for (auto* x : X) rep.push_back(matmul(SCt(const_cast<Ct*>(x), [](Ct*) {}), M.fdiag, M.meta.n1_F));
+      for (size_t i = 0; i < X.size(); ++i) planes[i] = rep[i].get();
+    }
+    SCt dec = seccomp(planes);
     std::vector<SCt> lv;
     SCt src = M.meta.fold ? dec : matmul(dec, M.rdiag, M.meta.n1_R);
     for (uint32_t l = 0; l < M.meta.d; ++l) lv.push_back(add_mask(matmul(src, M.ldiag[l], M.meta.n1_L), M.masks[l]));

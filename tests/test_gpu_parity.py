@@ -236,19 +236,28 @@ def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
                      enc, alpha, n_queries)
 
 
-def _e2e_text(C, text, n_features, precision, seed, log_n, fold, enc, alpha=3, n_queries=None, private=None):
+def _e2e_text(C, text, n_features, precision, seed, log_n, fold, enc, alpha=3, n_queries=None, private=None,
+              server_rep=False):
     shape = synth.ForestShape(0, 0, 0.0, n_features, precision, 0)
     oc = OC.compile_forest(text, shape.n_features, shape.precision)
     names, _ = F.parse_forest(text)
     m_plain = oc.m
     if private is not None:
         oc = OC.privatize(oc, private[0], private[1], len(names))
+    if server_rep:
+        oc = OC.server_replicated(oc)
     need = CI.seccomp_depth(shape.precision) + (1 if fold else 2) + (math.ceil(math.log2(oc.d)) if oc.d > 1 else 0)
+    need += 1 if server_rep else 0
     chain = dict(log_n=log_n, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=alpha,
                  special_max=1 << 49)
     ctx = C.Context(**chain)
     sc = B.BGV(nt.make_chain(log_n, T, need + 1, 1 << 49, 1 << 42, alpha, 1 << 49))
-    if private is None:
+    if server_rep:
+        comp, meta = C.forest_compile_ex(text, shape.n_features, shape.precision, log_n, fold=fold,
+                                         server_replication=True,
+                                         privacy_seed=None if private is None else private[0],
+                                         n_pad=0 if private is None else private[1])
+    elif private is None:
         comp, meta = C.forest_compile(text, shape.n_features, shape.precision, log_n, fold=fold)
     else:
         comp, meta = C.forest_compile_private(text, shape.n_features, shape.precision, log_n, private[0],
@@ -297,6 +306,16 @@ def test_result_privacy_bit_exact(C, fold, enc, n_pad):
     shape = synth.ForestShape(3, 4, 0.7, 3, 4, 3)
     text = synth.gen_forest_text(shape, 61)
     _e2e_text(C, text, 3, 4, 61, 11, fold, enc, private=(b"\x5a" * 32, n_pad))
+
+
+@pytest.mark.parametrize("fold,private", [(False, False), (True, False), (False, True)])
+def test_server_replication_bit_exact(C, fold, private):
+    """Queries holding each feature once, replicated by the server: query ciphertexts, result
+    ciphertext (batched and op-at-a-time paths) = oracle's; labels = tree walk."""
+    shape = synth.ForestShape(3, 4, 0.7, 4, 4, 3)
+    text = synth.gen_forest_text(shape, 63)
+    _e2e_text(C, text, 4, 4, 63, 11, fold, False, server_rep=True,
+              private=(b"\x3c" * 32, 4) if private else None)
 
 
 @pytest.mark.parametrize("name", ["depth4", "width677", "prec16"])

@@ -139,3 +139,20 @@ def test_private_compile_matches_oracle(seed, n_pad):
     assert C.compiled_codebook(comp) == oc.codebook
     _, pmeta = C.forest_compile(text, 4, 6, 13)
     assert pmeta.m + n_pad == meta.m
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_server_replication_layout_matches_oracle(seed):
+    """Server-side replication: block width, depth and rotations equal the oracle's (the query planes
+    are compared bit for bit after encryption in the GPU tests)."""
+    from oracle import circuit as CI
+    from oracle import compiler as OC
+    shape = synth.ForestShape(2 + seed, 4, 0.7, 3 + seed, 5, 3)
+    text = synth.gen_forest_text(shape, 120 + seed)
+    comp, meta = C.forest_compile_ex(text, shape.n_features, 5, 12, server_replication=True)
+    oc = OC.server_replicated(OC.compile_forest(text, shape.n_features, 5))
+    assert meta.server_rep == 1 and meta.block_w == oc.W and meta.n1_F == OC.bsgs_n1(shape.n_features)
+    _, plain = C.forest_compile(text, shape.n_features, 5, 12)
+    assert meta.depth == plain.depth + 1
+    pl = CI.make_plan(oc, 1 << 12, 20)
+    assert C.compiled_rotations(meta) == pl.rotations()
