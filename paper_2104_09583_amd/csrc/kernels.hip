@@ -61,6 +61,17 @@ __device__ __forceinline__ double reduce_sym(double x, double q, double qinv) {
 }
 __device__ __forceinline__ double canon(double x, double q) { return x < 0.0 ? x + q : x; }
 
+// A load known to be from global memory (not through a flat address).  Flat loads count on the same
+// wait counter as LDS and scalar loads, so every LDS wait before a barrier would also wait for them;
+// global loads count only on the vector-memory counter.
+__device__ __forceinline__ double gload(const double* p) {
+  return *(const __attribute__((address_space(1))) double*)(p);
+}
+// Workgroup barrier for LDS exchanges: waits for this wave's LDS accesses only, so global loads issued
+// before it (the next round's twiddles, an epilogue's operands) stay in flight across it.  The memory
+// clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // ------------------------------------------------------------------ automorphism (evaluation domain)
 // Slot k holds a(psi^e) with e = 2 bitrev(k) + 1.  sigma_g(a)(psi^e) = a(psi^(g e)), so the
 // output slot k reads the input slot holding exponent g e mod 2N.
@@ -401,6 +412,42 @@ __global__ __launch_bounds__(256) void ntt_rowreg_kernel(double* __restrict__ ba
   }
 }
 
+// Twiddles of one radix-8 round of a thread whose 8 elements gb + d k (k < 8) lie in one aligned block of
+// 8 d at stage offset m (the round's three stages use 1, 2 and 4 of them).
+struct Tw8 {
+  double w0, w1a, w1b, w2[4];
+};
+__device__ __forceinline__ Tw8 tw8_load(const double* tab, size_t gb, size_t d, size_t m) {
+  const size_t g0 = gb / (8 * d);
+  Tw8 w;
+  w.w0 = gload(tab + m + g0);
+  w.w1a = gload(tab + 2 * m + 2 * g0);
+  w.w1b = gload(tab + 2 * m + 2 * g0 + 1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w.w2[k] = gload(tab + 4 * m + 4 * g0 + k);
+  return w;
+}
+__device__ __forceinline__ void radix8_ct_w(double* x, const Tw8& w, const DevPrime& pr) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_ct(x[k], x[k + 4], w.w0, pr.q, pr.qinv);
+  bfly_ct(x[0], x[2], w.w1a, pr.q, pr.qinv);
+  bfly_ct(x[1], x[3], w.w1a, pr.q, pr.qinv);
+  bfly_ct(x[4], x[6], w.w1b, pr.q, pr.qinv);
+  bfly_ct(x[5], x[7], w.w1b, pr.q, pr.qinv);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_ct(x[2 * k], x[2 * k + 1], w.w2[k], pr.q, pr.qinv);
+}
+__device__ __forceinline__ void radix8_gs_w(double* x, const Tw8& w, const DevPrime& pr) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_gs(x[2 * k], x[2 * k + 1], w.w2[k], pr.q, pr.qinv);
+  bfly_gs(x[0], x[2], w.w1a, pr.q, pr.qinv);
+  bfly_gs(x[1], x[3], w.w1a, pr.q, pr.qinv);
+  bfly_gs(x[4], x[6], w.w1b, pr.q, pr.qinv);
+  bfly_gs(x[5], x[7], w.w1b, pr.q, pr.qinv);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bfly_gs(x[k], x[k + 4], w.w0, pr.q, pr.qinv);
+}
+
 // Row pass over a tile of 4096 contiguous elements (stages S1..S1+11): 512 threads x 8 registers,
 // four radix-8 rounds (distances 2048/1024/512, 256/128/64, 32/16/8, 4/2/1) with three LDS exchanges.
 constexpr int kLdsTile4 = 4096 + 4096 / 16;
@@ -409,40 +456,52 @@ constexpr int kLdsTile4 = 4096 + 4096 / 16;
 // exchanges between them and one more so that global memory is always touched at t + 512 k (each
 // load or store instruction covers 512 consecutive bytes per wave).  Both directions read src[t + 512 k]
 // of the tile and leave the values of tile positions t + 512 k in x[k] (signed, not reduced).  gb0 is the
-// tile's first index in the row (twiddle groups).
+// tile's first index in the row (twiddle groups).  The twiddles of the first two rounds are loaded with
+// the data and those of every later round one round ahead, so a small launch waits on memory once.
+// With pre given, the forward tile also loads pre[t + 512 k] into y[k] during its third round (an
+// epilogue's operand, so that its latency overlaps the transform).
 __device__ __forceinline__ void row4_fwd_tile(const double* __restrict__ src, size_t gb0, int S1, const DevPrime& pr,
-                                              double* sh, double x[8]) {
+                                              double* sh, double x[8], const double* pre = nullptr,
+                                              double* y = nullptr) {
   const int t = threadIdx.x;
   const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
   const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
+  const Tw8 wa = tw8_load(pr.fwd, gb0 + jA, 512, mA);
+  const Tw8 wb = tw8_load(pr.fwd, gb0 + jB, 64, mB);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) x[k] = src[jA + 512 * k];
-  radix8_ct(x, gb0 + jA, 512, mA, pr);
+  for (int k = 0; k < 8; ++k) x[k] = gload(src + jA + 512 * k);
+  radix8_ct_w(x, wa, pr);
+  const Tw8 wc = tw8_load(pr.fwd, gb0 + jC, 8, mC);
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = x[k];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
-  radix8_ct(x, gb0 + jB, 64, mB, pr);
+  radix8_ct_w(x, wb, pr);
+  const Tw8 wd = tw8_load(pr.fwd, gb0 + jD, 1, mD);
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
-  radix8_ct(x, gb0 + jC, 8, mC, pr);
+  if (pre != nullptr) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y[k] = gload(pre + t + 512 * k);
+  }
+  radix8_ct_w(x, wc, pr);
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
-  radix8_ct(x, gb0 + jD, 1, mD, pr);
+  radix8_ct_w(x, wd, pr);
   // each thread overwrites only the LDS words it just read
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 512 * k)];
 }
@@ -452,33 +511,37 @@ __device__ __forceinline__ void row4_inv_tile(const double* __restrict__ src, si
   const int t = threadIdx.x;
   const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
   const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
+  const Tw8 wd = tw8_load(pr.inv, gb0 + jD, 1, mD);
+  const Tw8 wc = tw8_load(pr.inv, gb0 + jC, 8, mC);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = src[jA + 512 * k];
-  __syncthreads();
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = gload(src + jA + 512 * k);
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
-  radix8_gs(x, gb0 + jD, 1, mD, pr);
+  radix8_gs_w(x, wd, pr);
+  const Tw8 wb = tw8_load(pr.inv, gb0 + jB, 64, mB);
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
-  radix8_gs(x, gb0 + jC, 8, mC, pr);
+  radix8_gs_w(x, wc, pr);
+  const Tw8 wa = tw8_load(pr.inv, gb0 + jA, 512, mA);
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
-  radix8_gs(x, gb0 + jB, 64, mB, pr);
+  radix8_gs_w(x, wb, pr);
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 512 * k)];
-  radix8_gs(x, gb0 + jA, 512, mA, pr);
+  radix8_gs_w(x, wa, pr);
 }
 
 template <bool kInverse>
@@ -542,8 +605,9 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
 //            out_job[k][i] = in_job[k][i] q_l^-1 - w t q_l^-1  (+ add_job[k][i] for k < add_np)
 // mul/tmul are P^-1 and t P^-1 per limb (kMode 1) or the modulus-switch table (q_l^-1 at 2 + 2 i,
 // t q_l^-1 at 3 + 2 i).  Outputs are canonical.
+// at most 80 VGPRs: three workgroups per CU, as for the plain row pass
 template <int kMode>
-__global__ __launch_bounds__(512) void ntt_rowfwd_finish_kernel(MPack out, Pack in, Pack add, GPack gal, Pack ws,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void ntt_rowfwd_finish_kernel(MPack out, Pack in, Pack add, GPack gal, Pack ws,
                                                                Pack tabs, IPack lvs,
                                                                const double* __restrict__ acc,
                                                                const double* __restrict__ w, int nE, int nl_,
@@ -563,18 +627,20 @@ __global__ __launch_bounds__(512) void ntt_rowfwd_finish_kernel(MPack out, Pack 
   const int t = threadIdx.x;
   double x[8];
   const double* wrow = kMode == 1 ? w + ((size_t)z * nl + i) * N : ws.p[j] + ((size_t)k * nl + i) * N;
-  row4_fwd_tile(wrow + t0, t0, S1, pr, sh, x);
   const double* tab = kMode == 1 ? nullptr : tabs.p[j];
   const double m1 = kMode == 1 ? mul[i] : tab[2 + 2 * i];
   const double m2 = kMode == 1 ? tmul[i] : tab[3 + 2 * i];
   const size_t orow = ((size_t)k * nl + i) * N;
   const double* yrow = kMode == 1 ? acc + ((size_t)z * nE + i) * N : in.p[j] + ((size_t)k * (nl + 1) + i) * N;
   const uint64_t g = kMode == 1 ? gal.g[j] : 1;
+  // the epilogue's main operand is loaded during the transform, so its latency overlaps it
+  double yv[8];
+  row4_fwd_tile(wrow + t0, t0, S1, pr, sh, x, yrow + t0, yv);
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) {
     const size_t c = t0 + t + 512 * kk;
     const double wv = reduce_sym(x[kk], pr.q, pr.qinv);
-    double v = mul_lazy(yrow[c], m1, pr.q, pr.qinv) - mul_lazy(wv, m2, pr.q, pr.qinv);
+    double v = mul_lazy(yv[kk], m1, pr.q, pr.qinv) - mul_lazy(wv, m2, pr.q, pr.qinv);
     v = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
     if (kMode == 1) {
       if (add_mode == 1) v = mod_add(v, add.p[j][orow + c], pr.q);
@@ -1617,11 +1683,6 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
 // Sums are lazy (|term| < 0.91 q) and folded back with reduce_sym every kRed baby steps.
 // grid: x = (N / 64) x ceil(G / 4) (XCD-aware), y = limbs, z = giant-group chunks of GM.
 constexpr int kMmLanes = 64, kMmWaves = 4;
-// a load known to be from global memory (not through a flat address): it does not hold up the scalar
-// loads of the pointer table, which flat loads would (both count on the same wait counter)
-__device__ __forceinline__ double gload(const double* p) {
-  return *(const __attribute__((address_space(1))) double*)(p);
-}
 template <int GM, bool kEnc>
 __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out, const double* __restrict__ baby,
                                                        const double* const* __restrict__ tab, int n_u, int ng, int G,
