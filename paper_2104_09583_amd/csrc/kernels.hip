@@ -67,6 +67,28 @@ __device__ __forceinline__ double canon(double x, double q) { return x < 0.0 ? x
 __device__ __forceinline__ double gload(const double* p) {
   return *(const __attribute__((address_space(1))) double*)(p);
 }
+// A load of a value that is uniform across the wave from a table no kernel writes (twiddles, row
+// descriptors, primes, conversion constants): read through the constant address space, so it is a scalar
+// load into scalar registers.
+template <class T>
+__device__ __forceinline__ T cload(const T* p) {
+  static_assert(std::is_scalar<T>::value, "scalar loads take numbers and pointers");
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+__device__ __forceinline__ int2 cload_row(const int2* p) {
+  const int* w = reinterpret_cast<const int*>(p);
+  return make_int2(cload(w), cload(w + 1));
+}
+// the fields of a prime the transforms use (q, 1/q, twiddle tables, N^-1)
+__device__ __forceinline__ DevPrime cload_prime(const DevPrime* p) {
+  DevPrime r;
+  r.q = cload(&p->q);
+  r.qinv = cload(&p->qinv);
+  r.fwd = cload(&p->fwd);
+  r.inv = cload(&p->inv);
+  r.ninv = cload(&p->ninv);
+  return r;
+}
 // Workgroup barrier for LDS exchanges: waits for this wave's LDS accesses only, so global loads issued
 // before it (the next round's twiddles, an epilogue's operands) stay in flight across it.  The memory
 // clobber keeps the compiler from moving LDS accesses across it.
@@ -782,6 +804,30 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
 constexpr int kBridgeIn = 4;
 // A workgroup is 64 columns x 4 waves: wave k runs the inverse stages of input row k (k < n_in) and
 // leaves [coef * mult_k] in LDS; then the four waves take the outputs of the block's chunk in turn.
+// What a wave needs for one output row besides the LDS values: its place, prime and twiddles and its
+// column of the conversion matrix.  All uniform (scalar registers); loaded one output ahead so that the
+// chain row descriptor -> prime -> twiddles is off the critical path.
+template <int S1>
+struct BridgeOut {
+  int2 row;
+  double q, qinv;
+  double w[1 << S1];   // fwd twiddles 1 .. 2^S1 - 1 of the first S1 stages
+  double m[kBridgeIn];
+};
+template <int S1, int kMode>
+__device__ __forceinline__ BridgeOut<S1> bridge_out_load(const BridgeDesc& d, const DevPrime* __restrict__ P, int o) {
+  BridgeOut<S1> b;
+  b.row = cload_row(d.out_rows + o);
+  const DevPrime po = cload_prime(P + b.row.y);
+  b.q = po.q;
+  b.qinv = po.qinv;
+#pragma unroll
+  for (int k = 1; k < (1 << S1); ++k) b.w[k] = cload(po.fwd + k);
+#pragma unroll
+  for (int k = 0; k < kBridgeIn; ++k) b.m[k] = (kMode == 0 && k < d.n_in) ? cload(d.mat + k * d.n_out + o) : 0.0;
+  return b;
+}
+
 template <int S1, int kMode>
 __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const DevPrime* __restrict__ P, int logN) {
   constexpr int R = 1 << S1;
@@ -802,40 +848,51 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
   const int n_in = d.n_in, n_out = d.n_out;
   const double* in = d.in + (size_t)blockIdx.z * d.in_bs;
   double* out = d.out + (size_t)blockIdx.z * d.out_bs;
+  // this wave's outputs: o0 + wv, o0 + wv + 4, ... below o1; the first one's parameters are fetched now
+  const int o0 = ((int)blockIdx.y - d.chunk0) * d.ochunk;
+  const int o1 = min(n_out, o0 + d.ochunk);
+  int o = o0 + wv;
+  BridgeOut<S1> cur;
+  if (o < o1) cur = bridge_out_load<S1, kMode>(d, P, o);
   if (wv < n_in && active) {
-    const int2 irow = d.in_rows[wv];
-    const DevPrime& pk = P[irow.y];
+    const int2 irow = cload_row(d.in_rows + wv);
+    const DevPrime pk = cload_prime(P + irow.y);
     const double* a = in + (size_t)irow.x * N;
     double x[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = a[r * C + c];
+    for (int r = 0; r < R; ++r) x[r] = gload(a + r * C + c);
+    double wi[R];
+#pragma unroll
+    for (int k = 1; k < R; ++k) wi[k] = cload(pk.inv + k);
+    // N^-1 mult_k mod p_k: one product per coefficient gives the canonical [coef * mult_k]_{p_k}
+    const double nm = canon(reduce_sym(mul_lazy(pk.ninv, cload(d.mult + wv), pk.q, pk.qinv), pk.q, pk.qinv), pk.q);
 #pragma unroll
     for (int s = S1 - 1; s >= 0; --s) {
       const int half = R >> (s + 1);
 #pragma unroll
       for (int g = 0; g < (1 << s); ++g) {
-        const double w = pk.inv[(1 << s) + g];
+        const double w = wi[(1 << s) + g];
 #pragma unroll
-        for (int o = 0; o < half; ++o) bfly_gs(x[g * 2 * half + o], x[g * 2 * half + o + half], w, pk.q, pk.qinv);
+        for (int oo = 0; oo < half; ++oo) bfly_gs(x[g * 2 * half + oo], x[g * 2 * half + oo + half], w, pk.q, pk.qinv);
       }
     }
-    const double mk = d.mult[wv];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      // coefficient in [0, p_k), then [coef * mult_k]_{p_k} in [0, p_k)
-      const double cf = canon(reduce_sym(mul_lazy(x[r], pk.ninv, pk.q, pk.qinv), pk.q, pk.qinv), pk.q);
-      double v = canon(mul_lazy(cf, mk, pk.q, pk.qinv), pk.q);
+      // for S1 <= 3, |x| < 4 p_k, so the lazy product lies in (-p_k, p_k) and canon gives
+      // [coef * mult_k]_{p_k}; four stages can reach 8 p_k, so the product is folded back first
+      double v = mul_lazy(x[r], nm, pk.q, pk.qinv);
+      if (S1 > 3) v = reduce_sym(v, pk.q, pk.qinv);
+      v = canon(v, pk.q);
       if (kMode == 1 && v > (pk.q - 1.0) * 0.5) v -= pk.q;
       ys[wv][r][lane] = v;
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (!active) return;
-  const int o0 = ((int)blockIdx.y - d.chunk0) * d.ochunk;
-  const int o1 = min(n_out, o0 + d.ochunk);
-  for (int o = o0 + wv; o < o1; o += 4) {
-    const int2 orow = d.out_rows[o];
-    const DevPrime& po = P[orow.y];
+  for (; o < o1; o += 4) {
+    BridgeOut<S1> nxt;
+    if (o + 4 < o1) nxt = bridge_out_load<S1, kMode>(d, P, o + 4);
+    const double q = cur.q, qinv = cur.qinv;
     double x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -843,10 +900,10 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kBridgeIn; ++k)
-          if (k < n_in) acc += mul_lazy(ys[k][r][lane], d.mat[k * n_out + o], po.q, po.qinv);
-        x[r] = reduce_sym(acc, po.q, po.qinv);
+          if (k < n_in) acc += mul_lazy(ys[k][r][lane], cur.m[k], q, qinv);
+        x[r] = reduce_sym(acc, q, qinv);
       } else {
-        x[r] = reduce_sym(ys[0][r][lane], po.q, po.qinv);
+        x[r] = reduce_sym(ys[0][r][lane], q, qinv);
       }
     }
 #pragma unroll
@@ -854,14 +911,15 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
       const int half = R >> (s + 1);
 #pragma unroll
       for (int g = 0; g < (1 << s); ++g) {
-        const double w = po.fwd[(1 << s) + g];
+        const double w = cur.w[(1 << s) + g];
 #pragma unroll
-        for (int oo = 0; oo < half; ++oo) bfly_ct(x[g * 2 * half + oo], x[g * 2 * half + oo + half], w, po.q, po.qinv);
+        for (int oo = 0; oo < half; ++oo) bfly_ct(x[g * 2 * half + oo], x[g * 2 * half + oo + half], w, q, qinv);
       }
     }
-    double* a = out + (size_t)orow.x * N;
+    double* a = out + (size_t)cur.row.x * N;
 #pragma unroll
-    for (int r = 0; r < R; ++r) a[r * C + c] = reduce_sym(x[r], po.q, po.qinv);
+    for (int r = 0; r < R; ++r) a[r * C + c] = reduce_sym(x[r], q, qinv);
+    cur = nxt;
   }
 }
 
