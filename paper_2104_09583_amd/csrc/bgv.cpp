@@ -188,6 +188,35 @@ KSTables& Context::kstab(int level) {
       ms.push_back((double)mulmod(t % q, inv, q));
     }
     T->d_ms = upload(T->owned, ms);
+    // ModDown merged with the switch to level - 1 (see launch_ntt_fwd_rows_mdms_finish)
+    std::vector<double> mm_mult, mm_mat, m1, m2, m3;
+    for (int r = 0; r < alpha; ++r) mm_mult.push_back(mdm[r]);
+    uint64_t Pl = 1;
+    for (int r = 0; r < alpha; ++r) Pl = mulmod(Pl, primes[L + 1 + r] % ql, ql);
+    mm_mult.push_back((double)invmod(mulmod(t % ql, Pl, ql), ql));
+    for (int r = 0; r < alpha; ++r)
+      for (int i = 0; i <= level; ++i) {
+        uint64_t q = primes[i];
+        mm_mat.push_back((double)invmod(primes[L + 1 + r] % q, q));
+      }
+    bool ok = true;
+    for (int i = 0; i < level; ++i) {
+      uint64_t q = primes[i];
+      uint64_t P = 1;
+      for (int r = 0; r < alpha; ++r) P = mulmod(P, primes[L + 1 + r] % q, q);
+      uint64_t qlinv = invmod(ql % q, q);
+      m1.push_back((double)mulmod(invmod(P, q), qlinv, q));
+      m2.push_back((double)mulmod(t % q, qlinv, q));
+      m3.push_back((double)qlinv);
+      ok = ok && ql < 4 * q;
+    }
+    T->d_mm_mult = upload(T->owned, mm_mult);
+    T->d_mm_mat = upload(T->owned, mm_mat);
+    T->d_mm_m1 = upload(T->owned, m1);
+    T->d_mm_m2 = upload(T->owned, m2);
+    T->d_mm_m3 = upload(T->owned, m3);
+    T->mm_ptop = (double)Pl;
+    T->mm_ok = ok;
   }
   auto& ref = *T;
   ks[level] = std::move(T);

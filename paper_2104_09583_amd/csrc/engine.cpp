@@ -162,18 +162,22 @@ struct KsReq {
   const double* add;    // mode 1: (d0, d1) to add; mode 2: c0 to permute and add
 };
 
+// merge (add_mode 1 only): the ModDown also switches to level - 1, as a relinearization followed by a
+// modulus switch would; each request's out then holds 2 polys of `level` limbs
 static void ks_batch(Context& c, int level, const std::vector<const double*>& inputs, const std::vector<KsReq>& reqs,
-                     int add_mode) {
+                     int add_mode, bool merge = false) {
   if (reqs.empty()) return;
   const size_t N = c.N;
   const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
   const int I = (int)inputs.size(), R = (int)reqs.size();
   const int Lt = c.n_primes();
   KSTables& T = c.kstab(level);
+  const bool fused = bridge_supported(c, c.alpha);
+  if (merge && !(fused && add_mode == 1 && level >= 1 && T.mm_ok))
+    fail(COPSE_EINVAL, "internal: merged switch not available here");
   // ModUp of every input: coefficient form, base conversion per digit, transform of the new rows
   DBuf cf(&c, (size_t)I * nl * N);
   DBuf ext(&c, (size_t)I * D * nE * N);
-  const bool fused = bridge_supported(c, c.alpha);
   if (!fused) launch_gather(c, cf.get(), inputs, nl);
   if (fused) {
     // inverse row pass read straight from the inputs, then per digit the fused column passes with the
@@ -222,9 +226,40 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   for (int q = 0; q < R; ++q) {
     const KsReq& rq = reqs[q];
     jobs.push_back(KsJob2{inputs[rq.input], ext.get() + (size_t)rq.input * D * nE * N, rq.key->b.get(),
-                          rq.key->a.get(), acc.get() + (size_t)q * 2 * nE * N, rq.g});
+                          rq.key->a.get(), acc.get() + (size_t)q * 2 * nE * N, rq.g, merge ? rq.add : nullptr});
   }
-  launch_ks_inner2(c, jobs, D, nE, level, (size_t)Lt * N);
+  launch_ks_inner2(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
+  if (merge) {
+    // ModDown by P and switch by q_l in one pass: the top data row (now y_l + P a_l) joins the special rows
+    // in the inverse transform, the fused column pass lifts the switched top limb, and the finish writes
+    // the result at level - 1
+    const int l = level;
+    const int2* r = rows_cached(c, "mdmsrows:" + std::to_string(level) + ":" + std::to_string(2 * R), [&] {
+      std::vector<int2> h;
+      for (int k = 0; k < 2 * R; ++k) {
+        for (int s2 = 0; s2 < c.alpha; ++s2) h.push_back(make_int2(k * nE + nl + s2, c.L + 1 + s2));
+        h.push_back(make_int2(k * nE + l, l));
+      }
+      return h;
+    }());
+    launch_ntt_inv_rows(c, acc.get(), r, 2 * R * (c.alpha + 1));
+    std::vector<int2> inr, outr;
+    for (int s2 = 0; s2 < c.alpha; ++s2) inr.push_back(make_int2(nl + s2, c.L + 1 + s2));
+    inr.push_back(make_int2(l, l));
+    for (int i = 0; i < l; ++i) outr.push_back(make_int2(i, i));
+    DBuf w(&c, (size_t)2 * R * l * N);
+    launch_bridge(c, 2, w.get(), rows_cached(c, "mdmsout:" + std::to_string(level), outr), l, acc.get(),
+                  rows_cached(c, "mdmsin:" + std::to_string(level), inr), c.alpha + 1, T.d_mm_mult, T.d_mm_mat,
+                  2 * R, (size_t)nE * N, (size_t)l * N);
+    std::vector<double*> outs;
+    std::vector<const double*> adds;
+    for (auto& rq : reqs) {
+      outs.push_back(rq.out);
+      adds.push_back(rq.add);
+    }
+    launch_ntt_fwd_rows_mdms_finish(c, outs, adds, acc.get(), w.get(), nE, l, T.d_mm_m1, T.d_mm_m2, T.d_mm_m3);
+    return;
+  }
   // ModDown of all accumulators
   {
     std::string key = "mdspec:" + std::to_string(level) + ":" + std::to_string(2 * R);
@@ -269,15 +304,16 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   launch_md_finish2(c, outs, adds, gal, acc.get(), zh.get(), nE, nl, T.d_md_pinv, T.d_md_tpinv, add_mode);
 }
 
-// relinearize 3-component ciphertexts (any mix of levels)
-static std::vector<SCt> b_relin(Context& c, const Keys& k, const std::vector<const Ct*>& in3) {
+// relinearize 3-component ciphertexts (any mix of levels); with switch_down, each result is also switched
+// to one level lower, bit-identical to b_modswitch of the relinearized ciphertext
+static std::vector<SCt> b_relin(Context& c, const Keys& k, const std::vector<const Ct*>& in3, bool switch_down = false) {
   if (!k.relin) fail(COPSE_EKEY, "relinearization key absent");
   std::vector<SCt> out(in3.size());
   std::map<int, std::vector<size_t>> groups;
   for (size_t i = 0; i < in3.size(); ++i) groups[in3[i]->level].push_back(i);
   for (auto& kv : groups) {
     const int l = kv.first;
-    auto outs = alloc_batch(c, (int)kv.second.size(), l, 2);
+    auto outs = alloc_batch(c, (int)kv.second.size(), switch_down ? l - 1 : l, 2);
     std::vector<const double*> inputs;
     std::vector<KsReq> reqs;
     for (size_t q = 0; q < kv.second.size(); ++q) {
@@ -286,9 +322,14 @@ static std::vector<SCt> b_relin(Context& c, const Keys& k, const std::vector<con
       reqs.push_back(KsReq{(int)q, k.relin.get(), 1, outs[q]->data(), x->data()});
       out[kv.second[q]] = outs[q];
     }
-    ks_batch(c, l, inputs, reqs, 1);
+    ks_batch(c, l, inputs, reqs, 1, switch_down);
   }
   return out;
+}
+
+// whether a product at level l can relinearize and switch in one key switch
+static bool merged_switch_ok(Context& c, int l) {
+  return l >= 1 && bridge_supported(c, c.alpha) && c.kstab(l).mm_ok;
 }
 
 // products of pairs: equalize, tensor, relinearize, switch
@@ -321,10 +362,15 @@ std::vector<SCt> b_mul(Context& c, const Keys& k, const std::vector<std::pair<SC
     launch_tensor_multi(c, d, a, b, l + 1);
     std::vector<const Ct*> in3;
     for (auto& x : t3) in3.push_back(x.get());
-    auto rel = b_relin(c, k, in3);
-    std::vector<const Ct*> rin;
-    for (auto& x : rel) rin.push_back(x.get());
-    auto ms = b_modswitch(c, rin);
+    std::vector<SCt> ms;
+    if (merged_switch_ok(c, l)) {
+      ms = b_relin(c, k, in3, true);
+    } else {
+      auto rel = b_relin(c, k, in3);
+      std::vector<const Ct*> rin;
+      for (auto& x : rel) rin.push_back(x.get());
+      ms = b_modswitch(c, rin);
+    }
     for (size_t q = 0; q < kv.second.size(); ++q) out[kv.second[q]] = ms[q];
   }
   return out;

@@ -199,6 +199,16 @@ struct KSTables {
   double* d_md_tpinv = nullptr;  // [nl] t P^-1 mod q_i
   // Modulus switch from this level to level-1
   double* d_ms = nullptr;        // [4 + 2*level]: q_l, t^-1 mod q_l, then per i<l: q_l^-1, t q_l^-1
+  // ModDown merged with the switch to level-1 (level >= 1): conversion multipliers of the special rows
+  // and (t P)^-1 mod q_l for the top row, [alpha][level + 1] p_r^-1 mod q_i, and the finish factors
+  // (P q_l)^-1, t q_l^-1, q_l^-1 mod q_i for i < level; ptop = P mod q_l
+  double* d_mm_mult = nullptr;
+  double* d_mm_mat = nullptr;
+  double* d_mm_m1 = nullptr;
+  double* d_mm_m2 = nullptr;
+  double* d_mm_m3 = nullptr;
+  double mm_ptop = 0.0;
+  bool mm_ok = false;            // the merged step's bounds hold for this chain (q_l < 4 q_i for i < l)
   std::vector<double*> owned;
 };
 
@@ -219,6 +229,11 @@ void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const
 void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
                                    const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE,
                                    int nl, const double* pinv, const double* tpinv, int add_mode);
+// forward row pass of the merged ModDown + switch rows w (l = level of the inputs, l output limbs) fused
+// with its finish: out_j[k][i] = acc[2j+k][i] m1_i + add_j[k][i] m3_i - w[2j+k][i] m2_i  (i < l)
+void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out,
+                                     const std::vector<const double*>& add, const double* acc, const double* w,
+                                     int nE, int l, const double* m1, const double* m2, const double* m3);
 // forward row pass of the modulus-switch rows fused with the switch's finish; job j switches from
 // levels[j], its rows w[j] = [np][levels[j]][N], its table tabs[j] (as launch_ms_finish_multi)
 void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
@@ -249,7 +264,9 @@ struct BridgeSet {
 };
 void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_base, std::vector<BridgeDesc> descs,
                        int batch, size_t in_bs, size_t out_bs);
-// mode 0: fast base conversion (as launch_bconv); mode 1: modulus-switch lift of one row (mult = t^-1)
+// mode 0: fast base conversion (as launch_bconv); mode 1: modulus-switch lift of one row (mult = t^-1);
+// mode 2: ModDown merged with the modulus switch: n_in = alpha special rows and the top row, mat is
+// [alpha][n_out + 1] (the last column for the top prime), see ntt_bridge_kernel
 void launch_bridge(Context& c, int mode, double* out_base, const int2* out_rows, int n_out, const double* in_base,
                    const int2* in_rows, int n_in, const double* mult, const double* mat, int batch, size_t in_bs,
                    size_t out_bs);
@@ -313,6 +330,9 @@ struct KsJob2 {
   const double* ka;
   double* acc;           // [2][nE][N]
   uint64_t g;
+  // optional (relinearization merged with the switch): the 2 polys of the addend (NTT form, nl limbs);
+  // P times their top limb is added to the top data row of acc
+  const double* top = nullptr;
 };
 struct KsPack {
   static constexpr int kMax = 16;
@@ -328,7 +348,9 @@ void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::v
 void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
                             const double* w, int np, int level, const double* tab,
                             const std::vector<const double*>* add = nullptr, int add_np = 0);
-void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds);
+// ptop: P mod q_level, the factor of the jobs' top addends
+void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
+                      double ptop = 0.0);
 void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
                        const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE, int nl,
                        const double* pinv, const double* tpinv, int add_mode);

@@ -625,6 +625,9 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
 //            + add_job[0][i] at the automorphism's source index when add_mode 2 and k = 0)
 //   kMode 2: block (tile, i, z = job * np + k) transforms w row z * l + i and writes
 //            out_job[k][i] = in_job[k][i] q_l^-1 - w t q_l^-1  (+ add_job[k][i] for k < add_np)
+//   kMode 3: as kMode 1 for a ModDown merged with the switch by q_l (l = nl output limbs, the addend
+//            add_job has l + 1 limbs): out_job[k][i] = acc[z][i] mul_i + add_job[k][i] amul_i - w tmul_i
+//            with mul = (P q_l)^-1, tmul = t q_l^-1, amul = q_l^-1
 // mul/tmul are P^-1 and t P^-1 per limb (kMode 1) or the modulus-switch table (q_l^-1 at 2 + 2 i,
 // t q_l^-1 at 3 + 2 i).  Outputs are canonical.
 // at most 80 VGPRs: three workgroups per CU, as for the plain row pass
@@ -636,24 +639,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
                                                                int np, int add_mode, int add_np,
                                                                const double* __restrict__ mul,
                                                                const double* __restrict__ tmul,
-                                                               const DevPrime* __restrict__ P, int logN, int S1) {
+                                                               const DevPrime* __restrict__ P, int logN, int S1,
+                                                               const double* __restrict__ amul) {
   __shared__ double sh[kLdsTile4];
   const int i = blockIdx.y, z = blockIdx.z;
-  const int j = kMode == 1 ? (z >> 1) : z / np, k = kMode == 1 ? (z & 1) : z % np;
+  constexpr bool kMd = kMode != 2;   // ModDown layout (2 polys per job, accumulator rows)
+  const int j = kMd ? (z >> 1) : z / np, k = kMd ? (z & 1) : z % np;
   // kMode 2: job j switches from level lv[j]: it writes nl = lv[j] limbs per poly below an input with nl + 1
-  const int nl = kMode == 1 ? nl_ : lvs.v[j];
+  const int nl = kMd ? nl_ : lvs.v[j];
   if (i >= nl) return;   // uniform per workgroup, before any barrier
   const DevPrime pr = P[i];
   const size_t N = (size_t)1 << logN;
   const size_t t0 = (size_t)blockIdx.x * 4096;
   const int t = threadIdx.x;
   double x[8];
-  const double* wrow = kMode == 1 ? w + ((size_t)z * nl + i) * N : ws.p[j] + ((size_t)k * nl + i) * N;
-  const double* tab = kMode == 1 ? nullptr : tabs.p[j];
-  const double m1 = kMode == 1 ? mul[i] : tab[2 + 2 * i];
-  const double m2 = kMode == 1 ? tmul[i] : tab[3 + 2 * i];
+  const double* wrow = kMd ? w + ((size_t)z * nl + i) * N : ws.p[j] + ((size_t)k * nl + i) * N;
+  const double* tab = kMd ? nullptr : tabs.p[j];
+  const double m1 = kMd ? mul[i] : tab[2 + 2 * i];
+  const double m2 = kMd ? tmul[i] : tab[3 + 2 * i];
+  const double m3 = kMode == 3 ? amul[i] : 0.0;
   const size_t orow = ((size_t)k * nl + i) * N;
-  const double* yrow = kMode == 1 ? acc + ((size_t)z * nE + i) * N : in.p[j] + ((size_t)k * (nl + 1) + i) * N;
+  const double* yrow = kMd ? acc + ((size_t)z * nE + i) * N : in.p[j] + ((size_t)k * (nl + 1) + i) * N;
   const uint64_t g = kMode == 1 ? gal.g[j] : 1;
   // the epilogue's main operand is loaded during the transform, so its latency overlaps it
   double yv[8];
@@ -663,6 +669,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
     const size_t c = t0 + t + 512 * kk;
     const double wv = reduce_sym(x[kk], pr.q, pr.qinv);
     double v = mul_lazy(yv[kk], m1, pr.q, pr.qinv) - mul_lazy(wv, m2, pr.q, pr.qinv);
+    if (kMode == 3) v += mul_lazy(add.p[j][((size_t)k * (nl + 1) + i) * N + c], m3, pr.q, pr.qinv);
     v = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
     if (kMode == 1) {
       if (add_mode == 1) v = mod_add(v, add.p[j][orow + c], pr.q);
@@ -670,7 +677,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
         const size_t src = g == 1 ? c : auto_src((uint32_t)c, g, logN);
         v = mod_add(v, add.p[j][(size_t)i * N + src], pr.q);
       }
-    } else if (k < add_np && add.p[j] != nullptr) {
+    } else if (kMode == 2 && k < add_np && add.p[j] != nullptr) {
       v = mod_add(v, add.p[j][orow + c], pr.q);
     }
     out.p[j][orow + c] = v;
@@ -797,6 +804,12 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
 // passes stay separate (launch_ntt_inv_rows / launch_ntt_fwd_rows).  Maps:
 //   kMode 0 (fast base conversion): out_o = sum_k [x_k mult_k]_{p_k} mat[k][o]  mod q_o
 //   kMode 1 (modulus switch):       z = [x_0 mult_0]_{p_0} centered,  out_o = z mod q_o
+//   kMode 2 (ModDown by P merged with the switch by q_l): inputs are the alpha special rows y_r and the
+//            top data row y_l (which already holds P times the addend's top limb); with
+//            z_r = [y_r mult_r]_{p_r} (mult_r = t^-1 (P/p_r)^-1) and s_o = sum_r z_r p_r^-1 mod q_o, the
+//            ModDown result's top limb times t^-1 is [y_l (t P)^-1 - s_l]_{q_l}; v is its centered value
+//            (the switch's lift) and out_o = s_o + v mod q_o for o < l.  mat is [alpha][n_out + 1]
+//            (p_r^-1 mod q_o, the last column for q_l), mult[alpha] = (t P)^-1 mod q_l.
 // The values handed to the forward stages are any representatives of the residues (|v| <= q/2), so the
 // transform's canonical output is the same as that of the unfused steps.
 // grid: x over column groups of 64, y over chunks of ochunk outputs (small batches: more blocks, the
@@ -823,15 +836,20 @@ __device__ __forceinline__ BridgeOut<S1> bridge_out_load(const BridgeDesc& d, co
   b.qinv = po.qinv;
 #pragma unroll
   for (int k = 1; k < (1 << S1); ++k) b.w[k] = cload(po.fwd + k);
+  // mode 2: the special rows' column of the [alpha][n_out + 1] matrix
+  const int n_conv = kMode == 2 ? d.n_in - 1 : d.n_in;
+  const int stride = kMode == 2 ? d.n_out + 1 : d.n_out;
 #pragma unroll
-  for (int k = 0; k < kBridgeIn; ++k) b.m[k] = (kMode == 0 && k < d.n_in) ? cload(d.mat + k * d.n_out + o) : 0.0;
+  for (int k = 0; k < kBridgeIn; ++k) b.m[k] = (kMode != 1 && k < n_conv) ? cload(d.mat + k * stride + o) : 0.0;
   return b;
 }
 
 template <int S1, int kMode>
 __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const DevPrime* __restrict__ P, int logN) {
   constexpr int R = 1 << S1;
-  __shared__ double ys[kBridgeIn][R][64];
+  // mode 2 has one more input (the top row) than conversion rows
+  constexpr int kSlots = kMode == 2 ? kBridgeIn + 1 : kBridgeIn;
+  __shared__ double ys[kSlots][R][64];
   const size_t N = (size_t)1 << logN;
   const size_t C = N >> S1;
   const int lane = threadIdx.x & 63;
@@ -854,8 +872,9 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
   int o = o0 + wv;
   BridgeOut<S1> cur;
   if (o < o1) cur = bridge_out_load<S1, kMode>(d, P, o);
-  if (wv < n_in && active) {
-    const int2 irow = cload_row(d.in_rows + wv);
+  // input k < n_in is run by wave k % 4
+  for (int ik = wv; ik < n_in && active; ik += 4) {
+    const int2 irow = cload_row(d.in_rows + ik);
     const DevPrime pk = cload_prime(P + irow.y);
     const double* a = in + (size_t)irow.x * N;
     double x[R];
@@ -865,7 +884,7 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
 #pragma unroll
     for (int k = 1; k < R; ++k) wi[k] = cload(pk.inv + k);
     // N^-1 mult_k mod p_k: one product per coefficient gives the canonical [coef * mult_k]_{p_k}
-    const double nm = canon(reduce_sym(mul_lazy(pk.ninv, cload(d.mult + wv), pk.q, pk.qinv), pk.q, pk.qinv), pk.q);
+    const double nm = canon(reduce_sym(mul_lazy(pk.ninv, cload(d.mult + ik), pk.q, pk.qinv), pk.q, pk.qinv), pk.q);
 #pragma unroll
     for (int s = S1 - 1; s >= 0; --s) {
       const int half = R >> (s + 1);
@@ -884,11 +903,31 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
       if (S1 > 3) v = reduce_sym(v, pk.q, pk.qinv);
       v = canon(v, pk.q);
       if (kMode == 1 && v > (pk.q - 1.0) * 0.5) v -= pk.q;
-      ys[wv][r][lane] = v;
+      ys[ik][r][lane] = v;
     }
   }
   lds_barrier();
   if (!active) return;
+  // mode 2: the switch's centered lift v of the top limb, per coefficient of this thread's column
+  double vt[kMode == 2 ? R : 1];
+  if (kMode == 2 && o < o1) {
+    const int nc = n_in - 1;
+    const int2 trow = cload_row(d.in_rows + nc);
+    const double ql = cload(&P[trow.y].q), qlinv = cload(&P[trow.y].qinv);
+    double mt[kBridgeIn];
+#pragma unroll
+    for (int k = 0; k < kBridgeIn; ++k) mt[k] = k < nc ? cload(d.mat + k * (n_out + 1) + n_out) : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double sl = 0.0;
+#pragma unroll
+      for (int k = 0; k < kBridgeIn; ++k)
+        if (k < nc) sl += mul_lazy(ys[k][r][lane], mt[k], ql, qlinv);
+      // z_r < 2^49, so each lazy product is below 0.6 q_l and |ys_top - sl| < 4 q_l: the symmetric
+      // reduction gives the centered representative
+      vt[r] = reduce_sym(ys[nc][r][lane] - sl, ql, qlinv);
+    }
+  }
   for (; o < o1; o += 4) {
     BridgeOut<S1> nxt;
     if (o + 4 < o1) nxt = bridge_out_load<S1, kMode>(d, P, o + 4);
@@ -896,11 +935,14 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
     double x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (kMode == 0) {
+      if (kMode != 1) {
+        const int nc = kMode == 2 ? n_in - 1 : n_in;
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kBridgeIn; ++k)
-          if (k < n_in) acc += mul_lazy(ys[k][r][lane], cur.m[k], q, qinv);
+          if (k < nc) acc += mul_lazy(ys[k][r][lane], cur.m[k], q, qinv);
+        // mode 2: |v| <= q_l / 2 < 2 q_o, so the sum stays below 8 q_o
+        if (kMode == 2) acc += vt[r];
         x[r] = reduce_sym(acc, q, qinv);
       } else {
         x[r] = reduce_sym(ys[0][r][lane], q, qinv);
@@ -946,8 +988,10 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
         d.nz = batch;
       }
       if (d.nz > kMaxGridY) fail(COPSE_EINVAL, "internal: batch too large for one fused column pass");
-      if (!bridge_supported(c, d.n_in)) fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
+      if (!bridge_supported(c, mode == 2 ? d.n_in - 1 : d.n_in))
+        fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
       if (mode == 1 && d.n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
+      if (mode == 2 && d.n_in < 2) fail(COPSE_EINVAL, "internal: merged switch needs special rows and the top row");
       if (d.n_out <= 0) fail(COPSE_EINVAL, "internal: conversion without outputs");
       // at least ~512 workgroups (2048 waves) when the batch is small, by splitting the outputs into chunks
       // of at least 4 (one per wave)
@@ -973,12 +1017,19 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
         case 3: COPSE_BRIDGE(3, 0); break;
         default: COPSE_BRIDGE(4, 0); break;
       }
-    } else {
+    } else if (mode == 1) {
       switch (S1) {
         case 1: COPSE_BRIDGE(1, 1); break;
         case 2: COPSE_BRIDGE(2, 1); break;
         case 3: COPSE_BRIDGE(3, 1); break;
         default: COPSE_BRIDGE(4, 1); break;
+      }
+    } else {
+      switch (S1) {
+        case 1: COPSE_BRIDGE(1, 2); break;
+        case 2: COPSE_BRIDGE(2, 2); break;
+        case 3: COPSE_BRIDGE(3, 2); break;
+        default: COPSE_BRIDGE(4, 2); break;
       }
     }
 #undef COPSE_BRIDGE
@@ -1078,9 +1129,37 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<1>, dim3((unsigned)(c.N / 4096), nl, 2 * cnt), dim3(512), 0,
                        c.stream, po, pin, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
                        w + first * 2 * nl * c.N, nE, nl, 2, add_mode, 0, pinv, tpinv, c.d_primes, (int)c.log_n,
-                       (int)c.log_n - 12);
+                       (int)c.log_n - 12, nullptr);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 7, ev, (6.0 + (add_mode == 1 ? 2.0 : add_mode == 2 ? 1.0 : 0.0)) * nl * cnt * (double)c.N * 8.0);
+  }
+}
+
+void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out,
+                                     const std::vector<const double*>& add, const double* acc, const double* w,
+                                     int nE, int l, const double* m1, const double* m2, const double* m3) {
+  if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  if (l < 1) fail(COPSE_EINVAL, "internal: no switch below level 0");
+  for (size_t first = 0; first < out.size(); first += kPack) {
+    const int cnt = (int)std::min<size_t>(kPack, out.size() - first);
+    MPack po;
+    Pack pa, none{};
+    GPack pg;
+    IPack nolv{};
+    for (int k = 0; k < cnt; ++k) {
+      po.p[k] = out[first + k];
+      pa.p[k] = add[first + k];
+      pg.g[k] = 1;
+    }
+    hipEvent_t ev;
+    prof_begin(c, 7, &ev);
+    hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<3>, dim3((unsigned)(c.N / 4096), l, 2 * cnt), dim3(512), 0,
+                       c.stream, po, none, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
+                       w + first * 2 * l * c.N, nE, l, 2, 0, 0, m1, m2, c.d_primes, (int)c.log_n,
+                       (int)c.log_n - 12, m3);
+    COPSE_HIP(hipGetLastError());
+    // per output row: the bridge's row, the accumulator and addend rows read, the output written
+    prof_end(c, 7, ev, 4.0 * l * 2 * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1113,7 +1192,7 @@ void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, 
     prof_begin(c, 8, &ev);
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<2>, dim3((unsigned)(c.N / 4096), lmax, np * cnt), dim3(512), 0,
                        c.stream, po, pi, pa, pg, pw, pt, lv, nullptr, nullptr, 0, 0, np, 0, add ? add_np : 0,
-                       nullptr, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12);
+                       nullptr, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12, nullptr);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 8, ev, bytes);
   }
@@ -1640,7 +1719,7 @@ void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const s
 
 // key-switch inner product over jobs; digit rows come straight from the job's input poly
 __global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha, int logN, size_t key_ds,
-                                 const DevPrime* P) {
+                                 const DevPrime* P, double ptop) {
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -1658,11 +1737,16 @@ __global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int 
     a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
     a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
   }
+  if (jb.top != nullptr && o == nl - 1) {   // uniform per workgroup
+    a0 += mul_lazy(jb.top[(size_t)o * N + i], ptop, pr.q, pr.qinv);
+    a1 += mul_lazy(jb.top[((size_t)nl + o) * N + i], ptop, pr.q, pr.qinv);
+  }
   jb.acc[(size_t)o * N + i] = canon(reduce_sym(a0, pr.q, pr.qinv), pr.q);
   jb.acc[((size_t)nE + o) * N + i] = canon(reduce_sym(a1, pr.q, pr.qinv), pr.q);
 }
 
-void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds) {
+void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
+                      double ptop) {
   for (size_t first = 0; first < jobs.size(); first += KsPack::kMax) {
     int cnt = (int)std::min<size_t>(KsPack::kMax, jobs.size() - first);
     KsPack pk;
@@ -1670,7 +1754,7 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
     hipEvent_t ev;
     prof_begin(c, 4, &ev);
     hipLaunchKernelGGL(ks_inner2_kernel, dim3((unsigned)((c.N + 255) / 256), nE, cnt), dim3(256), 0, c.stream, pk, D,
-                       nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes);
+                       nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes, ptop);
     COPSE_HIP(hipGetLastError());
     // per job and extended row: D digit rows read and 2 rows written; each distinct key's 2 D rows once
     int keys = 0;
