@@ -223,6 +223,47 @@ KSTables& Context::kstab(int level) {
   return ref;
 }
 
+const MsMulti& Context::ms_multi(int level, int k) {
+  if (k < 1 || k > 4 || k > level) fail(COPSE_EINVAL, "internal: switch by an unsupported prime count");
+  KSTables& T = kstab(level);
+  auto it = T.multi.find(k);
+  if (it != T.multi.end()) return it->second;
+  MsMulti M;
+  const int n_out = level - k + 1;
+  std::vector<uint64_t> pm;   // p_m = q_{level - m}
+  for (int m = 0; m < k; ++m) pm.push_back(primes[level - m]);
+  // D_u mod x for u <= k
+  auto Dmod = [&](int u, uint64_t x) {
+    uint64_t d = 1;
+    for (int v = 0; v < u; ++v) d = mulmod(d, pm[v] % x, x);
+    return d;
+  };
+  std::vector<double> mult, mat((size_t)k * n_out + 4 * k, 0.0), tab(2 + 2 * (size_t)n_out, 0.0);
+  for (int m = 0; m < k; ++m) mult.push_back((double)invmod(mulmod(t % pm[m], Dmod(m, pm[m]), pm[m]), pm[m]));
+  for (int u = 0; u < k; ++u)
+    for (int o = 0; o < n_out; ++o) mat[(size_t)u * n_out + o] = (double)Dmod(u, primes[o]);
+  for (int m = 1; m < k; ++m) {
+    const uint64_t dinv = invmod(Dmod(m, pm[m]), pm[m]);
+    for (int u = 0; u < m; ++u) mat[(size_t)k * n_out + 4 * m + u] = (double)mulmod(Dmod(u, pm[m]), dinv, pm[m]);
+  }
+  tab[0] = (double)level;
+  for (int o = 0; o < n_out; ++o) {
+    const uint64_t q = primes[o];
+    const uint64_t dinv = invmod(Dmod(k, q), q);
+    tab[2 + 2 * o] = (double)dinv;
+    tab[3 + 2 * o] = (double)mulmod(t % q, dinv, q);
+  }
+  M.mult = upload(T.owned, mult);
+  M.mat = upload(T.owned, mat);
+  M.tab = upload(T.owned, tab);
+  std::vector<int2> ir, orr;
+  for (int m = 0; m < k; ++m) ir.push_back(make_int2(m, level - m));
+  for (int o = 0; o < n_out; ++o) orr.push_back(make_int2(o, o));
+  M.in_rows = rows("mskin:" + std::to_string(level) + ":" + std::to_string(k), ir);
+  M.out_rows = rows("mskout:" + std::to_string(level) + ":" + std::to_string(k), orr);
+  return T.multi.emplace(k, M).first->second;
+}
+
 uint64_t galois_of(const Context& c, int64_t r) {
   int64_t half = (int64_t)c.N / 2;
   int64_t rr = ((r % half) + half) % half;

@@ -139,8 +139,94 @@ std::vector<SCt> b_modswitch(Context& c, const std::vector<const Ct*>& in,
   return out;
 }
 
-// switch each ciphertext down to its target level (one prime at a time, batched per step)
+// switch in[i] down by k[i] primes at once (1 <= k[i] <= 4): bit-identical to k[i] single switches.  Per
+// polynomial count: one inverse row pass over the dropped limbs of every job, fused column passes per
+// (level, k) (mode 3: the single switches' lifts one after the other), one forward row pass with the finish.
+static std::vector<SCt> b_switch_by(Context& c, const std::vector<const Ct*>& in, const std::vector<int>& kk) {
+  std::vector<SCt> out(in.size());
+  const size_t N = c.N;
+  std::map<int, std::vector<size_t>> by_np;
+  for (size_t i = 0; i < in.size(); ++i) {
+    if (kk[i] < 1 || kk[i] > 4 || kk[i] > in[i]->level) fail(COPSE_EINVAL, "internal: switch count");
+    by_np[in[i]->npolys].push_back(i);
+  }
+  for (auto& kv : by_np) {
+    const int np = kv.first;
+    std::vector<size_t> idx = kv.second;
+    // jobs of one (level, k) next to each other
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+      return std::make_pair(-in[a]->level, kk[a]) < std::make_pair(-in[b]->level, kk[b]);
+    });
+    const int J = (int)idx.size();
+    int kmax = 0;
+    size_t wrows = 0;
+    for (size_t j : idx) {
+      kmax = std::max(kmax, kk[j]);
+      wrows += (size_t)np * (in[j]->level - kk[j] + 1);
+    }
+    const int rpj = np * kmax;
+    DBuf top(&c, (size_t)J * rpj * N);
+    DBuf w(&c, wrows * N);
+    std::vector<double*> po;
+    std::vector<const double*> pi, pw, tabs;
+    std::vector<int> glv, flv;
+    std::vector<BridgeDesc> ds;
+    size_t woff = 0;
+    for (int j0 = 0; j0 < J;) {
+      const int l = in[idx[j0]]->level, k = kk[idx[j0]];
+      int j1 = j0;
+      while (j1 < J && in[idx[j1]]->level == l && kk[idx[j1]] == k) ++j1;
+      const MsMulti& M = c.ms_multi(l, k);
+      const int n_out = l - k + 1;
+      auto outs = alloc_batch(c, j1 - j0, l - k, np);
+      BridgeDesc d{M.out_rows, M.in_rows, M.mult, M.mat, n_out, k, 0, 0};
+      d.in = top.get() + (size_t)j0 * rpj * N;
+      d.out = w.get() + woff * N;
+      d.in_bs = (size_t)kmax * N;
+      d.out_bs = (size_t)n_out * N;
+      d.nz = (j1 - j0) * np;
+      ds.push_back(d);
+      for (int j = j0; j < j1; ++j) {
+        const size_t g = idx[j];
+        po.push_back(outs[j - j0]->data());
+        pi.push_back(in[g]->data());
+        pw.push_back(w.get() + woff * N);
+        tabs.push_back(M.tab);
+        glv.push_back(l | (k << 16));
+        flv.push_back(n_out | ((l + 1) << 16));
+        out[g] = outs[j - j0];
+        woff += (size_t)np * n_out;
+      }
+      j0 = j1;
+    }
+    launch_ntt_inv_rows_gather(c, top.get(), pi, rpj, (size_t)kmax, 0, -3, &glv);
+    launch_bridge_set(c, 3, nullptr, nullptr, ds, 0, 0, 0);
+    launch_ntt_fwd_rows_ms_finish(c, po, pi, pw, flv, tabs, np, nullptr, 0);
+  }
+  return out;
+}
+
+// switch each ciphertext down to its target level (several primes per step where the fused passes run)
 static std::vector<SCt> b_down(Context& c, std::vector<SCt> v, const std::vector<int>& target) {
+  if (bridge_supported(c, 4)) {
+    while (true) {
+      std::vector<size_t> todo;
+      std::vector<int> kk;
+      for (size_t i = 0; i < v.size(); ++i)
+        if (v[i]->level > target[i]) {
+          todo.push_back(i);
+          kk.push_back(std::min(4, v[i]->level - target[i]));
+        }
+      if (todo.empty()) return v;
+      std::vector<const Ct*> in;
+      for (size_t i : todo) in.push_back(v[i].get());
+      bool single = true;
+      for (int k : kk) single = single && k == 1;
+      // switches by one prime keep the single-switch path (its own lift kernel)
+      auto r = single ? b_modswitch(c, in) : b_switch_by(c, in, kk);
+      for (size_t k = 0; k < todo.size(); ++k) v[todo[k]] = r[k];
+    }
+  }
   while (true) {
     std::vector<size_t> todo;
     for (size_t i = 0; i < v.size(); ++i)

@@ -178,6 +178,8 @@ struct Context {
   int n_digits(int level) const { return (level + 1 + alpha - 1) / alpha; }
   const int2* rows(const std::string& key, const std::vector<int2>& host);
   KSTables& kstab(int level);
+  // constants of the switch from `level` by k primes at once (1 <= k <= min(4, level))
+  const struct MsMulti& ms_multi(int level, int k);
   ~Context();
 };
 
@@ -209,7 +211,20 @@ struct KSTables {
   double* d_mm_m3 = nullptr;
   double mm_ptop = 0.0;
   bool mm_ok = false;            // the merged step's bounds hold for this chain (q_l < 4 q_i for i < l)
+  std::map<int, MsMulti> multi;  // switches by k > 1 primes from this level
   std::vector<double*> owned;
+};
+
+// Switch from level l by k primes p_m = q_{l-m} (m < k) at once (fused column pass mode 3 and the
+// switch finish): mult[k], mat = [k][n_out] D_m mod q_o then the chain constants at k n_out + 4 m + u,
+// tab in the single switch's layout with D_k^-1 and t D_k^-1 per output limb; row descriptors of the k
+// input rows (m, q_{l-m}) and the n_out = l - k + 1 output rows (o, q_o).
+struct MsMulti {
+  double* mult = nullptr;
+  double* mat = nullptr;
+  double* tab = nullptr;
+  const int2* in_rows = nullptr;
+  const int2* out_rows = nullptr;
 };
 
 // ------------------------------------------------------------------ kernel launchers (kernels.hip)

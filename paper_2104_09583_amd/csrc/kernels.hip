@@ -603,14 +603,25 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
   const int r = blockIdx.y;
   const int j = r / rpj, sub = r % rpj;
   const size_t N = (size_t)1 << logN;
-  // prime_fixed -2: the top limb of job j's polynomial sub, job j at level lv[j]
-  const int top = lv.v[j];
-  const int prime = prime_fixed == -2 ? top : prime_fixed >= 0 ? prime_fixed : sub;
-  const size_t stride = prime_fixed == -2 ? (size_t)(top + 1) * N : src_stride;
-  const size_t off = prime_fixed == -2 ? (size_t)top * N : src_off;
+  // prime_fixed -2: the top limb of job j's polynomial sub, job j at level lv[j];
+  // prime_fixed -3: limb top - m of polynomial sub / src_stride with m = sub % src_stride, where lv[j] =
+  //                 top | k << 16 and only m < k is transformed (job j at level top drops k limbs)
+  const int top = prime_fixed == -3 ? (lv.v[j] & 0xffff) : lv.v[j];
+  int prime, poly;
+  if (prime_fixed == -3) {
+    const int kmax = (int)src_stride, m = sub % kmax;
+    if (m >= (lv.v[j] >> 16)) return;   // uniform per workgroup, before any barrier
+    prime = top - m;
+    poly = sub / kmax;
+  } else {
+    prime = prime_fixed == -2 ? top : prime_fixed >= 0 ? prime_fixed : sub;
+    poly = sub;
+  }
+  const size_t stride = prime_fixed <= -2 ? (size_t)(top + 1) * N : src_stride;
+  const size_t off = prime_fixed <= -2 ? (size_t)prime * N : src_off;
   const DevPrime pr = P[prime];
   const size_t t0 = (size_t)blockIdx.x * 4096;
-  const double* a = src.p[j] + (size_t)sub * stride + off + t0;
+  const double* a = src.p[j] + (size_t)poly * stride + off + t0;
   double x[8];
   row4_inv_tile(a, t0, S1, pr, sh, x);
   double* o = dst + (size_t)r * N + t0;
@@ -645,8 +656,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
   const int i = blockIdx.y, z = blockIdx.z;
   constexpr bool kMd = kMode != 2;   // ModDown layout (2 polys per job, accumulator rows)
   const int j = kMd ? (z >> 1) : z / np, k = kMd ? (z & 1) : z % np;
-  // kMode 2: job j switches from level lv[j]: it writes nl = lv[j] limbs per poly below an input with nl + 1
-  const int nl = kMd ? nl_ : lvs.v[j];
+  // kMode 2: job j writes nl = lv[j] & 0xffff limbs per poly from an input with lv[j] >> 16 limbs per poly
+  // (nl + 1 when zero: a switch by one prime)
+  const int nl = kMd ? nl_ : (lvs.v[j] & 0xffff);
+  const int nin = kMd ? 0 : ((lvs.v[j] >> 16) != 0 ? (lvs.v[j] >> 16) : nl + 1);
   if (i >= nl) return;   // uniform per workgroup, before any barrier
   const DevPrime pr = P[i];
   const size_t N = (size_t)1 << logN;
@@ -659,7 +672,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
   const double m2 = kMd ? tmul[i] : tab[3 + 2 * i];
   const double m3 = kMode == 3 ? amul[i] : 0.0;
   const size_t orow = ((size_t)k * nl + i) * N;
-  const double* yrow = kMd ? acc + ((size_t)z * nE + i) * N : in.p[j] + ((size_t)k * (nl + 1) + i) * N;
+  const double* yrow = kMd ? acc + ((size_t)z * nE + i) * N : in.p[j] + ((size_t)k * nin + i) * N;
   const uint64_t g = kMode == 1 ? gal.g[j] : 1;
   // the epilogue's main operand is loaded during the transform, so its latency overlaps it
   double yv[8];
@@ -810,6 +823,11 @@ void launch_ntt_inv(Context& c, double* base, const int2* rows, int nrows) {
 //            ModDown result's top limb times t^-1 is [y_l (t P)^-1 - s_l]_{q_l}; v is its centered value
 //            (the switch's lift) and out_o = s_o + v mod q_o for o < l.  mat is [alpha][n_out + 1]
 //            (p_r^-1 mod q_o, the last column for q_l), mult[alpha] = (t P)^-1 mod q_l.
+//   kMode 3 (switch by k primes at once, exactly as k single switches): inputs m < k are the limbs of
+//            p_m = q_{l-m}; with D_m = p_0 ... p_{m-1}, mult_m = (t D_m)^-1 mod p_m, the single switches'
+//            lifts are z_m = centered [x_m mult_m - sum_{u<m} z_u D_u D_m^-1]_{p_m} (mat[k n_out + 4 m + u]
+//            holds D_u D_m^-1 mod p_m) and out_o = sum_m z_m D_m mod q_o (mat[m n_out + o] = D_m mod q_o);
+//            the finish then computes (c - t out) D_k^-1.
 // The values handed to the forward stages are any representatives of the residues (|v| <= q/2), so the
 // transform's canonical output is the same as that of the unfused steps.
 // grid: x over column groups of 64, y over chunks of ochunk outputs (small batches: more blocks, the
@@ -837,7 +855,7 @@ __device__ __forceinline__ BridgeOut<S1> bridge_out_load(const BridgeDesc& d, co
 #pragma unroll
   for (int k = 1; k < (1 << S1); ++k) b.w[k] = cload(po.fwd + k);
   // mode 2: the special rows' column of the [alpha][n_out + 1] matrix
-  const int n_conv = kMode == 2 ? d.n_in - 1 : d.n_in;
+  const int n_conv = kMode == 2 ? d.n_in - 1 : d.n_in;   // mode 3: the k lifts
   const int stride = kMode == 2 ? d.n_out + 1 : d.n_out;
 #pragma unroll
   for (int k = 0; k < kBridgeIn; ++k) b.m[k] = (kMode != 1 && k < n_conv) ? cload(d.mat + k * stride + o) : 0.0;
@@ -907,6 +925,27 @@ __global__ __launch_bounds__(256) void ntt_bridge_kernel(BridgeSet set, const De
     }
   }
   lds_barrier();
+  if (kMode == 3) {
+    // the k lifts of the single switches, one after the other per coefficient; wave w takes rows w, w + 4..
+    for (int r = wv; r < R && active; r += 4) {
+      double z[kBridgeIn];
+#pragma unroll
+      for (int m = 0; m < kBridgeIn; ++m) {
+        if (m < n_in) {
+          const int2 irow = cload_row(d.in_rows + m);
+          const double pq = cload(&P[irow.y].q), pqinv = cload(&P[irow.y].qinv);
+          double a = ys[m][r][lane];
+#pragma unroll
+          for (int u = 0; u < kBridgeIn; ++u)
+            if (u < m) a -= mul_lazy(z[u], cload(d.mat + n_out * n_in + 4 * m + u), pq, pqinv);
+          // |a| < 4 p_m: the symmetric reduction is the centered lift
+          z[m] = reduce_sym(a, pq, pqinv);
+          ys[m][r][lane] = z[m];
+        }
+      }
+    }
+    lds_barrier();
+  }
   if (!active) return;
   // mode 2: the switch's centered lift v of the top limb, per coefficient of this thread's column
   double vt[kMode == 2 ? R : 1];
@@ -992,6 +1031,7 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
         fail(COPSE_EINVAL, "internal: fused column pass not available for this ring");
       if (mode == 1 && d.n_in != 1) fail(COPSE_EINVAL, "internal: modulus-switch map takes one row");
       if (mode == 2 && d.n_in < 2) fail(COPSE_EINVAL, "internal: merged switch needs special rows and the top row");
+      if (mode == 3 && d.n_in < 1) fail(COPSE_EINVAL, "internal: switch by no prime");
       if (d.n_out <= 0) fail(COPSE_EINVAL, "internal: conversion without outputs");
       // at least ~512 workgroups (2048 waves) when the batch is small, by splitting the outputs into chunks
       // of at least 4 (one per wave)
@@ -1024,12 +1064,19 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
         case 3: COPSE_BRIDGE(3, 1); break;
         default: COPSE_BRIDGE(4, 1); break;
       }
-    } else {
+    } else if (mode == 2) {
       switch (S1) {
         case 1: COPSE_BRIDGE(1, 2); break;
         case 2: COPSE_BRIDGE(2, 2); break;
         case 3: COPSE_BRIDGE(3, 2); break;
         default: COPSE_BRIDGE(4, 2); break;
+      }
+    } else {
+      switch (S1) {
+        case 1: COPSE_BRIDGE(1, 3); break;
+        case 2: COPSE_BRIDGE(2, 3); break;
+        case 3: COPSE_BRIDGE(3, 3); break;
+        default: COPSE_BRIDGE(4, 3); break;
       }
     }
 #undef COPSE_BRIDGE
@@ -1087,7 +1134,8 @@ void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows) 
 void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const double*>& src, int rpj,
                                 size_t src_stride, size_t src_off, int prime_fixed, const std::vector<int>* levels) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
-  if (prime_fixed == -2 && (!levels || levels->size() != src.size())) fail(COPSE_EINVAL, "internal: levels");
+  if (prime_fixed <= -2 && (!levels || levels->size() != src.size())) fail(COPSE_EINVAL, "internal: levels");
+  if (prime_fixed == -3 && (src_stride == 0 || rpj % (int)src_stride != 0)) fail(COPSE_EINVAL, "internal: limbs");
   const int per = std::max(1, std::min(kPack, kMaxGridY / std::max(1, rpj)));
   for (size_t first = 0; first < src.size(); first += per) {
     const int cnt = (int)std::min<size_t>(per, src.size() - first);
@@ -1185,8 +1233,9 @@ void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, 
       pt.p[k] = tabs[first + k];
       pg.g[k] = 1;
       lv.v[k] = levels[first + k];
-      lmax = std::max(lmax, lv.v[k]);
-      bytes += (3.0 * np + (add ? add_np : 0)) * lv.v[k] * (double)c.N * 8.0;
+      const int nl = lv.v[k] & 0xffff;
+      lmax = std::max(lmax, nl);
+      bytes += (3.0 * np + (add ? add_np : 0)) * nl * (double)c.N * 8.0;
     }
     hipEvent_t ev;
     prof_begin(c, 8, &ev);
