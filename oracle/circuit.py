@@ -226,7 +226,14 @@ class Evaluator:
                 lt[k] = sc.sub(ts, u)
         seq = [eq[p - 1 - i] for i in range(p - 1)]
         pre = S.kogge_stone_prefix(seq, self.mul)
-        terms = [lt[p - 1]] + [self.mul(lt[k], pre[p - 2 - k]) for k in range(p - 1)]
+        # The p - 1 products lt_k * pre_{p-2-k} form one round; every operand is first switched to the
+        # lowest level among them (the deepest prefix), so the round runs at one level.  The paper fixes
+        # which products are formed, not their levels; this takes no more depth than pairwise alignment.
+        terms = [lt[p - 1]]
+        if p > 1:
+            lv = min(min(lt[k].level for k in range(p - 1)), min(x.level for x in pre))
+            terms += [self.mul(sc.modswitch_to(lt[k], lv), sc.modswitch_to(pre[p - 2 - k], lv))
+                      for k in range(p - 1)]
         return self.sum_all(terms)
 
     def matmul(self, v: Ciphertext, diags: list, n1: int) -> Ciphertext:
