@@ -720,9 +720,21 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
       for (int b = 0; b < G; ++b) nxt[i][b] = r[z++];
     cur = std::move(nxt);
   }
+  // the last products form one round at the lowest level among their operands (one key-switch batch)
   std::vector<std::pair<SCt, SCt>> fin;
-  for (int kb = 0; kb < p - 1; ++kb)
-    for (int b = 0; b < G; ++b) fin.push_back({lt[kb][b], cur[p - 2 - kb][b]});
+  if (p > 1) {
+    int lv = lt[0][0]->level;
+    for (int kb = 0; kb < p - 1; ++kb)
+      for (int b = 0; b < G; ++b) lv = std::min({lv, lt[kb][b]->level, cur[kb][b]->level});
+    std::vector<SCt> ops;
+    for (int kb = 0; kb < p - 1; ++kb)
+      for (int b = 0; b < G; ++b) {
+        ops.push_back(lt[kb][b]);
+        ops.push_back(cur[p - 2 - kb][b]);
+      }
+    ops = b_down(c, ops, std::vector<int>(ops.size(), lv));
+    for (size_t i = 0; i + 1 < ops.size(); i += 2) fin.push_back({ops[i], ops[i + 1]});
+  }
   auto prods = b_mul(c, k, fin);
   std::vector<std::vector<SCt>> terms(G);
   for (int b = 0; b < G; ++b) {

@@ -65,8 +65,12 @@ struct Plain1 {
       for (size_t i = s; i < cur.size(); ++i) nxt[i] = mul(cur[i], cur[i - s]);
       cur = std::move(nxt);
     }
+    // the last products form one round at the lowest level among their operands
     std::vector<SCt> terms{lt[p - 1]};
-    for (int kb = 0; kb < p - 1; ++kb) terms.push_back(mul(lt[kb], cur[p - 2 - kb]));
+    int lv = lt[0]->level;
+    for (int kb = 0; kb < p - 1; ++kb) lv = std::min({lv, lt[kb]->level, cur[kb]->level});
+    auto down = [&](const SCt& x) { return x->level > lv ? share(op_modswitch_to(c, *x, lv)) : x; };
+    for (int kb = 0; kb < p - 1; ++kb) terms.push_back(mul(down(lt[kb]), down(cur[p - 2 - kb])));
     return sum_all(terms);
   }
 
