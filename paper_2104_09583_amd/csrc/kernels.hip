@@ -1872,9 +1872,12 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
 // step the GM diagonal loads are issued together (a zero diagonal loads the baby value again, which is in
 // cache, and its product is skipped by a uniform branch).
 // Sums are lazy (|term| < 0.91 q) and folded back with reduce_sym every kRed baby steps.
+// kSplit (one batch element): the four waves of a workgroup take every fourth baby step of the same
+// coefficients and add their partial sums through LDS at the end, so each wave's chain of dependent
+// loads is a quarter as long.
 // grid: x = (N / 64) x ceil(G / 4) (XCD-aware), y = limbs, z = giant-group chunks of GM.
 constexpr int kMmLanes = 64, kMmWaves = 4;
-template <int GM, bool kEnc>
+template <int GM, bool kEnc, bool kSplit>
 __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out, const double* __restrict__ baby,
                                                        const double* const* __restrict__ tab, int n_u, int ng, int G,
                                                        int nl, size_t baby_slot, size_t baby_b, const DevPrime* P,
@@ -1882,15 +1885,17 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
   constexpr int kNp = kEnc ? 3 : 2;
   constexpr int kRed = kEnc ? 3 : 7;
   const size_t N = (size_t)1 << logN;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kMmLanes));
   // consecutive workgroups go to different XCDs: give each XCD a contiguous range of logical blocks so
   // that the batch chunks of one coefficient tile run on one XCD together
   unsigned bx = blockIdx.x;
   const unsigned nbx = gridDim.x;
   if ((nbx & 7u) == 0) bx = (bx & 7u) * (nbx >> 3) + (bx >> 3);
-  const unsigned bchunks = (unsigned)(G + kMmWaves - 1) / kMmWaves;
+  const unsigned bchunks = kSplit ? 1u : (unsigned)(G + kMmWaves - 1) / kMmWaves;
   // the batch element is uniform per wave: keep it (and the baby pointers) in scalar registers
-  const int b = (int)(bx % bchunks) * kMmWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kMmLanes));
+  const int b = kSplit ? 0 : (int)(bx % bchunks) * kMmWaves + wv;
   const size_t i = (size_t)(bx / bchunks) * kMmLanes + (threadIdx.x % kMmLanes);
+  // N is a multiple of 64, so a workgroup is either wholly in range or wholly out (uniform exit)
   if (i >= N || b >= G) return;
   const int l = blockIdx.y;
   const int s0 = blockIdx.z * GM;
@@ -1903,7 +1908,7 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
 #pragma unroll
     for (int p = 0; p < kNp; ++p) acc[s][p] = 0.0;
   int cnt = 0;
-  for (int u = 0; u < n_u; ++u) {
+  for (int u = kSplit ? wv : 0; u < n_u; u += kSplit ? kMmWaves : 1) {
     // tables carry kMmTabPad trailing entries, so all GM pointers of a row can be fetched together
     const double* const* row = tab + (size_t)u * ng + s0;
     const double* ptr[GM];
@@ -1945,6 +1950,33 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
         for (int p = 0; p < kNp; ++p) acc[s][p] = reduce_sym(acc[s][p], pr.q, pr.qinv);
     }
   }
+  if (kSplit) {
+    // four groups at a time: every wave leaves its folded partial sums in LDS, wave w completes group w
+    __shared__ double red[kMmWaves][kMmWaves][kNp][kMmLanes];
+    const int lane = threadIdx.x % kMmLanes;
+#pragma unroll
+    for (int sb = 0; sb < GM; sb += kMmWaves) {
+#pragma unroll
+      for (int q = 0; q < kMmWaves; ++q)
+        if (sb + q < GM)
+#pragma unroll
+          for (int p = 0; p < kNp; ++p) red[wv][q][p][lane] = reduce_sym(acc[sb + q][p], pr.q, pr.qinv);
+      lds_barrier();
+      const int s = sb + wv;
+      if (s < gm) {
+        double* op = out + ((size_t)(s0 + s) * G + b) * kNp * ps;
+#pragma unroll
+        for (int p = 0; p < kNp; ++p) {
+          double v = 0.0;
+#pragma unroll
+          for (int w2 = 0; w2 < kMmWaves; ++w2) v += red[w2][wv][p][lane];
+          op[(size_t)p * ps + o] = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
+        }
+      }
+      lds_barrier();
+    }
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < GM; ++s) {
     if (s < gm) {
@@ -1960,8 +1992,12 @@ static void mm_inner_launch(Context& c, double* out, const double* baby, const d
                             int G, int nl, size_t baby_slot, size_t baby_b) {
   const unsigned tiles = (unsigned)((c.N + kMmLanes - 1) / kMmLanes);
   const unsigned bchunks = (unsigned)((G + kMmWaves - 1) / kMmWaves);
-  hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc>), dim3(tiles * bchunks, nl, (ng + GM - 1) / GM), dim3(256), 0,
-                     c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+  if (G == 1)
+    hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc, true>), dim3(tiles, nl, (ng + GM - 1) / GM), dim3(256), 0,
+                       c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+  else
+    hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc, false>), dim3(tiles * bchunks, nl, (ng + GM - 1) / GM), dim3(256),
+                       0, c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
 }
 
 void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng, int G,
