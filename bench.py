@@ -380,6 +380,9 @@ def main():
     ch = dict(w.chain)
     if args.server_rep:
         ch["n_data_primes"] += 1   # the replication product takes one level
+    # baby-step counts: the command line, else the workload's measured choice, else the compiler's rule
+    args.n1_r = args.n1_r or w.n1[0]
+    args.n1_l = args.n1_l or w.n1[1]
     log("workload", w.name, "chain", ch)
     t0 = time.perf_counter()
     ctx = C.Context(**ch)

@@ -50,6 +50,9 @@ class Workload:
     notes: str = ""
     chain: dict = field(default_factory=dict)
     fold: bool = False
+    # baby steps of the reshuffle and level products (0: the compiler's square-root rule); a measured
+    # choice where it beats the rule on the GPU
+    n1: tuple = (0, 0)
 
 
 def _gen_tree(rng: np.random.Generator, shape: ForestShape, depth: int, out: list) -> None:
@@ -114,7 +117,7 @@ WORKLOADS = {
         "16 random unbalanced trees, max depth 5, one query, N=32768", CHAIN_32K_P8),
     "c3_batched_32x_d6": Workload(
         "c3_batched_32x_d6", ForestShape(32, 6, 0.7, 16, 8, 8), 1024, 15, False, 3,
-        "1024 queries against 32 trees of max depth 6, N=32768", CHAIN_32K_P8),
+        "1024 queries against 32 trees of max depth 6, N=32768", CHAIN_32K_P8, n1=(0, 16)),
     "c4_encmodel_64x_d8": Workload(
         "c4_encmodel_64x_d8", ForestShape(64, 8, 0.7, 32, 16, 10), 256, 15, True, 4,
         "encrypted model and queries, 64 trees max depth 8, 16-bit, N=32768", CHAIN_32K_P16),

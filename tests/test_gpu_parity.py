@@ -506,7 +506,8 @@ def test_workload_full_size_labels(C, name, groups, batch):
     text, queries, seed = synth.workload_inputs(w)
     say("full-size labels", name, "groups", groups, "batch", batch)
     ctx = C.Context(**w.chain)
-    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold)
+    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
+                                  n1_R=w.n1[0], n1_L=w.n1[1])
     keys = ctx.keygen(seed, C.compiled_rotations(meta))
     evk = ctx.export_eval(keys)
     if w.encrypted_model:
