@@ -83,7 +83,8 @@ class Plan:
 
 
 def seccomp_depth(p: int) -> int:
-    return 1 + math.ceil(math.log2(p - 1)) + 1 if p > 2 else p
+    """Levels the comparison takes: the plaintext layer's switch, then ceil(log2 p) product rounds."""
+    return 1 + math.ceil(math.log2(p))
 
 
 def make_plan(c: Compiled, N: int, L: int, fold: bool = False, encrypted_model: bool = False,
@@ -224,17 +225,18 @@ class Evaluator:
                 if k >= 1:
                     eq[k] = sc.add_plain(sc.sub(sc.sub(sc.mul_int(u, 2), xs), ts), one)
                 lt[k] = sc.sub(ts, u)
-        seq = [eq[p - 1 - i] for i in range(p - 1)]
-        pre = S.kogge_stone_prefix(seq, self.mul)
-        # The p - 1 products lt_k * pre_{p-2-k} form one round; every operand is first switched to the
-        # lowest level among them (the deepest prefix), so the round runs at one level.  The paper fixes
-        # which products are formed, not their levels; this takes no more depth than pairwise alignment.
-        terms = [lt[p - 1]]
-        if p > 1:
-            lv = min(min(lt[k].level for k in range(p - 1)), min(x.level for x in pre))
-            terms += [self.mul(sc.modswitch_to(lt[k], lv), sc.modswitch_to(pre[p - 2 - k], lv))
-                      for k in range(p - 1)]
-        return self.sum_all(terms)
+        # the terms lt_k * prod_{j > k} eq_j in ceil(log2 p) rounds of products (slotsim's plan); each
+        # round first switches all its operands to the lowest level among them, so it runs at one level
+        val = {}
+        for m in range(p - 1):
+            val[frozenset([("e", m)])] = eq[p - 1 - m]
+            val[frozenset([("l", m)])] = lt[p - 2 - m]
+        rounds, terms = S.seccomp_product_plan(p - 1)
+        for rnd in rounds:
+            lv = min(min(val[a].level, val[b].level) for _, a, b in rnd)
+            for k, a, b in rnd:
+                val[k] = self.mul(sc.modswitch_to(val[a], lv), sc.modswitch_to(val[b], lv))
+        return self.sum_all([lt[p - 1]] + [val[terms[i]] for i in range(p - 1)])
 
     def matmul(self, v: Ciphertext, diags: list, n1: int) -> Ciphertext:
         sc = self.sc

@@ -112,15 +112,77 @@ def kogge_stone_prefix(seq: List, mul) -> List:
     return cur
 
 
+def seccomp_product_plan(n: int):
+    """Products that form t_i = l_i * e_0 * e_1 * ... * e_i for every i < n in ceil(log2(n + 1))
+    rounds, with the comparison's e_m = eq_{p-1-m} and l_i = lt_{p-2-i} (n = p - 1), so that
+    t_i = lt_k * prod_{j > k} eq_j for k = p - 2 - i.
+
+    Every value is named by the set of leaves it multiplies: ('e', m) and ('l', i).  The e's are
+    combined in aligned blocks [j 2^s, (j + 1) 2^s), block s from two blocks s - 1 (depth s); the
+    factors of t_i are the aligned blocks that tile [0, i], left to right (sizes falling), then
+    l_i; they are multiplied from the right end (the last two into one) until one is left.  A
+    product's depth is one more than its deeper operand; since the blocks' sizes are distinct
+    powers of two, t_i ends at depth ceil(log2(i + 2)).  Products with the same leaf set are made
+    once.
+
+    Returns (rounds, terms): rounds[d] lists (key, a, b) of the products of depth d + 1 in the order
+    they were first needed; terms[i] is the key of t_i."""
+    depth = {}
+    order = []
+
+    def leaf(kind, idx):
+        k = frozenset([(kind, idx)])
+        depth[k] = 0
+        return k
+
+    def prod(a, b):
+        k = a | b
+        if k not in depth:
+            depth[k] = max(depth[a], depth[b]) + 1
+            order.append((k, a, b))
+        return k
+
+    def block(s, j):
+        if s == 0:
+            return leaf("e", j)
+        return prod(block(s - 1, 2 * j), block(s - 1, 2 * j + 1))
+
+    terms = []
+    for i in range(n):
+        factors = []
+        start = 0
+        while start <= i:
+            size = 1
+            while start % (2 * size) == 0 and start + 2 * size <= i + 1:
+                size *= 2
+            factors.append(block(size.bit_length() - 1, start // size))
+            start += size
+        factors.append(leaf("l", i))
+        while len(factors) > 1:
+            b = factors.pop()
+            a = factors.pop()
+            factors.append(prod(a, b))
+        terms.append(factors[0])
+    n_rounds = max((depth[k] for k in terms), default=0)
+    rounds = [[(k, a, b) for k, a, b in order if depth[k] == d + 1] for d in range(n_rounds)]
+    return rounds, terms
+
+
 def seccomp_slots(xp: List[np.ndarray], tp: List[np.ndarray], t: int) -> np.ndarray:
     p = len(xp)
     eq = [(1 - xp[k] - tp[k] + 2 * xp[k] * tp[k]) % t for k in range(p)]
     lt = [(tp[k] - xp[k] * tp[k]) % t for k in range(p)]
-    seq = [eq[p - 1 - i] for i in range(p - 1)]           # eq_{p-1}, ..., eq_1
-    pre = kogge_stone_prefix(seq, lambda a, b: (a * b) % t)
+    val = {}
+    for m in range(p - 1):
+        val[frozenset([("e", m)])] = eq[p - 1 - m]
+        val[frozenset([("l", m)])] = lt[p - 2 - m]
+    rounds, terms = seccomp_product_plan(p - 1)
+    for rnd in rounds:
+        for k, a, b in rnd:
+            val[k] = (val[a] * val[b]) % t
     dec = lt[p - 1].copy()
-    for k in range(p - 1):
-        dec = (dec + lt[k] * pre[p - 2 - k]) % t
+    for i in range(p - 1):
+        dec = (dec + val[terms[i]]) % t
     return dec
 
 

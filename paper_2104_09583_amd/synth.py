@@ -97,15 +97,17 @@ def crypto_seed(label: str) -> bytes:
 # Prime-chain parameters (see the library's copse_params): number of data
 # primes, exclusive bounds for q_0, the other data primes and the special
 # primes, and alpha = special primes = primes per key-switching digit.
-#   N=16384: 9 data primes, total log2(PQ) ~ 433 <= 438 (HE-standard bound
+#   N=16384: 8 data primes, total log2(PQ) ~ 394 <= 438 (HE-standard bound
 #            for 128-bit security); the reshuffle is folded into the level
 #            products to fit the circuit in that chain.
-#   N=32768: 11 (p = 8) or 12 (p = 16) data primes, log2(PQ) ~ 660-700 <= 881.
-CHAIN_16K = dict(log_n=14, n_data_primes=9, q0_max=1 << 42, data_max=388736063996,   # 2^38.5
+#   N=32768: 10 (p = 8) or 11 (p = 16) data primes, log2(PQ) ~ 617-659 <= 881.
+# Each chain has exactly the levels the circuit takes: the comparison (1 + ceil(log2 p)), the
+# reshuffle (unless folded), the level products and the product tree over d levels.
+CHAIN_16K = dict(log_n=14, n_data_primes=8, q0_max=1 << 42, data_max=388736063996,   # 2^38.5
                  alpha=2, special_max=1 << 44)
-CHAIN_32K_P8 = dict(log_n=15, n_data_primes=11, q0_max=1 << 48, data_max=1 << 42, alpha=4,
+CHAIN_32K_P8 = dict(log_n=15, n_data_primes=10, q0_max=1 << 48, data_max=1 << 42, alpha=4,
                     special_max=1 << 48)
-CHAIN_32K_P16 = dict(log_n=15, n_data_primes=12, q0_max=1 << 48, data_max=1 << 42, alpha=4,
+CHAIN_32K_P16 = dict(log_n=15, n_data_primes=11, q0_max=1 << 48, data_max=1 << 42, alpha=4,
                      special_max=1 << 48)
 
 WORKLOADS = {

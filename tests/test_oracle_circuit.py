@@ -64,15 +64,18 @@ def test_determinism_of_ciphertexts():
 
 
 def test_operation_counts_closed_form():
-    """SecComp uses (p-1)-prefix Kogge-Stone products plus p-1 final products;
-    MultAll uses d-1 products; with n1 = 1 (no baby steps) the rotation count
-    is the paper's q + d b minus the d + 1 rotations by zero (Table 2)."""
+    """SecComp's products: every aligned block of two or more of the n = p - 1 equality bits
+    (sum_s floor(n / 2^s)) plus popcount(i) merges for term i = 1..n (21 -> 16 for p = 8);
+    MultAll uses d-1 products; with n1 = 1 (no baby steps) the rotation count is the paper's
+    q + d b minus the d + 1 rotations by zero (Table 2)."""
     sc, keys, pl, queries, X, model, trees, c = _setup(8, False, False)
     p = c.precision
-    ks = sum(max(0, (p - 1) - s) for s in [1 << i for i in range(math.ceil(math.log2(p - 1)))])
+    n = p - 1
+    blocks = sum(n >> s for s in range(1, n.bit_length() + 1))
+    merges = sum(bin(i).count("1") for i in range(1, n + 1))
     ev = CI.Evaluator(sc, keys, pl)
     ev.seccomp(X, model)
-    assert ev.counts["mul"] == ks + (p - 1)
+    assert ev.counts["mul"] == blocks + merges
     ev2 = CI.Evaluator(sc, keys, pl)
     ev2.counts["mul"] = 0
     S.multall(list(range(c.d)), lambda a, b: ev2.counts.__setitem__("mul", ev2.counts["mul"] + 1) or 0)

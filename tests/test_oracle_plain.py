@@ -3,6 +3,8 @@ the slot simulator of Algorithm 1 (CPU only)."""
 import itertools
 import os
 
+import math
+
 import numpy as np
 import pytest
 
@@ -156,6 +158,33 @@ def test_seccomp_p16_edges():
     xs, ts = xs.reshape(1, -1), ts.reshape(1, -1)
     dec = S.seccomp_slots([(xs >> k) & 1 for k in range(16)], [(ts >> k) & 1 for k in range(16)], 65537)
     assert (dec == (xs < ts)).all()
+
+
+@pytest.mark.parametrize("n", list(range(0, 34)))
+def test_seccomp_product_plan(n):
+    """Each term multiplies exactly e_0..e_i and l_i, at depth ceil(log2(i + 2)); every product's
+    operands exist before its round; the plan has ceil(log2(n + 1)) rounds."""
+    rounds, terms = S.seccomp_product_plan(n)
+    assert len(rounds) == (0 if n == 0 else int(np.ceil(np.log2(n + 1))))
+    have = {frozenset([("e", m)]): 0 for m in range(n)}
+    have.update({frozenset([("l", i)]): 0 for i in range(n)})
+    for d, rnd in enumerate(rounds):
+        for k, a, b in rnd:
+            assert a in have and b in have and max(have[a], have[b]) == d and not (a & b) and k == a | b
+            have[k] = d + 1
+    for i, k in enumerate(terms):
+        assert k == frozenset([("e", m) for m in range(i + 1)] + [("l", i)])
+        assert have[k] == int(np.ceil(np.log2(i + 2)))
+    # products with values: the plan's t_i against the running product
+    rng = np.random.default_rng(n)
+    ev, lv = rng.integers(1, 97, n), rng.integers(1, 97, n)
+    val = {frozenset([("e", m)]): int(ev[m]) for m in range(n)}
+    val.update({frozenset([("l", i)]): int(lv[i]) for i in range(n)})
+    for rnd in rounds:
+        for k, a, b in rnd:
+            val[k] = val[a] * val[b]
+    for i, k in enumerate(terms):
+        assert val[k] == math.prod(int(x) for x in ev[:i + 1]) * int(lv[i])
 
 
 def test_kogge_stone_prefix_matches_sequential():
