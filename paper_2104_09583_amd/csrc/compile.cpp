@@ -7,6 +7,9 @@
 #include <cmath>
 #include <sstream>
 
+#include <functional>
+#include <map>
+
 #include "compiled.hpp"
 
 namespace copse {
@@ -188,7 +191,7 @@ std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t 
   M.n1_R = n1R ? n1R : baby_steps(q);
   M.n1_L = n1L ? n1L : baby_steps(fold ? q : b);
   // depth: comparison, reshuffle (unless folded), level product, product tree
-  uint32_t seccomp = prec > 2 ? 2 + (uint32_t)std::ceil(std::log2((double)(prec - 1))) : prec;
+  const uint32_t seccomp = (uint32_t)seccomp_depth(prec);
   uint32_t tree = 0;
   while ((1u << tree) < d) ++tree;
   M.depth = seccomp + (fold ? 1 : 2) + tree;
@@ -339,6 +342,79 @@ void diagonal_slots(const copse_public_meta& M, size_t N, const std::vector<std:
   }
   *nonzero = nz;
   replicate_blocks(M, N, vec, slots, t);
+}
+
+// Every value is named by the set of leaves it multiplies (bit m: e_m, bit 32 + i: l_i), so a product
+// is made once.  The e's are combined in aligned blocks [j 2^s, (j + 1) 2^s) (block s from two blocks
+// s - 1, depth s); t_i multiplies the aligned blocks that tile [0, i] (left to right, sizes falling)
+// and l_i, from the right end (the last two into one) until one value is left.  As the block sizes
+// are distinct powers of two, t_i ends at depth ceil(log2(i + 2)).
+SeccompPlan seccomp_plan(int n) {
+  if (n < 0 || n > 31) fail(COPSE_EINVAL, "comparison of more than 32 bits");
+  SeccompPlan P;
+  P.n = n;
+  std::vector<uint64_t> mask;
+  std::vector<int> depth;
+  std::map<uint64_t, int> id_of;
+  for (int m = 0; m < n; ++m) {
+    mask.push_back(1ULL << m);
+    depth.push_back(0);
+  }
+  for (int i = 0; i < n; ++i) {
+    mask.push_back(1ULL << (32 + i));
+    depth.push_back(0);
+  }
+  std::vector<SeccompPlan::Prod> order;
+  auto prod = [&](int a, int b) {
+    const uint64_t k = mask[a] | mask[b];
+    auto it = id_of.find(k);
+    if (it != id_of.end()) return it->second;
+    const int id = (int)mask.size();
+    mask.push_back(k);
+    depth.push_back(std::max(depth[a], depth[b]) + 1);
+    id_of[k] = id;
+    order.push_back({id, a, b});
+    return id;
+  };
+  std::function<int(int, int)> block = [&](int s, int j) -> int {
+    if (s == 0) return j;
+    const int a = block(s - 1, 2 * j);
+    const int b = block(s - 1, 2 * j + 1);
+    return prod(a, b);
+  };
+  for (int i = 0; i < n; ++i) {
+    std::vector<int> f;
+    for (int start = 0; start <= i;) {
+      int size = 1, s = 0;
+      while (start % (2 * size) == 0 && start + 2 * size <= i + 1) {
+        size *= 2;
+        ++s;
+      }
+      f.push_back(block(s, start / size));
+      start += size;
+    }
+    f.push_back(n + i);
+    while (f.size() > 1) {
+      const int b = f.back();
+      f.pop_back();
+      const int a = f.back();
+      f.pop_back();
+      f.push_back(prod(a, b));
+    }
+    P.terms.push_back(f[0]);
+  }
+  int rounds = 0;
+  for (int t : P.terms) rounds = std::max(rounds, depth[t]);
+  P.rounds.resize(rounds);
+  for (auto& pr : order) P.rounds[depth[pr.out] - 1].push_back(pr);
+  P.n_values = (int)mask.size();
+  return P;
+}
+
+int seccomp_depth(uint32_t p) {
+  int r = 0;
+  while ((1u << r) < p) ++r;
+  return 1 + r;
 }
 
 }  // namespace copse

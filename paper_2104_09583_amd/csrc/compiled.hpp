@@ -43,6 +43,20 @@ void server_replicate(Compiled& C, uint32_t n1F);
 // block width and queries per ciphertext from B_in (and the replication input span)
 void set_block(Compiled& C);
 std::vector<int32_t> needed_rotations(const copse_public_meta& M);
+// The comparison's products: with e_m = eq_{p-1-m} and l_i = lt_{p-2-i} (n = p - 1), the terms
+// t_i = l_i e_0 ... e_i = lt_k prod_{j > k} eq_j (k = p - 2 - i) in ceil(log2(n + 1)) rounds.  Value
+// ids: e_m = m, l_i = n + i, products from 2 n on; rounds[d] holds the products of depth d + 1.
+struct SeccompPlan {
+  struct Prod {
+    int out, a, b;
+  };
+  std::vector<std::vector<Prod>> rounds;
+  std::vector<int> terms;   // id of t_i
+  int n = 0, n_values = 0;
+};
+SeccompPlan seccomp_plan(int n);
+// levels the comparison takes: the plaintext layer's switch and the product rounds
+int seccomp_depth(uint32_t p);
 void replicate_blocks(const copse_public_meta& M, size_t N, const std::vector<int64_t>& vec,
                       std::vector<uint64_t>& slots, uint64_t t);
 void query_plane_slots(const copse_public_meta& M, size_t N, const uint32_t* feats, size_t nq, uint32_t plane,

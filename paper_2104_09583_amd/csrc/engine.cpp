@@ -705,41 +705,38 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
       }
     launch_seccomp_combine(c, pe, pl, pu, px, pt, nl);
   }
-  // prefix products of (eq_{p-1}, ..., eq_1), Kogge-Stone
-  std::vector<std::vector<SCt>> cur(p - 1, std::vector<SCt>(G));
-  for (int i = 0; i < p - 1; ++i)
-    for (int b = 0; b < G; ++b) cur[i][b] = eq[p - 1 - i][b];
-  for (int s = 1; s < p - 1; s *= 2) {
-    std::vector<std::pair<SCt, SCt>> pairs;
-    for (int i = s; i < p - 1; ++i)
-      for (int b = 0; b < G; ++b) pairs.push_back({cur[i][b], cur[i - s][b]});
-    auto r = b_mul(c, k, pairs);
-    auto nxt = cur;
-    size_t z = 0;
-    for (int i = s; i < p - 1; ++i)
-      for (int b = 0; b < G; ++b) nxt[i][b] = r[z++];
-    cur = std::move(nxt);
-  }
-  // the last products form one round at the lowest level among their operands (one key-switch batch)
-  std::vector<std::pair<SCt, SCt>> fin;
-  if (p > 1) {
-    int lv = lt[0][0]->level;
-    for (int kb = 0; kb < p - 1; ++kb)
-      for (int b = 0; b < G; ++b) lv = std::min({lv, lt[kb][b]->level, cur[kb][b]->level});
+  // the terms lt_k prod_{j > k} eq_j in ceil(log2 p) rounds of products; each round first switches all
+  // its operands to the lowest level among them (one key-switch batch per round)
+  const int n = p - 1;
+  const SeccompPlan plan = seccomp_plan(n);
+  std::vector<std::vector<SCt>> val(plan.n_values, std::vector<SCt>(G));
+  for (int m = 0; m < n; ++m)
+    for (int b = 0; b < G; ++b) {
+      val[m][b] = eq[p - 1 - m][b];
+      val[n + m][b] = lt[p - 2 - m][b];
+    }
+  for (const auto& rnd : plan.rounds) {
+    int lv = c.L;
+    for (const auto& pr : rnd)
+      for (int b = 0; b < G; ++b) lv = std::min({lv, val[pr.a][b]->level, val[pr.b][b]->level});
     std::vector<SCt> ops;
-    for (int kb = 0; kb < p - 1; ++kb)
+    for (const auto& pr : rnd)
       for (int b = 0; b < G; ++b) {
-        ops.push_back(lt[kb][b]);
-        ops.push_back(cur[p - 2 - kb][b]);
+        ops.push_back(val[pr.a][b]);
+        ops.push_back(val[pr.b][b]);
       }
     ops = b_down(c, ops, std::vector<int>(ops.size(), lv));
-    for (size_t i = 0; i + 1 < ops.size(); i += 2) fin.push_back({ops[i], ops[i + 1]});
+    std::vector<std::pair<SCt, SCt>> pairs;
+    for (size_t i = 0; i + 1 < ops.size(); i += 2) pairs.push_back({ops[i], ops[i + 1]});
+    auto r = b_mul(c, k, pairs);
+    size_t z = 0;
+    for (const auto& pr : rnd)
+      for (int b = 0; b < G; ++b) val[pr.out][b] = r[z++];
   }
-  auto prods = b_mul(c, k, fin);
   std::vector<std::vector<SCt>> terms(G);
   for (int b = 0; b < G; ++b) {
     terms[b].push_back(lt[p - 1][b]);
-    for (int kb = 0; kb < p - 1; ++kb) terms[b].push_back(prods[kb * G + b]);
+    for (int i = 0; i < n; ++i) terms[b].push_back(val[plan.terms[i]][b]);
   }
   std::vector<SCt> dec = b_sum_all(c, terms);
   for (auto& x : dec)

@@ -28,13 +28,6 @@
 
 namespace copse {
 
-static int seccomp_depth(uint32_t p) {
-  if (p <= 2) return (int)p;
-  int r = 0;
-  while ((1u << r) < p - 1) ++r;
-  return 2 + r;
-}
-
 static uint64_t obj_id(uint64_t kind, uint64_t a, uint64_t b) { return (kind << 56) | (a << 32) | b; }
 
 std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k, bool encrypt_model,

@@ -58,19 +58,23 @@ struct Plain1 {
         lt[kb] = share(op_sub(c, *ts, *u));
       }
     }
-    std::vector<SCt> cur;
-    for (int i = 0; i < p - 1; ++i) cur.push_back(eq[p - 1 - i]);
-    for (size_t s = 1; s < cur.size(); s *= 2) {
-      std::vector<SCt> nxt = cur;
-      for (size_t i = s; i < cur.size(); ++i) nxt[i] = mul(cur[i], cur[i - s]);
-      cur = std::move(nxt);
+    // the terms lt_k prod_{j > k} eq_j in ceil(log2 p) rounds; each round at the lowest level of its
+    // operands
+    const int n = p - 1;
+    const SeccompPlan plan = seccomp_plan(n);
+    std::vector<SCt> val(plan.n_values);
+    for (int m = 0; m < n; ++m) {
+      val[m] = eq[p - 1 - m];
+      val[n + m] = lt[p - 2 - m];
     }
-    // the last products form one round at the lowest level among their operands
+    for (const auto& rnd : plan.rounds) {
+      int lv = c.L;
+      for (const auto& pr : rnd) lv = std::min({lv, val[pr.a]->level, val[pr.b]->level});
+      auto down = [&](const SCt& x) { return x->level > lv ? share(op_modswitch_to(c, *x, lv)) : x; };
+      for (const auto& pr : rnd) val[pr.out] = mul(down(val[pr.a]), down(val[pr.b]));
+    }
     std::vector<SCt> terms{lt[p - 1]};
-    int lv = lt[0]->level;
-    for (int kb = 0; kb < p - 1; ++kb) lv = std::min({lv, lt[kb]->level, cur[kb]->level});
-    auto down = [&](const SCt& x) { return x->level > lv ? share(op_modswitch_to(c, *x, lv)) : x; };
-    for (int kb = 0; kb < p - 1; ++kb) terms.push_back(mul(down(lt[kb]), down(cur[p - 2 - kb])));
+    for (int i = 0; i < n; ++i) terms.push_back(val[plan.terms[i]]);
     return sum_all(terms);
   }
 
