@@ -31,7 +31,7 @@ import math
 import os
 import subprocess
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -515,3 +515,31 @@ class BGV:
 
     def rotate(self, ct: Ciphertext, r: int, keys: Keys) -> Ciphertext:
         return self.rotate_hoisted(ct, [r], keys)[r]
+
+    def rotate_sum(self, items: Sequence[Tuple[Ciphertext, int]], keys: Keys) -> Ciphertext:
+        """sum_g rot(ct_g, r_g) with one ModDown: the key-switching inner products of the rotated
+        terms are added in the extended basis P Q_l and brought down once; the sigma(c0) parts and the
+        unrotated terms are added in Q_l.  A ModDown of a sum and the sum of ModDowns differ only in
+        rounding, which is why both sides fix this form."""
+        level = items[0][0].level
+        assert all(ct.level == level and len(ct.polys) == 2 for ct, _ in items)
+        idx = self.data_idx(level)
+        ext = self.ext_idx(level)
+        c0 = np.zeros((len(idx), self.N), dtype=np.uint64)
+        c1 = np.zeros_like(c0)
+        y0 = y1 = None
+        for ct, r in items:
+            if r % (self.N // 2) == 0:
+                c0 = self.padd(c0, ct.polys[0], idx)
+                c1 = self.padd(c1, ct.polys[1], idx)
+                continue
+            g = self.galois(r)
+            digits = [self.pauto(d, g, ext) for d in self.modup(ct.polys[1], level)]
+            a0, a1 = self.ks_inner(digits, keys.rot[g], level)
+            y0 = a0 if y0 is None else self.padd(y0, a0, ext)
+            y1 = a1 if y1 is None else self.padd(y1, a1, ext)
+            c0 = self.padd(c0, self.pauto(ct.polys[0], g, idx), idx)
+        if y0 is not None:
+            c0 = self.padd(c0, self.moddown(y0, level), idx)
+            c1 = self.padd(c1, self.moddown(y1, level), idx)
+        return Ciphertext([c0, c1], level)

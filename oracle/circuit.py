@@ -270,13 +270,9 @@ class Evaluator:
                     acc0 = sc.padd(acc0, sc.pmul_ntt(baby_ntt[j][0], pt, idx), idx)
                     acc1 = sc.padd(acc1, sc.pmul_ntt(baby_ntt[j][1], pt, idx), idx)
                 inner = Ciphertext([sc.intt(acc0, idx), sc.intt(acc1, idx)], v.level)
-            if g > 0:
-                inner = sc.rotate(inner, g * n1, self.keys)
-            parts.append(inner)
-        out = parts[0]
-        for ptc in parts[1:]:
-            out = sc.add(out, ptc)
-        return sc.modswitch(out)
+            parts.append((inner, g * n1))
+        # giant steps: the rotated inner sums added with one ModDown (BGV.rotate_sum), then one switch
+        return sc.modswitch(sc.rotate_sum(parts, self.keys))
 
     def add_mask(self, ct: Ciphertext, mask) -> Ciphertext:
         if isinstance(mask, Ciphertext):

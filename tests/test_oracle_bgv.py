@@ -232,6 +232,27 @@ def test_rotations(scheme, keys):
     assert all((p == q).all() for p, q in zip(single.polys, rots[5].polys))
 
 
+def test_rotate_sum(scheme, keys):
+    """One ModDown for a sum of rotations: decrypts to the sum of the rotated messages (the same as
+    the sum of single rotations), and with no rotated term it is the plain sum."""
+    rng = np.random.default_rng(12)
+    msgs = [rng.integers(0, T, size=(2, scheme.N // 2)) for _ in range(4)]
+    cts = [scheme.encrypt_slots(keys, m, b"\x0e" * 32, 20 + i) for i, m in enumerate(msgs)]
+    rs = [0, 2, 16, 31]
+    out = scheme.rotate_sum(list(zip(cts, rs)), keys)
+    want = sum(S.rot(m, r) for m, r in zip(msgs, rs)) % T
+    assert (scheme.decrypt_slots(keys, out) == want).all()
+    single = cts[0]
+    for ct, r in zip(cts[1:], rs[1:]):
+        single = scheme.add(single, scheme.rotate(ct, r, keys))
+    assert (scheme.decrypt_slots(keys, single) == want).all()
+    plain = scheme.rotate_sum([(cts[0], 0), (cts[1], 0)], keys)
+    assert all((p == q).all() for p, q in zip(plain.polys, scheme.add(cts[0], cts[1]).polys))
+    # a lower level, and the switch after it keeps the message
+    low = scheme.rotate_sum([(scheme.modswitch_to(ct, 2), r) for ct, r in zip(cts, rs)], keys)
+    assert (scheme.decrypt_slots(keys, scheme.modswitch(low)) == want).all()
+
+
 def test_keyswitch_lower_level(scheme, keys):
     """The top-level key serves every lower level (dropped limbs removed)."""
     rng = np.random.default_rng(10)
