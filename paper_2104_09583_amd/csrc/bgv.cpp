@@ -830,4 +830,49 @@ CtPtr op_rotate(Context& c, const Keys& k, const Ct& a, int32_t r) {
   return std::move(v[0]);
 }
 
+// sum_u rot(x_u, r_u) with one ModDown: the rotated terms' key-switch inner products are added in the
+// extended basis and brought down once; sigma(c0) parts and unrotated terms are added in Q_l
+CtPtr op_rotate_sum(Context& c, const Keys& k, const std::vector<std::pair<const Ct*, int32_t>>& items) {
+  if (items.empty()) fail(COPSE_EINVAL, "empty rotation sum");
+  const size_t N = c.N;
+  const int l = items[0].first->level, nl = l + 1, nE = nl + c.alpha, D = c.n_digits(l);
+  const int Lt = c.n_primes();
+  for (auto& it : items)
+    if (it.first->level != l || it.first->npolys != 2) fail(COPSE_EINVAL, "rotation sum terms must share one level");
+  std::vector<int2> er;
+  for (int kk = 0; kk < 2; ++kk)
+    for (int o = 0; o < nE; ++o) er.push_back(make_int2(kk * nE + o, o < nl ? o : c.L + 1 + (o - nl)));
+  const int2* extrows = c.rows("extrows:" + std::to_string(l), er);
+  CtPtr unrot;               // sum of the unrotated terms
+  DBuf c0s(&c, (size_t)nl * N), acc(&c, (size_t)2 * nE * N), one(&c, (size_t)2 * nE * N);
+  bool have = false;
+  for (auto& it : items) {
+    const Ct& x = *it.first;
+    const uint64_t g = galois_of(c, it.second);
+    if (g == 1) {
+      unrot = unrot ? op_add(c, *unrot, x) : ct_copy(c, x);
+      continue;
+    }
+    auto kit = k.rot.find(g);
+    if (kit == k.rot.end()) fail(COPSE_EKEY, "rotation key for offset " + std::to_string(it.second) + " absent");
+    DBuf ext = modup(c, x.poly(1, N), l);
+    KsJob job{ext.get(), kit->second->b.get(), kit->second->a.get(), have ? one.get() : acc.get(), g};
+    launch_ks_inner(c, &job, 1, D, nE, l, (size_t)Lt * N);
+    if (have) {
+      launch_add(c, acc.get(), acc.get(), one.get(), extrows, 2 * nE);
+      DBuf t(&c, (size_t)nl * N);
+      launch_automorphism(c, t.get(), x.poly(0, N), g, nl, 1);
+      launch_add(c, c0s.get(), c0s.get(), t.get(), ct_rows(c, 1, nl), nl);
+    } else {
+      launch_automorphism(c, c0s.get(), x.poly(0, N), g, nl, 1);
+    }
+    have = true;
+  }
+  if (!have) return unrot;
+  auto o = ct_alloc(c, l, 2);
+  moddown(c, acc.get(), 2, l, o->data(), c0s.get(), 0, 2);   // the sigma(c0) sum joins poly 0
+  if (unrot) return op_add(c, *o, *unrot);
+  return o;
+}
+
 }  // namespace copse

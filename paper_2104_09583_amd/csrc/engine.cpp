@@ -240,30 +240,16 @@ static std::vector<SCt> b_down(Context& c, std::vector<SCt> v, const std::vector
 }
 
 // ------------------------------------------------------------------ key switching (batched)
-struct KsReq {
-  int input;
-  const Keys::KSK* key;
-  uint64_t g;
-  double* out;          // 2 polys at the level
-  const double* add;    // mode 1: (d0, d1) to add; mode 2: c0 to permute and add
-};
-
-// merge (add_mode 1 only): the ModDown also switches to level - 1, as a relinearization followed by a
-// modulus switch would; each request's out then holds 2 polys of `level` limbs
-static void ks_batch(Context& c, int level, const std::vector<const double*>& inputs, const std::vector<KsReq>& reqs,
-                     int add_mode, bool merge = false) {
-  if (reqs.empty()) return;
+// ModUp of every input (NTT form, `level`): coefficient form, base conversion per digit, transform of the
+// new rows; out [I][D][nE][N] (the digits' own limbs are not copied: readers take them from the input)
+static DBuf modup_batch(Context& c, int level, const std::vector<const double*>& inputs) {
   const size_t N = c.N;
   const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
-  const int I = (int)inputs.size(), R = (int)reqs.size();
-  const int Lt = c.n_primes();
+  const int I = (int)inputs.size();
   KSTables& T = c.kstab(level);
-  const bool fused = bridge_supported(c, c.alpha);
-  if (merge && !(fused && add_mode == 1 && level >= 1 && T.mm_ok))
-    fail(COPSE_EINVAL, "internal: merged switch not available here");
-  // ModUp of every input: coefficient form, base conversion per digit, transform of the new rows
   DBuf cf(&c, (size_t)I * nl * N);
   DBuf ext(&c, (size_t)I * D * nE * N);
+  const bool fused = bridge_supported(c, c.alpha);
   if (!fused) launch_gather(c, cf.get(), inputs, nl);
   if (fused) {
     // inverse row pass read straight from the inputs, then per digit the fused column passes with the
@@ -306,6 +292,31 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
     if (fused) launch_ntt_fwd_rows(c, ext.get(), r, cnt);
     else launch_ntt_fwd(c, ext.get(), r, cnt);
   }
+  return ext;
+}
+
+struct KsReq {
+  int input;
+  const Keys::KSK* key;
+  uint64_t g;
+  double* out;          // 2 polys at the level
+  const double* add;    // mode 1: (d0, d1) to add; mode 2: c0 to permute and add
+};
+
+// merge (add_mode 1 only): the ModDown also switches to level - 1, as a relinearization followed by a
+// modulus switch would; each request's out then holds 2 polys of `level` limbs
+static void ks_batch(Context& c, int level, const std::vector<const double*>& inputs, const std::vector<KsReq>& reqs,
+                     int add_mode, bool merge = false) {
+  if (reqs.empty()) return;
+  const size_t N = c.N;
+  const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
+  const int I = (int)inputs.size(), R = (int)reqs.size();
+  const int Lt = c.n_primes();
+  KSTables& T = c.kstab(level);
+  const bool fused = bridge_supported(c, c.alpha);
+  if (merge && !(fused && add_mode == 1 && level >= 1 && T.mm_ok))
+    fail(COPSE_EINVAL, "internal: merged switch not available here");
+  DBuf ext = modup_batch(c, level, inputs);
   // inner products
   DBuf acc(&c, (size_t)R * 2 * nE * N);
   std::vector<KsJob2> jobs;
@@ -529,42 +540,103 @@ static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, co
     in2 = b_relin(c, k, in3);
   }
   auto ptr2 = [&](int z) -> const double* { return enc ? in2[z]->data() : inner.get() + (size_t)z * ps2; };
-  DBuf rb(&c, (size_t)ngs * G * ps2);
-  std::vector<const double*> inputs;
-  std::vector<KsReq> reqs;
-  for (size_t i = 0; i < plans.size(); ++i) {
-    const MatPlan& P = *plans[i];
-    for (size_t s = 0; s < P.groups.size(); ++s) {
-      const uint32_t g = P.groups[s];
+  const int np = (int)plans.size();
+  std::vector<std::vector<SCt>> out(np, std::vector<SCt>(G));
+  // Giant steps: per output (product i, batch element b), sum_s rot(inner_s, g_s n1) with one ModDown of
+  // the summed key-switch inner products (BGV rotation sum), then one switch and the mask.
+  if (merged_switch_ok(c, level)) {
+    // one batched pass: ModUp of every rotated inner sum; the sigma(c0) parts and the unrotated inner sum
+    // gathered per output (the addend); the inner products summed per output, with P times the addend's
+    // top limb on the top data row; the ModDown merged with the switch, whose finish adds the mask
+    KSTables& T = c.kstab(level);
+    const int nE = nl + c.alpha, D = c.n_digits(level);
+    std::vector<const double*> inputs;
+    std::vector<KsSumJob> jobs;
+    std::vector<AutoTerm> terms;
+    std::vector<KsSumOut> kouts;
+    std::vector<AutoOut> aouts;
+    std::vector<double*> outs;
+    std::vector<const double*> addp, maskp;
+    DBuf addend(&c, (size_t)np * G * ps2);
+    DBuf acc(&c, (size_t)np * G * 2 * nE * N);
+    auto res = alloc_batch(c, np * G, level - 1, 2);
+    for (int i = 0; i < np; ++i) {
+      const MatPlan& P = *plans[i];
       for (int b = 0; b < G; ++b) {
-        const int z = (off[i] + (int)s) * G + b;
-        double* dst = rb.get() + (size_t)z * ps2;
-        if (g == 0) {
-          // group 0 needs no rotation: the plaintext-model sum reads it in place
-          if (enc) launch_copy(c, dst, ptr2(z), ps2);
-          continue;
+        const int u = i * G + b;
+        AutoOut ao{addend.get() + (size_t)u * ps2, nullptr, nullptr, (int)terms.size(), 0};
+        KsSumOut ko{acc.get() + (size_t)u * 2 * nE * N, addend.get() + (size_t)u * ps2, (int)jobs.size(), 0};
+        for (size_t s2 = 0; s2 < P.groups.size(); ++s2) {
+          const uint32_t g = P.groups[s2];
+          const int z = (off[i] + (int)s2) * G + b;
+          if (g == 0) {
+            ao.f0 = ptr2(z);
+            ao.f1 = ptr2(z) + (size_t)nl * N;
+            continue;
+          }
+          const uint64_t gal = galois_of(c, (int64_t)g * P.n1);
+          auto it = k.rot.find(gal);
+          if (it == k.rot.end()) fail(COPSE_EKEY, "giant-step key absent");
+          inputs.push_back(ptr2(z) + (size_t)nl * N);
+          jobs.push_back(KsSumJob{ptr2(z) + (size_t)nl * N, nullptr, it->second->b.get(), it->second->a.get(), gal});
+          terms.push_back(AutoTerm{ptr2(z), gal});
+          ++ao.count;
+          ++ko.count;
         }
-        const uint64_t gal = galois_of(c, (int64_t)g * P.n1);
-        auto it = k.rot.find(gal);
-        if (it == k.rot.end()) fail(COPSE_EKEY, "giant-step key absent");
-        inputs.push_back(ptr2(z) + (size_t)nl * N);
-        reqs.push_back(KsReq{(int)inputs.size() - 1, it->second.get(), gal, dst, ptr2(z)});
+        aouts.push_back(ao);
+        kouts.push_back(ko);
+        outs.push_back(res[u]->data());
+        addp.push_back(addend.get() + (size_t)u * ps2);
+        maskp.push_back(adds ? (*adds)[u] : nullptr);
+        out[i][b] = res[u];
       }
     }
+    DBuf ext = inputs.empty() ? DBuf(&c, 1) : modup_batch(c, level, inputs);
+    for (size_t t = 0; t < jobs.size(); ++t) jobs[t].ext = ext.get() + t * (size_t)D * nE * N;
+    launch_auto_sum(c, terms, aouts, nl);
+    launch_ks_inner_sum(c, jobs, kouts, D, nE, level, (size_t)c.n_primes() * N, T.mm_ptop);
+    const int l = level, R = np * G;
+    const int2* r = rows_cached(c, "mdmsrows:" + std::to_string(level) + ":" + std::to_string(2 * R), [&] {
+      std::vector<int2> h;
+      for (int kk = 0; kk < 2 * R; ++kk) {
+        for (int s2 = 0; s2 < c.alpha; ++s2) h.push_back(make_int2(kk * nE + nl + s2, c.L + 1 + s2));
+        h.push_back(make_int2(kk * nE + l, l));
+      }
+      return h;
+    }());
+    launch_ntt_inv_rows(c, acc.get(), r, 2 * R * (c.alpha + 1));
+    std::vector<int2> inr, outr;
+    for (int s2 = 0; s2 < c.alpha; ++s2) inr.push_back(make_int2(nl + s2, c.L + 1 + s2));
+    inr.push_back(make_int2(l, l));
+    for (int i = 0; i < l; ++i) outr.push_back(make_int2(i, i));
+    DBuf w(&c, (size_t)2 * R * l * N);
+    launch_bridge(c, 2, w.get(), rows_cached(c, "mdmsout:" + std::to_string(level), outr), l, acc.get(),
+                  rows_cached(c, "mdmsin:" + std::to_string(level), inr), c.alpha + 1, T.d_mm_mult, T.d_mm_mat,
+                  2 * R, (size_t)nE * N, (size_t)l * N);
+    launch_ntt_fwd_rows_mdms_finish(c, outs, addp, acc.get(), w.get(), nE, l, T.d_mm_m1, T.d_mm_m2, T.d_mm_m3,
+                                    adds ? &maskp : nullptr, add_np);
+    return out;
   }
-  ks_batch(c, level, inputs, reqs, 2);
-  const int np = (int)plans.size();
-  auto sums = alloc_batch(c, np * G, level, 2);
+  // otherwise (small rings): the rotation sum per output, then one batched switch with the masks
+  std::vector<SCt> sums;
+  std::vector<std::shared_ptr<Ct>> views;
   for (int i = 0; i < np; ++i) {
     const MatPlan& P = *plans[i];
-    const double* first = (!enc && P.groups[0] == 0) ? inner.get() + (size_t)off[i] * G * ps2 : nullptr;
-    launch_sum_parts(c, sums[(size_t)i * G]->data(), rb.get() + (size_t)off[i] * G * ps2, (int)P.groups.size(),
-                     (size_t)G * ps2, ps2, first, ps2, nl, 2 * nl, G);
+    for (int b = 0; b < G; ++b) {
+      std::vector<std::pair<const Ct*, int32_t>> items;
+      for (size_t s2 = 0; s2 < P.groups.size(); ++s2) {
+        const int z = (off[i] + (int)s2) * G + b;
+        auto v = std::make_shared<Ct>();
+        v->level = level; v->npolys = 2; v->n = N; v->ptr = const_cast<double*>(ptr2(z));
+        views.push_back(v);
+        items.push_back({v.get(), (int32_t)(P.groups[s2] * P.n1)});
+      }
+      sums.push_back(SCt(op_rotate_sum(c, k, items).release()));
+    }
   }
   std::vector<const Ct*> sin;
   for (auto& x : sums) sin.push_back(x.get());
   auto sw = b_modswitch(c, sin, adds, add_np);
-  std::vector<std::vector<SCt>> out(np);
   for (int i = 0; i < np; ++i) out[i].assign(sw.begin() + (size_t)i * G, sw.begin() + (size_t)(i + 1) * G);
   return out;
 }

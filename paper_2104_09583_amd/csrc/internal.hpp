@@ -246,9 +246,11 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
                                    int nl, const double* pinv, const double* tpinv, int add_mode);
 // forward row pass of the merged ModDown + switch rows w (l = level of the inputs, l output limbs) fused
 // with its finish: out_j[k][i] = acc[2j+k][i] m1_i + add_j[k][i] m3_i - w[2j+k][i] m2_i  (i < l)
+// masks (optional): masks[j] (l limbs per poly) is added to the first mask_np polys of out[j]
 void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out,
                                      const std::vector<const double*>& add, const double* acc, const double* w,
-                                     int nE, int l, const double* m1, const double* m2, const double* m3);
+                                     int nE, int l, const double* m1, const double* m2, const double* m3,
+                                     const std::vector<const double*>* masks = nullptr, int mask_np = 0);
 // forward row pass of the modulus-switch rows fused with the switch's finish; job j switches from
 // levels[j], its rows w[j] = [np][levels[j]][N], its table tabs[j] (as launch_ms_finish_multi)
 void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
@@ -366,6 +368,35 @@ void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const s
 // ptop: P mod q_level, the factor of the jobs' top addends
 void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
                       double ptop = 0.0);
+// Key-switch inner products summed per output (giant steps of a product, one ModDown for their sum):
+// output u accumulates, over its jobs, sum_j digit_j(sigma_g(in)) key_j in the extended basis, plus
+// P times the top limb of its addend (2 polys, NTT form, nl limbs) on the top data row.
+struct KsSumJob {
+  const double* in;     // the rotated input poly (NTT form, nl limbs): the digits' own limbs
+  const double* ext;    // its ModUp output [D][nE][N]
+  const double* kb;
+  const double* ka;
+  uint64_t g;
+};
+struct KsSumOut {
+  double* acc;          // [2][nE][N]
+  const double* top;    // the addend
+  int first, count;     // its jobs
+};
+void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const std::vector<KsSumOut>& outs, int D,
+                         int nE, int level, size_t key_ds, double ptop);
+// Per output u: dst_u poly 0 = f0_u + sum_t sigma_{g_t}(c0_t), poly 1 = f1_u (null f: zero), nl limbs.
+struct AutoTerm {
+  const double* c0;
+  uint64_t g;
+};
+struct AutoOut {
+  double* dst;
+  const double* f0;
+  const double* f1;
+  int first, count;
+};
+void launch_auto_sum(Context& c, const std::vector<AutoTerm>& terms, const std::vector<AutoOut>& outs, int nl);
 void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
                        const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE, int nl,
                        const double* pinv, const double* tpinv, int add_mode);
@@ -441,6 +472,8 @@ CtPtr op_relin(Context& c, const Keys& k, const Ct& a);
 CtPtr op_mul(Context& c, const Keys& k, const Ct& a, const Ct& b);
 std::vector<CtPtr> op_rotate_hoisted(Context& c, const Keys& k, const Ct& a, const std::vector<int32_t>& rs);
 CtPtr op_rotate(Context& c, const Keys& k, const Ct& a, int32_t r);
+// sum of rotations of same-level ciphertexts with one ModDown (see bgv.cpp)
+CtPtr op_rotate_sum(Context& c, const Keys& k, const std::vector<std::pair<const Ct*, int32_t>>& items);
 
 void to_coef_u64(Context& c, const Ct& a, std::vector<uint64_t>& out);
 CtPtr from_coef_u64(Context& c, const uint64_t* data, int level, int npolys);

@@ -684,6 +684,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
     double v = mul_lazy(yv[kk], m1, pr.q, pr.qinv) - mul_lazy(wv, m2, pr.q, pr.qinv);
     if (kMode == 3) v += mul_lazy(add.p[j][((size_t)k * (nl + 1) + i) * N + c], m3, pr.q, pr.qinv);
     v = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
+    // kMode 3: an optional mask (the `in` pack, l limbs per poly) on the first add_np polys
+    if (kMode == 3 && k < add_np && in.p[j] != nullptr) v = mod_add(v, in.p[j][orow + c], pr.q);
     if (kMode == 1) {
       if (add_mode == 1) v = mod_add(v, add.p[j][orow + c], pr.q);
       if (add_mode == 2 && k == 0) {
@@ -1185,29 +1187,31 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
 
 void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out,
                                      const std::vector<const double*>& add, const double* acc, const double* w,
-                                     int nE, int l, const double* m1, const double* m2, const double* m3) {
+                                     int nE, int l, const double* m1, const double* m2, const double* m3,
+                                     const std::vector<const double*>* masks, int mask_np) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
   if (l < 1) fail(COPSE_EINVAL, "internal: no switch below level 0");
   for (size_t first = 0; first < out.size(); first += kPack) {
     const int cnt = (int)std::min<size_t>(kPack, out.size() - first);
     MPack po;
-    Pack pa, none{};
+    Pack pa, pm, none{};
     GPack pg;
     IPack nolv{};
     for (int k = 0; k < cnt; ++k) {
       po.p[k] = out[first + k];
       pa.p[k] = add[first + k];
+      pm.p[k] = masks ? (*masks)[first + k] : nullptr;
       pg.g[k] = 1;
     }
     hipEvent_t ev;
     prof_begin(c, 7, &ev);
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<3>, dim3((unsigned)(c.N / 4096), l, 2 * cnt), dim3(512), 0,
-                       c.stream, po, none, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
-                       w + first * 2 * l * c.N, nE, l, 2, 0, 0, m1, m2, c.d_primes, (int)c.log_n,
-                       (int)c.log_n - 12, m3);
+                       c.stream, po, pm, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
+                       w + first * 2 * l * c.N, nE, l, 2, 0, masks ? mask_np : 0, m1, m2, c.d_primes,
+                       (int)c.log_n, (int)c.log_n - 12, m3);
     COPSE_HIP(hipGetLastError());
-    // per output row: the bridge's row, the accumulator and addend rows read, the output written
-    prof_end(c, 7, ev, 4.0 * l * 2 * cnt * (double)c.N * 8.0);
+    // per output row: the bridge's row, the accumulator and addend rows read, the output written (+ mask)
+    prof_end(c, 7, ev, (4.0 * 2 + (masks ? mask_np : 0)) * l * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1813,6 +1817,129 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
       keys += !seen;
     }
     prof_end(c, 4, ev, ((D + 2.0) * cnt + 2.0 * D * keys) * nE * (double)c.N * 8.0);
+  }
+}
+
+// Per-output sums of key-switch inner products (see launch_ks_inner_sum).  grid: x over coefficients,
+// y over extended rows, z over the outputs of the pack; each thread runs through its output's jobs.
+struct KsSumPack {
+  static constexpr int kJobs = 48, kOuts = 16;
+  KsSumJob j[kJobs];
+  KsSumOut o[kOuts];
+};
+__global__ void ks_inner_sum_kernel(KsSumPack pk, int D, int nE, int nl, int L, int alpha, int logN,
+                                    size_t key_ds, const DevPrime* P, double ptop) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int o = blockIdx.y;
+  const KsSumOut ou = pk.o[blockIdx.z];
+  const int prime = o < nl ? o : L + 1 + (o - nl);
+  const DevPrime& pr = P[prime];
+  const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
+  double a0 = 0.0, a1 = 0.0;
+  for (int t = ou.first; t < ou.first + ou.count; ++t) {
+    const KsSumJob jb = pk.j[t];
+    const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
+    for (int j = 0; j < D; ++j) {
+      const double e = (j == own) ? jb.in[(size_t)o * N + src] : jb.ext[((size_t)j * nE + o) * N + src];
+      const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
+      a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
+      a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
+    }
+    // D <= 8 lazy products per job: fold back after each job
+    a0 = reduce_sym(a0, pr.q, pr.qinv);
+    a1 = reduce_sym(a1, pr.q, pr.qinv);
+  }
+  if (o == nl - 1) {   // uniform per workgroup
+    a0 += mul_lazy(ou.top[(size_t)o * N + i], ptop, pr.q, pr.qinv);
+    a1 += mul_lazy(ou.top[((size_t)nl + o) * N + i], ptop, pr.q, pr.qinv);
+  }
+  ou.acc[(size_t)o * N + i] = canon(reduce_sym(a0, pr.q, pr.qinv), pr.q);
+  ou.acc[((size_t)nE + o) * N + i] = canon(reduce_sym(a1, pr.q, pr.qinv), pr.q);
+}
+
+void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const std::vector<KsSumOut>& outs, int D,
+                         int nE, int level, size_t key_ds, double ptop) {
+  // packs of whole outputs: at most kOuts outputs and kJobs jobs each
+  size_t u0 = 0;
+  while (u0 < outs.size()) {
+    KsSumPack pk;
+    int nu = 0, nj = 0;
+    while (u0 + nu < outs.size() && nu < KsSumPack::kOuts) {
+      const KsSumOut& o = outs[u0 + nu];
+      if (o.count > KsSumPack::kJobs) fail(COPSE_EINVAL, "internal: too many giant steps for one output");
+      if (nj + o.count > KsSumPack::kJobs) break;
+      pk.o[nu] = o;
+      pk.o[nu].first = nj;
+      for (int t = 0; t < o.count; ++t) pk.j[nj + t] = jobs[o.first + t];
+      nj += o.count;
+      ++nu;
+    }
+    hipEvent_t ev;
+    prof_begin(c, 4, &ev);
+    hipLaunchKernelGGL(ks_inner_sum_kernel, dim3((unsigned)((c.N + 255) / 256), nE, nu), dim3(256), 0, c.stream, pk,
+                       D, nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes, ptop);
+    COPSE_HIP(hipGetLastError());
+    // per job: D digit rows read; per output: 2 rows written; each distinct key's 2 D rows once
+    int keys = 0;
+    for (int t = 0; t < nj; ++t) {
+      bool seen = false;
+      for (int t2 = 0; t2 < t; ++t2) seen |= pk.j[t2].kb == pk.j[t].kb;
+      keys += !seen;
+    }
+    prof_end(c, 4, ev, ((double)D * nj + 2.0 * nu + 2.0 * D * keys) * nE * (double)c.N * 8.0);
+    u0 += nu;
+  }
+}
+
+// Sums of automorphisms of c0 parts plus optional unrotated parts (see launch_auto_sum).
+// grid: x over coefficients, y over limbs, z over (output, poly) of the pack.
+struct AutoSumPack {
+  static constexpr int kTerms = 64, kOuts = 16;
+  AutoTerm t[kTerms];
+  AutoOut o[kOuts];
+};
+__global__ void auto_sum_kernel(AutoSumPack pk, int nl, const DevPrime* P, int logN) {
+  const size_t N = (size_t)1 << logN;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int r = blockIdx.y, u = blockIdx.z >> 1, k = blockIdx.z & 1;
+  const AutoOut ou = pk.o[u];
+  const DevPrime& pr = P[r];
+  const double* f = k == 0 ? ou.f0 : ou.f1;
+  double v = f != nullptr ? f[(size_t)r * N + i] : 0.0;
+  if (k == 0)
+    for (int t = ou.first; t < ou.first + ou.count; ++t) {
+      const AutoTerm tm = pk.t[t];
+      const size_t src = tm.g == 1 ? i : auto_src((uint32_t)i, tm.g, logN);
+      v = mod_add(v, tm.c0[(size_t)r * N + src], pr.q);
+    }
+  ou.dst[((size_t)k * nl + r) * N + i] = v;
+}
+
+void launch_auto_sum(Context& c, const std::vector<AutoTerm>& terms, const std::vector<AutoOut>& outs, int nl) {
+  size_t u0 = 0;
+  while (u0 < outs.size()) {
+    AutoSumPack pk;
+    int nu = 0, nt = 0;
+    while (u0 + nu < outs.size() && nu < AutoSumPack::kOuts) {
+      const AutoOut& o = outs[u0 + nu];
+      if (o.count > AutoSumPack::kTerms) fail(COPSE_EINVAL, "internal: too many giant steps for one output");
+      if (nt + o.count > AutoSumPack::kTerms) break;
+      pk.o[nu] = o;
+      pk.o[nu].first = nt;
+      for (int t = 0; t < o.count; ++t) pk.t[nt + t] = terms[o.first + t];
+      nt += o.count;
+      ++nu;
+    }
+    hipEvent_t ev;
+    prof_begin(c, 6, &ev);
+    hipLaunchKernelGGL(auto_sum_kernel, dim3((unsigned)((c.N + 255) / 256), nl, 2 * nu), dim3(256), 0, c.stream, pk,
+                       nl, c.d_primes, (int)c.log_n);
+    COPSE_HIP(hipGetLastError());
+    prof_end(c, 6, ev, ((double)nt + 4.0 * nu) * nl * (double)c.N * 8.0);
+    u0 += nu;
   }
 }
 

@@ -88,6 +88,7 @@ struct Plain1 {
     for (int32_t r : used) baby[r] = share(op_rotate(c, k, *v, r));   // one key switch per rotation
     const int nl = v->level + 1;
     std::vector<SCt> parts;
+    std::vector<int32_t> shifts;
     for (uint32_t g = 0; g < n2; ++g) {
       std::vector<std::pair<uint32_t, const Operand*>> terms;
       for (uint32_t j = 0; j < n1; ++j) {
@@ -116,12 +117,14 @@ struct Plain1 {
         }
         inner = op_relin(c, k, *acc);
       }
-      if (g > 0) inner = op_rotate(c, k, *inner, (int32_t)(g * n1));
       parts.push_back(share(std::move(inner)));
+      shifts.push_back((int32_t)(g * n1));
     }
-    SCt out = parts[0];
-    for (size_t i = 1; i < parts.size(); ++i) out = share(op_add(c, *out, *parts[i]));
-    return share(op_modswitch(c, *out));
+    // giant steps: the rotated inner sums added with one ModDown, then one switch
+    std::vector<std::pair<const Ct*, int32_t>> items;
+    for (size_t i = 0; i < parts.size(); ++i) items.push_back({parts[i].get(), shifts[i]});
+    auto sum = op_rotate_sum(c, k, items);
+    return share(op_modswitch(c, *sum));
   }
 
   SCt add_mask(const SCt& a, const Operand& mk) {
