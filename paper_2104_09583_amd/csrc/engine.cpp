@@ -473,9 +473,10 @@ std::vector<SCt> b_mul(Context& c, const Keys& k, const std::vector<std::pair<SC
   return out;
 }
 
-// hoisted rotations of each of v (same level) by every offset in rots, into B[u][b]
-static void b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*>& v, const std::vector<int32_t>& rots,
-                          double* B) {
+// hoisted rotations of each of v (same level) by every offset in rots, into B[u][b]; returns the slot u of
+// the rotation by zero when it is left empty (the inner sums then read v in place), else -1
+static int b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*>& v, const std::vector<int32_t>& rots,
+                         double* B) {
   const size_t N = c.N;
   const int l = v[0]->level, nl = l + 1, G = (int)v.size();
   const size_t ps = (size_t)2 * nl * N;
@@ -485,8 +486,13 @@ static void b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*
     inputs.push_back(x->poly(1, N));
   }
   std::vector<KsReq> reqs;
+  int u0 = -1;
   for (size_t u = 0; u < rots.size(); ++u) {
     uint64_t g = galois_of(c, rots[u]);
+    if (g == 1 && u0 < 0 && G <= kPack) {
+      u0 = (int)u;
+      continue;
+    }
     for (int b = 0; b < G; ++b) {
       double* dst = B + ((size_t)u * G + b) * ps;
       if (g == 1) {
@@ -499,6 +505,7 @@ static void b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*
     }
   }
   ks_batch(c, l, inputs, reqs, 2);
+  return u0;
 }
 
 // ------------------------------------------------------------------ MatMul (baby-step / giant-step)
@@ -506,9 +513,11 @@ static void b_rotate_into(Context& c, const Keys& k, const std::vector<const Ct*
 // inner sums over the giant groups of all of them (tab is their concatenated [u][group] diagonal table),
 // one batch of giant rotations, a sum per product and batch element, one switch for all.  adds[i * G + b]
 // (optional) is added to the first add_np polys of result (i, b) after the switch.
+// u0 / v0: the baby slot of the rotation by zero left empty by b_rotate_into and the unrotated inputs
 static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, const std::vector<const MatPlan*>& plans,
                                                    const double* const* tab, int n_u, const double* B, int G,
-                                                   int level, const std::vector<const double*>* adds = nullptr,
+                                                   int level, int u0, const std::vector<const Ct*>& v0,
+                                                   const std::vector<const double*>* adds = nullptr,
                                                    int add_np = 0) {
   const size_t N = c.N;
   const int nl = level + 1;
@@ -526,7 +535,9 @@ static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, co
   size_t nnz = 0;
   for (auto* P : plans)
     for (auto* d : P->tab) nnz += d != nullptr;
-  launch_mm_inner(c, inner.get(), B, tab, n_u, ngs, G, nl, (size_t)G * ps2, ps2, enc, nnz);
+  std::vector<const double*> b0;
+  for (auto* x : v0) b0.push_back(x->data());
+  launch_mm_inner(c, inner.get(), B, tab, n_u, ngs, G, nl, (size_t)G * ps2, ps2, enc, nnz, u0, &b0);
   std::vector<SCt> in2;   // encrypted model: per (group, b) relinearized inner sums
   if (enc) {
     std::vector<SCt> t3;
@@ -715,8 +726,8 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
     const MatPlan& P = M.plan_F;
     const int GP = (int)all.size();
     DBuf B(&c, P.rots.size() * GP * 2 * (size_t)(c.L + 1) * N);
-    b_rotate_into(c, k, all, P.rots, B.get());
-    auto r = b_matmul_many(c, k, {&P}, P.d_tab, (int)P.rots.size(), B.get(), GP, c.L)[0];
+    const int u0 = b_rotate_into(c, k, all, P.rots, B.get());
+    auto r = b_matmul_many(c, k, {&P}, P.d_tab, (int)P.rots.size(), B.get(), GP, c.L, u0, all)[0];
     for (int b = 0; b < G; ++b) {
       rep_planes.emplace_back(r.begin() + (size_t)b * p, r.begin() + (size_t)(b + 1) * p);
       for (int kb = 0; kb < p; ++kb) planes_in[b][kb] = rep_planes[b][kb].get();
@@ -822,8 +833,8 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
     DBuf B(&c, P.rots.size() * G * 2 * (size_t)(l + 1) * N);
     std::vector<const Ct*> v;
     for (auto& x : dec) v.push_back(x.get());
-    b_rotate_into(c, k, v, P.rots, B.get());
-    src = b_matmul_many(c, k, {&P}, P.d_tab, (int)P.rots.size(), B.get(), G, l)[0];
+    const int u0 = b_rotate_into(c, k, v, P.rots, B.get());
+    src = b_matmul_many(c, k, {&P}, P.d_tab, (int)P.rots.size(), B.get(), G, l, u0, v)[0];
   }
   // 3. levels: one set of hoisted baby rotations shared by every level
   next_stage(2);
@@ -833,7 +844,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
     DBuf B(&c, M.lvl_rots.size() * G * 2 * (size_t)(l + 1) * N);
     std::vector<const Ct*> v;
     for (auto& x : src) v.push_back(x.get());
-    b_rotate_into(c, k, v, M.lvl_rots, B.get());
+    const int u0 = b_rotate_into(c, k, v, M.lvl_rots, B.get());
     // all level products at once; the mask is added by the switch that ends each product
     std::vector<const MatPlan*> plans;
     std::vector<const double*> madd;
@@ -845,7 +856,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
       if (!mk.ct && mk.pt->level != ml) fail(COPSE_EINVAL, "internal: mask level");
       for (int b = 0; b < G; ++b) madd.push_back(mk.ct ? mk.ct->data() : mk.pt->buf.get());
     }
-    lv = b_matmul_many(c, k, plans, M.d_lcat, (int)M.lvl_rots.size(), B.get(), G, l, &madd,
+    lv = b_matmul_many(c, k, plans, M.d_lcat, (int)M.lvl_rots.size(), B.get(), G, l, u0, v, &madd,
                        M.masks[0].ct ? 2 : 1);
   }
   // 4. product tree

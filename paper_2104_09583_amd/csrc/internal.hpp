@@ -404,8 +404,10 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
 // whole chunks of a row); tab[u * n_groups + s] is the pre-rotated diagonal that multiplies baby step u in giant
 // group s (plaintext [nl][N], or ciphertext [2][nl][N] when enc), null when that diagonal is zero.
 constexpr int kMmTabPad = 32;
+// u0 >= 0: baby step u0 of batch element b is read from b0[b] instead of the baby buffer
 void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int n_groups,
-                     int G, int nl, size_t baby_slot, size_t baby_b, bool enc, size_t nnz);
+                     int G, int nl, size_t baby_slot, size_t baby_b, bool enc, size_t nnz, int u0 = -1,
+                     const std::vector<const double*>* b0 = nullptr);
 // out_j = sum of terms[j * T .. j * T + T - 1] (canonical, exact)
 void launch_sum_terms(Context& c, const std::vector<double*>& out, const std::vector<const double*>& terms, int T,
                       int nl, int rows_per_job);

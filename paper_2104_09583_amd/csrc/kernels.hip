@@ -1613,20 +1613,28 @@ void launch_moddown_finish(Context& c, double* out, const double* y, size_t ys, 
 namespace copse {
 
 // dst row (j * rows + r) <- src_j row r
+// four consecutive values per thread, as two 16-byte loads and stores (rows hold N = 2^logN >= 16
+// values, so every thread's quad is in range and 32-byte aligned)
 __global__ void gather_kernel(double* dst, Pack src, int rows, int logN) {
   const size_t N = (size_t)1 << logN;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i >= N) return;
   const int r = blockIdx.y, j = blockIdx.z;
-  dst[((size_t)j * rows + r) * N + i] = src.p[j][(size_t)r * N + i];
+  typedef double dvec2 __attribute__((ext_vector_type(2)));
+  const auto* s = (const __attribute__((address_space(1))) dvec2*)(src.p[j] + (size_t)r * N + i);
+  auto* d = (__attribute__((address_space(1))) dvec2*)(dst + ((size_t)j * rows + r) * N + i);
+  const dvec2 a = s[0], b = s[1];
+  d[0] = a;
+  d[1] = b;
 }
 
 void launch_gather(Context& c, double* dst, const std::vector<const double*>& src, int rows) {
+  if (c.N % 4 != 0) fail(COPSE_EINVAL, "internal: gather needs N a multiple of 4");
   for (size_t first = 0; first < src.size(); first += kPack) {
     int cnt = (int)std::min<size_t>(kPack, src.size() - first);
     Pack pk;
     for (int k = 0; k < cnt; ++k) pk.p[k] = src[first + k];
-    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((c.N + 255) / 256), rows, cnt), dim3(256), 0, c.stream,
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((c.N / 4 + 255) / 256), rows, cnt), dim3(256), 0, c.stream,
                        dst + first * rows * c.N, pk, rows, (int)c.log_n);
   }
   COPSE_HIP(hipGetLastError());
@@ -2008,7 +2016,7 @@ template <int GM, bool kEnc, bool kSplit>
 __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out, const double* __restrict__ baby,
                                                        const double* const* __restrict__ tab, int n_u, int ng, int G,
                                                        int nl, size_t baby_slot, size_t baby_b, const DevPrime* P,
-                                                       int logN) {
+                                                       int logN, Pack b0, int u0) {
   constexpr int kNp = kEnc ? 3 : 2;
   constexpr int kRed = kEnc ? 3 : 7;
   const size_t N = (size_t)1 << logN;
@@ -2047,7 +2055,8 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
       any |= ptr[s] != nullptr;
     }
     if (!any) continue;   // uniform: this baby step has no term in the chunk
-    const double* bp = baby + (size_t)u * baby_slot + (size_t)b * baby_b;
+    // baby step u0 (the rotation by zero) is read from the unrotated inputs
+    const double* bp = u == u0 ? b0.p[b] : baby + (size_t)u * baby_slot + (size_t)b * baby_b;
     const double x0 = gload(bp + o), x1 = gload(bp + ps + o);
     double d0[GM], d1[GM];
 #pragma unroll
@@ -2116,20 +2125,25 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
 
 template <int GM, bool kEnc>
 static void mm_inner_launch(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng,
-                            int G, int nl, size_t baby_slot, size_t baby_b) {
+                            int G, int nl, size_t baby_slot, size_t baby_b, const Pack& b0, int u0) {
   const unsigned tiles = (unsigned)((c.N + kMmLanes - 1) / kMmLanes);
   const unsigned bchunks = (unsigned)((G + kMmWaves - 1) / kMmWaves);
   if (G == 1)
     hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc, true>), dim3(tiles, nl, (ng + GM - 1) / GM), dim3(256), 0,
-                       c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+                       c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0, u0);
   else
     hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc, false>), dim3(tiles * bchunks, nl, (ng + GM - 1) / GM), dim3(256),
-                       0, c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n);
+                       0, c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0,
+                       u0);
 }
 
 void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng, int G,
-                     int nl, size_t baby_slot, size_t baby_b, bool enc, size_t nnz) {
+                     int nl, size_t baby_slot, size_t baby_b, bool enc, size_t nnz, int u0,
+                     const std::vector<const double*>* b0) {
   if (ng <= 0 || G <= 0) return;
+  if (u0 >= 0 && (!b0 || (int)b0->size() != G || G > kPack)) fail(COPSE_EINVAL, "internal: unrotated baby inputs");
+  Pack p0{};
+  for (int b = 0; u0 >= 0 && b < G; ++b) p0.p[b] = (*b0)[b];
   if ((size_t)((c.N + kMmLanes - 1) / kMmLanes) * (size_t)((G + kMmWaves - 1) / kMmWaves) > 0x7fffffffu)
     fail(COPSE_EINVAL, "MatMul batch too large");
   hipEvent_t ev;
@@ -2140,8 +2154,8 @@ void launch_mm_inner(Context& c, double* out, const double* baby, const double* 
   const int per = (ng + chunks - 1) / chunks;
   auto run = [&](auto gm_tag) {
     constexpr int GM = decltype(gm_tag)::value;
-    if (enc) mm_inner_launch<GM, true>(c, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b);
-    else mm_inner_launch<GM, false>(c, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b);
+    if (enc) mm_inner_launch<GM, true>(c, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, p0, u0);
+    else mm_inner_launch<GM, false>(c, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, p0, u0);
   };
   if (per <= 4) run(std::integral_constant<int, 4>());
   else if (per <= 8) run(std::integral_constant<int, 8>());
