@@ -52,8 +52,10 @@ KIND_NAMES = {0: "ntt_fwd_rows", 1: "ntt_fwd_cols", 2: "ntt_inv_rows", 3: "ntt_i
               9: "matmul_inner", 10: "ntt_inv_rows_gather"}
 STAGE_NAMES = ("comparison", "reshuffle", "levels", "aggregation")
 # kernel of each class (for the counter runs); class 6 is a family of small kernels and is not a roofline
-KIND_KERNELS = {0: "ntt_rowreg4_kernel<false>", 2: "ntt_rowreg4_kernel<true>", 4: "ks_inner2_kernel",
-                5: "ntt_bridge_kernel", 7: "ntt_rowfwd_finish_kernel<1>", 8: "ntt_rowfwd_finish_kernel<2>",
+# (name patterns for rocprofv3's kernel filter: class 4 is ks_inner2_kernel and ks_inner_sum_kernel, class 7 the
+# ModDown finishes, alone and merged with the switch)
+KIND_KERNELS = {0: "ntt_rowreg4_kernel<false>", 2: "ntt_rowreg4_kernel<true>", 4: "ks_inner",
+                5: "ntt_bridge_kernel", 7: "ntt_rowfwd_finish_kernel<[13]>", 8: "ntt_rowfwd_finish_kernel<2>",
                 9: "mm_inner_kernel", 10: "ntt_rowinv_gather_kernel"}
 
 
