@@ -382,6 +382,7 @@ struct KsSumOut {
   double* acc;          // [2][nE][N]
   const double* top;    // the addend
   int first, count;     // its jobs
+  int accum = 0;        // set by the launcher: add to acc (a later chunk of a long output; no top term)
 };
 void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const std::vector<KsSumOut>& outs, int D,
                          int nE, int level, size_t key_ds, double ptop);
@@ -395,6 +396,7 @@ struct AutoOut {
   const double* f0;
   const double* f1;
   int first, count;
+  int accum = 0;        // set by the launcher: add to dst (a later chunk of a long output; no f terms)
 };
 void launch_auto_sum(Context& c, const std::vector<AutoTerm>& terms, const std::vector<AutoOut>& outs, int nl);
 void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,

@@ -1859,7 +1859,10 @@ __global__ void ks_inner_sum_kernel(KsSumPack pk, int D, int nE, int nl, int L, 
     a0 = reduce_sym(a0, pr.q, pr.qinv);
     a1 = reduce_sym(a1, pr.q, pr.qinv);
   }
-  if (o == nl - 1) {   // uniform per workgroup
+  if (ou.accum) {      // a later chunk: the earlier chunks' canonical sums
+    a0 += ou.acc[(size_t)o * N + i];
+    a1 += ou.acc[((size_t)nE + o) * N + i];
+  } else if (o == nl - 1) {   // uniform per workgroup
     a0 += mul_lazy(ou.top[(size_t)o * N + i], ptop, pr.q, pr.qinv);
     a1 += mul_lazy(ou.top[((size_t)nl + o) * N + i], ptop, pr.q, pr.qinv);
   }
@@ -1867,16 +1870,28 @@ __global__ void ks_inner_sum_kernel(KsSumPack pk, int D, int nE, int nl, int L, 
   ou.acc[((size_t)nE + o) * N + i] = canon(reduce_sym(a1, pr.q, pr.qinv), pr.q);
 }
 
-void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const std::vector<KsSumOut>& outs, int D,
+void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const std::vector<KsSumOut>& outs_in, int D,
                          int nE, int level, size_t key_ds, double ptop) {
-  // packs of whole outputs: at most kOuts outputs and kJobs jobs each
-  size_t u0 = 0;
-  while (u0 < outs.size()) {
+  // outputs with more than kJobs jobs run in chunks: chunk r of every output in round r (rounds in stream
+  // order, later chunks adding to the accumulator); within a round, packs of at most kOuts chunks and kJobs
+  // jobs
+  std::vector<std::vector<KsSumOut>> rounds;
+  for (const KsSumOut& o : outs_in)
+    for (int r = 0, done = 0; done < o.count || r == 0; ++r) {
+      KsSumOut ch = o;
+      ch.first = o.first + done;
+      ch.count = std::min(KsSumPack::kJobs, o.count - done);
+      ch.accum = r > 0;
+      if ((int)rounds.size() <= r) rounds.emplace_back();
+      rounds[r].push_back(ch);
+      done += ch.count;
+    }
+  for (const auto& outs : rounds)
+  for (size_t u0 = 0; u0 < outs.size();) {
     KsSumPack pk;
     int nu = 0, nj = 0;
     while (u0 + nu < outs.size() && nu < KsSumPack::kOuts) {
       const KsSumOut& o = outs[u0 + nu];
-      if (o.count > KsSumPack::kJobs) fail(COPSE_EINVAL, "internal: too many giant steps for one output");
       if (nj + o.count > KsSumPack::kJobs) break;
       pk.o[nu] = o;
       pk.o[nu].first = nj;
@@ -1916,24 +1931,36 @@ __global__ void auto_sum_kernel(AutoSumPack pk, int nl, const DevPrime* P, int l
   const AutoOut ou = pk.o[u];
   const DevPrime& pr = P[r];
   const double* f = k == 0 ? ou.f0 : ou.f1;
-  double v = f != nullptr ? f[(size_t)r * N + i] : 0.0;
+  const size_t d = ((size_t)k * nl + r) * N + i;
+  double v = ou.accum ? ou.dst[d] : f != nullptr ? f[(size_t)r * N + i] : 0.0;
   if (k == 0)
     for (int t = ou.first; t < ou.first + ou.count; ++t) {
       const AutoTerm tm = pk.t[t];
       const size_t src = tm.g == 1 ? i : auto_src((uint32_t)i, tm.g, logN);
       v = mod_add(v, tm.c0[(size_t)r * N + src], pr.q);
     }
-  ou.dst[((size_t)k * nl + r) * N + i] = v;
+  ou.dst[d] = v;
 }
 
-void launch_auto_sum(Context& c, const std::vector<AutoTerm>& terms, const std::vector<AutoOut>& outs, int nl) {
-  size_t u0 = 0;
-  while (u0 < outs.size()) {
+void launch_auto_sum(Context& c, const std::vector<AutoTerm>& terms, const std::vector<AutoOut>& outs_in, int nl) {
+  // long outputs in chunks, chunk r in round r (see launch_ks_inner_sum)
+  std::vector<std::vector<AutoOut>> rounds;
+  for (const AutoOut& o : outs_in)
+    for (int r = 0, done = 0; done < o.count || r == 0; ++r) {
+      AutoOut ch = o;
+      ch.first = o.first + done;
+      ch.count = std::min(AutoSumPack::kTerms, o.count - done);
+      ch.accum = r > 0;
+      if ((int)rounds.size() <= r) rounds.emplace_back();
+      rounds[r].push_back(ch);
+      done += ch.count;
+    }
+  for (const auto& outs : rounds)
+  for (size_t u0 = 0; u0 < outs.size();) {
     AutoSumPack pk;
     int nu = 0, nt = 0;
     while (u0 + nu < outs.size() && nu < AutoSumPack::kOuts) {
       const AutoOut& o = outs[u0 + nu];
-      if (o.count > AutoSumPack::kTerms) fail(COPSE_EINVAL, "internal: too many giant steps for one output");
       if (nt + o.count > AutoSumPack::kTerms) break;
       pk.o[nu] = o;
       pk.o[nu].first = nt;

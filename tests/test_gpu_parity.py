@@ -237,7 +237,7 @@ def _e2e(C, shape, seed, log_n, fold, enc, alpha=3, n_queries=None):
 
 
 def _e2e_text(C, text, n_features, precision, seed, log_n, fold, enc, alpha=3, n_queries=None, private=None,
-              server_rep=False):
+              server_rep=False, n1=(0, 0)):
     shape = synth.ForestShape(0, 0, 0.0, n_features, precision, 0)
     oc = OC.compile_forest(text, shape.n_features, shape.precision)
     names, _ = F.parse_forest(text)
@@ -258,12 +258,13 @@ def _e2e_text(C, text, n_features, precision, seed, log_n, fold, enc, alpha=3, n
                                          privacy_seed=None if private is None else private[0],
                                          n_pad=0 if private is None else private[1])
     elif private is None:
-        comp, meta = C.forest_compile(text, shape.n_features, shape.precision, log_n, fold=fold)
+        comp, meta = C.forest_compile(text, shape.n_features, shape.precision, log_n, fold=fold, n1_R=n1[0],
+                                      n1_L=n1[1])
     else:
         comp, meta = C.forest_compile_private(text, shape.n_features, shape.precision, log_n, private[0],
                                               private[1], fold=fold)
         assert C.compiled_codebook(comp) == oc.codebook
-    pl = CI.make_plan(oc, sc.N, sc.L, fold=fold, encrypted_model=enc)
+    pl = CI.make_plan(oc, sc.N, sc.L, fold=fold, encrypted_model=enc, n1_R=n1[0], n1_L=n1[1])
     kseed = bytes([seed % 256]) * 32
     say("e2e", shape, "log_n", log_n, "fold", fold, "enc", enc)
     keys = ctx.keygen(kseed, C.compiled_rotations(meta))
@@ -316,6 +317,43 @@ def test_server_replication_bit_exact(C, fold, private):
     text = synth.gen_forest_text(shape, 63)
     _e2e_text(C, text, 4, 4, 63, 11, fold, False, server_rep=True,
               private=(b"\x3c" * 32, 4) if private else None)
+
+
+@pytest.mark.parametrize("fold,enc", [(False, False), (True, False), (False, True)])
+def test_end_to_end_fused_ring(C, fold, enc):
+    """N = 8192, the smallest ring on which the fused column passes run: relinearization merged with its
+    switch, switches by several primes and the giant steps' single ModDown merged with the product's
+    switch, against the oracle bit for bit (and the op-at-a-time path)."""
+    shape = synth.ForestShape(3, 4, 0.7, 3, 4, 3)
+    _e2e_text(C, synth.gen_forest_text(shape, 71), 3, 4, 71, 13, fold, enc, alpha=4, n_queries=8)
+
+
+def test_long_products_in_chunks(C):
+    """With one baby step per product the giant steps per output exceed what one launch of the per-output
+    sums takes (48 key switches, 64 automorphism terms): the chunked sums give the op-at-a-time path's bits,
+    and the labels of the plain forest."""
+    shape = synth.ForestShape(8, 5, 0.7, 4, 4, 3)
+    text = synth.gen_forest_text(shape, 72)
+    oc = OC.compile_forest(text, 4, 4)
+    assert oc.q > 64 and oc.b > 64
+    need = CI.seccomp_depth(4) + 2 + math.ceil(math.log2(oc.d))
+    ctx = C.Context(log_n=13, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=4,
+                    special_max=1 << 49)
+    comp, meta = C.forest_compile(text, 4, 4, 13, n1_R=1, n1_L=1)
+    kseed = b"\x48" * 32
+    say("long products: q", oc.q, "b", oc.b, "d", oc.d)
+    keys = ctx.keygen(kseed, C.compiled_rotations(meta))
+    evk = ctx.export_eval(keys)
+    model = ctx.model_encode(comp)
+    queries = synth.gen_queries(meta.queries_per_ct, 4, 4, 73)
+    qct = ctx.query_encrypt(keys, meta, queries, kseed, group=0)
+    res = ctx.evaluate(model, evk, qct)
+    ref = ctx.evaluate_plain(model, evk, qct)
+    ea, eb = ctx.export(res)[0], ctx.export(ref)[0]
+    assert all((a == b).all() for a, b in zip(ea["polys"], eb["polys"]))
+    _, trees = F.parse_forest(text)
+    bits = ctx.decrypt_labels(keys, meta, res, len(queries))
+    assert (bits == np.array([F.evaluate(trees, list(x)) for x in queries])).all()
 
 
 @pytest.mark.parametrize("name", ["depth4", "width677", "prec16"])
