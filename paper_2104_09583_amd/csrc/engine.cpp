@@ -242,7 +242,9 @@ static std::vector<SCt> b_down(Context& c, std::vector<SCt> v, const std::vector
 // ------------------------------------------------------------------ key switching (batched)
 // ModUp of every input (NTT form, `level`): coefficient form, base conversion per digit, transform of the
 // new rows; out [I][D][nE][N] (the digits' own limbs are not copied: readers take them from the input)
-static DBuf modup_batch(Context& c, int level, const std::vector<const double*>& inputs) {
+// row_pass false (fused path only): the new rows are left after the column stages, for a consumer that
+// runs the forward row pass itself (launch_ks_inner_rows)
+static DBuf modup_batch(Context& c, int level, const std::vector<const double*>& inputs, bool row_pass = true) {
   const size_t N = c.N;
   const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
   const int I = (int)inputs.size();
@@ -273,6 +275,7 @@ static DBuf modup_batch(Context& c, int level, const std::vector<const double*>&
                    dg.d_mat, I, (size_t)nl * N, (size_t)D * nE * N);
     }
   }
+  if (fused && !row_pass) return ext;
   {
     std::string key = "ksntt:" + std::to_string(level) + ":" + std::to_string(I);
     auto it = c.row_tables.find(key);
@@ -316,7 +319,10 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   const bool fused = bridge_supported(c, c.alpha);
   if (merge && !(fused && add_mode == 1 && level >= 1 && T.mm_ok))
     fail(COPSE_EINVAL, "internal: merged switch not available here");
-  DBuf ext = modup_batch(c, level, inputs);
+  // relinearizations (no automorphism) fold the ModUp's forward row pass into the inner products
+  bool no_auto = fused;
+  for (const KsReq& rq : reqs) no_auto = no_auto && rq.g == 1;
+  DBuf ext = modup_batch(c, level, inputs, !no_auto);
   // inner products
   DBuf acc(&c, (size_t)R * 2 * nE * N);
   std::vector<KsJob2> jobs;
@@ -325,7 +331,8 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
     jobs.push_back(KsJob2{inputs[rq.input], ext.get() + (size_t)rq.input * D * nE * N, rq.key->b.get(),
                           rq.key->a.get(), acc.get() + (size_t)q * 2 * nE * N, rq.g, merge ? rq.add : nullptr});
   }
-  launch_ks_inner2(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
+  if (no_auto) launch_ks_inner_rows(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
+  else launch_ks_inner2(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
   if (merge) {
     // ModDown by P and switch by q_l in one pass: the top data row (now y_l + P a_l) joins the special rows
     // in the inverse transform, the fused column pass lifts the switched top limb, and the finish writes

@@ -1828,6 +1828,82 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
   }
 }
 
+// Relinearization inner products (no automorphism) with the ModUp's forward row pass folded in: block
+// (tile, extended row o, job) transforms the tile of row o of every digit that targets o (the bridge left
+// them after the column stages; a digit's own limbs come from the input in NTT form) and accumulates
+// digit x key in registers, so the extended rows are never written in NTT form.
+__global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha,
+                                                            int logN, int S1, size_t key_ds, const DevPrime* P,
+                                                            double ptop) {
+  __shared__ double sh[kLdsTile4];
+  const size_t N = (size_t)1 << logN;
+  const int o = blockIdx.y;
+  const KsJob2 jb = jobs.j[blockIdx.z];
+  const int prime = o < nl ? o : L + 1 + (o - nl);
+  const DevPrime pr = P[prime];
+  const size_t t0 = (size_t)blockIdx.x * 4096;
+  const int t = threadIdx.x;
+  const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
+  double a0[8], a1[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
+  for (int j = 0; j < D; ++j) {   // uniform per workgroup
+    double x[8];
+    if (j == own) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = gload(jb.in + (size_t)o * N + t0 + t + 512 * k);
+    } else {
+      row4_fwd_tile(jb.ext + ((size_t)j * nE + o) * N + t0, t0, S1, pr, sh, x);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = reduce_sym(x[k], pr.q, pr.qinv);
+    }
+    const size_t ko = (size_t)j * key_ds + (size_t)prime * N + t0 + t;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a0[k] += mul_lazy(x[k], gload(jb.kb + ko + 512 * k), pr.q, pr.qinv);
+      a1[k] += mul_lazy(x[k], gload(jb.ka + ko + 512 * k), pr.q, pr.qinv);
+    }
+  }
+  const bool top = jb.top != nullptr && o == nl - 1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const size_t c = t0 + t + 512 * k;
+    double v0 = a0[k], v1 = a1[k];
+    if (top) {
+      v0 += mul_lazy(gload(jb.top + (size_t)o * N + c), ptop, pr.q, pr.qinv);
+      v1 += mul_lazy(gload(jb.top + ((size_t)nl + o) * N + c), ptop, pr.q, pr.qinv);
+    }
+    jb.acc[(size_t)o * N + c] = canon(reduce_sym(v0, pr.q, pr.qinv), pr.q);
+    jb.acc[((size_t)nE + o) * N + c] = canon(reduce_sym(v1, pr.q, pr.qinv), pr.q);
+  }
+}
+
+void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
+                          double ptop) {
+  if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
+  if (D > 8) fail(COPSE_EINVAL, "internal: too many digits for the fused inner product");
+  for (size_t first = 0; first < jobs.size(); first += KsPack::kMax) {
+    const int cnt = (int)std::min<size_t>(KsPack::kMax, jobs.size() - first);
+    KsPack pk;
+    for (int k = 0; k < cnt; ++k) {
+      pk.j[k] = jobs[first + k];
+      if (pk.j[k].g != 1) fail(COPSE_EINVAL, "internal: the fused inner product takes no automorphism");
+    }
+    hipEvent_t ev;
+    prof_begin(c, 4, &ev);
+    hipLaunchKernelGGL(ks_inner_rows_kernel, dim3((unsigned)(c.N / 4096), nE, cnt), dim3(512), 0, c.stream, pk, D, nE,
+                       level + 1, c.L, c.alpha, (int)c.log_n, (int)c.log_n - 12, key_ds, c.d_primes, ptop);
+    COPSE_HIP(hipGetLastError());
+    int keys = 0;
+    for (int k = 0; k < cnt; ++k) {
+      bool seen = false;
+      for (int k2 = 0; k2 < k; ++k2) seen |= pk.j[k2].kb == pk.j[k].kb;
+      keys += !seen;
+    }
+    prof_end(c, 4, ev, ((D + 2.0) * cnt + 2.0 * D * keys) * nE * (double)c.N * 8.0);
+  }
+}
+
 // Per-output sums of key-switch inner products (see launch_ks_inner_sum).  grid: x over coefficients,
 // y over extended rows, z over the outputs of the pack; each thread runs through its output's jobs.
 struct KsSumPack {
