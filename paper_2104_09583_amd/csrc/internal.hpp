@@ -356,8 +356,6 @@ struct KsPack {
   KsJob2 j[kMax];
 };
 void launch_gather(Context& c, double* dst, const std::vector<const double*>& src, int rows);
-void launch_ew_multi(Context& c, int op, const std::vector<double*>& out, const std::vector<const double*>& a,
-                     const std::vector<const double*>& b, int nl, int rows_per_job, int b_rows);
 void launch_ptlayer(Context& c, const std::vector<double*>& out, const std::vector<const double*>& a,
                     const std::vector<const double*>& mul, const std::vector<const double*>& add, int nl);
 void launch_tensor_multi(Context& c, const std::vector<double*>& d, const std::vector<const double*>& a,
@@ -417,8 +415,6 @@ void launch_mm_inner(Context& c, double* out, const double* baby, const double* 
 // out_j = sum of terms[j * T .. j * T + T - 1] (canonical, exact)
 void launch_sum_terms(Context& c, const std::vector<double*>& out, const std::vector<const double*>& terms, int T,
                       int nl, int rows_per_job);
-void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
-                      const double* first, size_t first_stride_b, int nl, int rows, int G);
 void launch_seccomp_combine(Context& c, const std::vector<double*>& eq, const std::vector<double*>& lt,
                             const std::vector<const double*>& u, const std::vector<const double*>& xs,
                             const std::vector<const double*>& ts, int nl);

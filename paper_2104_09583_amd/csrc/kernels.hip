@@ -1640,44 +1640,6 @@ void launch_gather(Context& c, double* dst, const std::vector<const double*>& sr
   COPSE_HIP(hipGetLastError());
 }
 
-// out_j = a_j (op) b_j over rows_per_job rows (row r has prime r % nl); b row = r % b_rows
-__global__ void ew_multi_kernel(MPack out, Pack a, Pack b, int op, int nl, int b_rows, const DevPrime* P,
-                                int logN) {
-  const size_t N = (size_t)1 << logN;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int r = blockIdx.y, j = blockIdx.z;
-  const DevPrime& pr = P[r % nl];
-  const double x = a.p[j][(size_t)r * N + i];
-  const double y = b.p[j][(size_t)(r % b_rows) * N + i];
-  double v;
-  switch (op) {
-    case 0: v = mod_add(x, y, pr.q); break;
-    case 1: v = mod_sub(x, y, pr.q); break;
-    default: v = mod_mul(x, y, pr.q, pr.qinv); break;
-  }
-  out.p[j][(size_t)r * N + i] = v;
-}
-
-void launch_ew_multi(Context& c, int op, const std::vector<double*>& out, const std::vector<const double*>& a,
-                     const std::vector<const double*>& b, int nl, int rows_per_job, int b_rows) {
-  for (size_t first = 0; first < out.size(); first += kPack) {
-    int cnt = (int)std::min<size_t>(kPack, out.size() - first);
-    MPack po;
-    Pack pa, pb;
-    for (int k = 0; k < cnt; ++k) {
-      po.p[k] = out[first + k];
-      pa.p[k] = a[first + k];
-      pb.p[k] = b[first + k];
-    }
-    hipEvent_t ev;
-    prof_begin(c, 6, &ev);
-    hipLaunchKernelGGL(ew_multi_kernel, dim3((unsigned)((c.N + 255) / 256), rows_per_job, cnt), dim3(256), 0,
-                       c.stream, po, pa, pb, op, nl, b_rows, c.d_primes, (int)c.log_n);
-    COPSE_HIP(hipGetLastError());
-    prof_end(c, 6, ev, 3.0 * rows_per_job * cnt * (double)c.N * 8.0);
-  }
-}
 
 // plaintext layer: out_j = (a0 * m_j + p_j, a1 * m_j)  (2 polys, nl limbs)
 __global__ void ptlayer_kernel(MPack out, Pack a, Pack mul, Pack add, int nl, const DevPrime* P, int logN) {
@@ -2272,29 +2234,6 @@ void launch_mm_inner(Context& c, double* out, const double* baby, const double* 
                          (double)c.N * 8.0);
 }
 
-// out_b = sum_{p < nparts} parts[p * stride_p + b * stride_b]  over rows (row r has prime r % nl);
-// when first is given, part 0 of batch element b is read from first + b * first_stride_b instead
-__global__ void sum_parts_kernel(double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
-                                 const double* first, size_t first_stride_b, int nl, int rows, const DevPrime* P,
-                                 int logN) {
-  const size_t N = (size_t)1 << logN;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int r = blockIdx.y, b = blockIdx.z;
-  const DevPrime& pr = P[r % nl];
-  const size_t o = (size_t)r * N + i;
-  double acc = first ? first[(size_t)b * first_stride_b + o] : parts[(size_t)b * stride_b + o];
-  for (int p = 1; p < nparts; ++p) acc = mod_add(acc, parts[(size_t)p * stride_p + (size_t)b * stride_b + o], pr.q);
-  out[(size_t)b * rows * N + o] = acc;
-}
-
-void launch_sum_parts(Context& c, double* out, const double* parts, int nparts, size_t stride_p, size_t stride_b,
-                      const double* first, size_t first_stride_b, int nl, int rows, int G) {
-  if (nparts <= 0) fail(COPSE_EINVAL, "internal: empty sum");
-  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((c.N + 255) / 256), rows, G), dim3(256), 0, c.stream, out,
-                     parts, nparts, stride_p, stride_b, first, first_stride_b, nl, rows, c.d_primes, (int)c.log_n);
-  COPSE_HIP(hipGetLastError());
-}
 
 // out_j = sum_{t < T} terms[j T + t] over rows_per_job rows (row r has prime r % nl)
 __global__ void sum_terms_kernel(MPack out, Pack terms, int T, int nl, const DevPrime* P, int logN) {
