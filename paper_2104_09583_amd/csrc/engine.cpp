@@ -206,6 +206,40 @@ static std::vector<SCt> b_switch_by(Context& c, const std::vector<const Ct*>& in
   return out;
 }
 
+// the plaintext layer out_j = (x_j * mul_j + add_j on polynomial 0, x_j * mul_j on polynomial 1) at level l,
+// switched to l - 1, without writing the layer: the switch's inverse row pass and finish compute it
+static std::vector<SCt> b_ptlayer_switch(Context& c, const std::vector<const double*>& x,
+                                         const std::vector<const double*>& mul, const std::vector<const double*>& add,
+                                         int l) {
+  const size_t N = c.N;
+  const int J = (int)x.size(), np = 2;
+  KSTables& T = c.kstab(l);
+  auto outs = alloc_batch(c, J, l - 1, np);
+  DBuf top(&c, (size_t)J * np * N);
+  DBuf w(&c, (size_t)J * np * l * N);
+  std::vector<double*> po;
+  std::vector<const double*> pw, tabs;
+  std::vector<int> lv(J, l);
+  for (int j = 0; j < J; ++j) {
+    po.push_back(outs[j]->data());
+    pw.push_back(w.get() + (size_t)j * np * l * N);
+    tabs.push_back(T.d_ms);
+  }
+  std::vector<int2> ir{make_int2(0, l)}, orr;
+  for (int i = 0; i < l; ++i) orr.push_back(make_int2(i, i));
+  BridgeDesc d{rows_cached(c, "msout:" + std::to_string(l), orr), rows_cached(c, "msin:" + std::to_string(l), ir),
+               T.d_ms + 1, nullptr, l, 1, 0, 0};
+  d.in = top.get();
+  d.out = w.get();
+  d.in_bs = N;
+  d.out_bs = (size_t)l * N;
+  d.nz = J * np;
+  launch_ntt_inv_rows_gather(c, top.get(), x, np, 0, 0, -4, &lv, &mul, &add);
+  launch_bridge_set(c, 1, nullptr, nullptr, {d}, 0, 0, 0);
+  launch_ntt_fwd_rows_ms_finish(c, po, x, pw, lv, tabs, np, &add, 0, &mul);
+  return outs;
+}
+
 // switch each ciphertext down to its target level (several primes per step where the fused passes run)
 static std::vector<SCt> b_down(Context& c, std::vector<SCt> v, const std::vector<int>& target) {
   if (bridge_supported(c, 4)) {
@@ -319,8 +353,10 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   const bool fused = bridge_supported(c, c.alpha);
   if (merge && !(fused && add_mode == 1 && level >= 1 && T.mm_ok))
     fail(COPSE_EINVAL, "internal: merged switch not available here");
-  // relinearizations (no automorphism) fold the ModUp's forward row pass into the inner products
-  bool no_auto = fused;
+  // small batches of relinearizations (no automorphism) fold the ModUp's forward row pass into the inner
+  // products (one launch fewer; the fused kernel holds a whole tile per thread group, so large batches
+  // keep the two kernels, which run at higher occupancy)
+  bool no_auto = fused && R <= KsPack::kMax;
   for (const KsReq& rq : reqs) no_auto = no_auto && rq.g == 1;
   DBuf ext = modup_batch(c, level, inputs, !no_auto);
   // inner products
@@ -744,25 +780,28 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
   if (!M.encrypted) {
     const int L = M.top_level, nl = L + 1;
     const int J = (2 * p - 1) * G;
-    auto raw = alloc_batch(c, J, L, 2);
-    std::vector<double*> out;
     std::vector<const double*> a, mul, add;
-    int z = 0;
-    std::vector<std::pair<int, int>> where;   // (k, is_eq)
     for (int kb = 0; kb < p; ++kb)
       for (int e = (kb >= 1 ? 1 : 0); e >= 0; --e)
         for (int b = 0; b < G; ++b) {
-          out.push_back(raw[z++]->data());
           a.push_back(planes_in[b][kb]->data());
           mul.push_back(e ? M.E[kb].pt->buf.get() : M.G[kb].pt->buf.get());
           add.push_back(e ? M.C[kb].pt->buf.get() : M.TH[kb].pt->buf.get());
-          where.push_back({kb, e});
         }
-    launch_ptlayer(c, out, a, mul, add, nl);
-    std::vector<const Ct*> rin;
-    for (auto& x : raw) rin.push_back(x.get());
-    auto sw = b_modswitch(c, rin);
-    z = 0;
+    std::vector<SCt> sw;
+    if (bridge_supported(c, 1) && L >= 1) {
+      // the layer is computed inside its switch
+      sw = b_ptlayer_switch(c, a, mul, add, L);
+    } else {
+      auto raw = alloc_batch(c, J, L, 2);
+      std::vector<double*> out;
+      for (auto& x : raw) out.push_back(x->data());
+      launch_ptlayer(c, out, a, mul, add, nl);
+      std::vector<const Ct*> rin;
+      for (auto& x : raw) rin.push_back(x.get());
+      sw = b_modswitch(c, rin);
+    }
+    int z = 0;
     for (int kb = 0; kb < p; ++kb)
       for (int e = (kb >= 1 ? 1 : 0); e >= 0; --e)
         for (int b = 0; b < G; ++b) (e ? eq : lt)[kb][b] = sw[z++];

@@ -237,9 +237,12 @@ void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows);
 // inverse row pass reading row r of job j from src[j] + r * src_stride + src_off (r < rpj), writing the
 // jobs' rows contiguously to dst; prime r, or prime_fixed when >= 0; prime_fixed -2: row r is the top
 // limb (levels[j]) of polynomial r of job j
+// prime_fixed -4: as -2 for the plaintext layer src * mulp (+ addp on polynomial 0)
 void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const double*>& src, int rpj,
                                 size_t src_stride, size_t src_off, int prime_fixed,
-                                const std::vector<int>* levels = nullptr);
+                                const std::vector<int>* levels = nullptr,
+                                const std::vector<const double*>* mulp = nullptr,
+                                const std::vector<const double*>* addp = nullptr);
 // forward row pass of the ModDown rows w fused with the ModDown finish (as launch_md_finish2)
 void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& add,
                                    const std::vector<uint64_t>& gal, const double* acc, const double* w, int nE,
@@ -253,10 +256,13 @@ void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out
                                      const std::vector<const double*>* masks = nullptr, int mask_np = 0);
 // forward row pass of the modulus-switch rows fused with the switch's finish; job j switches from
 // levels[j], its rows w[j] = [np][levels[j]][N], its table tabs[j] (as launch_ms_finish_multi)
+// mulp (optional): the switch of the plaintext layer in * mulp (+ add on polynomial 0): `add` then holds
+// the layer's addends and nothing is added after the switch
 void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
                                    const std::vector<const double*>& w, const std::vector<int>& levels,
                                    const std::vector<const double*>& tabs, int np,
-                                   const std::vector<const double*>* add, int add_np);
+                                   const std::vector<const double*>* add, int add_np,
+                                   const std::vector<const double*>* mulp = nullptr);
 // One coefficient map of the fused column pass: rows of the input block (index, prime), rows of the
 // output block, per-input multipliers and the [n_in][n_out] matrix (mode 0).  chunk0 / ochunk are set by
 // the launcher.  Several maps over the same input and output blocks (the digits of a ModUp) run as one

@@ -528,15 +528,16 @@ __device__ __forceinline__ void row4_fwd_tile(const double* __restrict__ src, si
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jA + 512 * k)];
 }
 
+// With vals given, the tile's values at t + 512 k are vals[k] instead of src[t + 512 k].
 __device__ __forceinline__ void row4_inv_tile(const double* __restrict__ src, size_t gb0, int S1, const DevPrime& pr,
-                                              double* sh, double x[8]) {
+                                              double* sh, double x[8], const double* vals = nullptr) {
   const int t = threadIdx.x;
   const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
   const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
   const Tw8 wd = tw8_load(pr.inv, gb0 + jD, 1, mD);
   const Tw8 wc = tw8_load(pr.inv, gb0 + jC, 8, mC);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = gload(src + jA + 512 * k);
+  for (int k = 0; k < 8; ++k) sh[lds_idx(jA + 512 * k)] = vals != nullptr ? vals[k] : gload(src + jA + 512 * k);
   lds_barrier();
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
@@ -598,12 +599,14 @@ __global__ __launch_bounds__(512) void ntt_rowreg4_kernel(double* __restrict__ b
 // dst + r * N; its prime is prime_fixed, or r % rpj when prime_fixed < 0.
 __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restrict__ dst, Pack src, IPack lv, int rpj,
                                                                size_t src_stride, size_t src_off, int prime_fixed,
-                                                               const DevPrime* __restrict__ P, int logN, int S1) {
+                                                               const DevPrime* __restrict__ P, int logN, int S1,
+                                                               Pack mulp, Pack addp) {
   __shared__ double sh[kLdsTile4];
   const int r = blockIdx.y;
   const int j = r / rpj, sub = r % rpj;
   const size_t N = (size_t)1 << logN;
   // prime_fixed -2: the top limb of job j's polynomial sub, job j at level lv[j];
+  // prime_fixed -4: as -2 for the plaintext layer src * mulp (+ addp on polynomial 0), computed here;
   // prime_fixed -3: limb top - m of polynomial sub / src_stride with m = sub % src_stride, where lv[j] =
   //                 top | k << 16 and only m < k is transformed (job j at level top drops k limbs)
   const int top = prime_fixed == -3 ? (lv.v[j] & 0xffff) : lv.v[j];
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
     prime = top - m;
     poly = sub / kmax;
   } else {
-    prime = prime_fixed == -2 ? top : prime_fixed >= 0 ? prime_fixed : sub;
+    prime = prime_fixed <= -2 ? top : prime_fixed >= 0 ? prime_fixed : sub;
     poly = sub;
   }
   const size_t stride = prime_fixed <= -2 ? (size_t)(top + 1) * N : src_stride;
@@ -623,7 +626,19 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
   const size_t t0 = (size_t)blockIdx.x * 4096;
   const double* a = src.p[j] + (size_t)poly * stride + off + t0;
   double x[8];
-  row4_inv_tile(a, t0, S1, pr, sh, x);
+  if (prime_fixed == -4) {
+    const int t = threadIdx.x;
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const size_t o2 = off + t0 + t + 512 * k;
+      v[k] = mod_mul(gload(a + t + 512 * k), gload(mulp.p[j] + o2), pr.q, pr.qinv);
+      if (poly == 0) v[k] = mod_add(v[k], gload(addp.p[j] + o2), pr.q);
+    }
+    row4_inv_tile(a, t0, S1, pr, sh, x, v);
+  } else {
+    row4_inv_tile(a, t0, S1, pr, sh, x);
+  }
   double* o = dst + (size_t)r * N + t0;
   const int t = threadIdx.x;
 #pragma unroll
@@ -636,6 +651,8 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
 //            + add_job[0][i] at the automorphism's source index when add_mode 2 and k = 0)
 //   kMode 2: block (tile, i, z = job * np + k) transforms w row z * l + i and writes
 //            out_job[k][i] = in_job[k][i] q_l^-1 - w t q_l^-1  (+ add_job[k][i] for k < add_np)
+//   kMode 4: as kMode 2 for the switch of a plaintext layer: in_job[k] stands for in_job[k] * mulp_job
+//            (+ add_job on k = 0), computed here (no post-switch add)
 //   kMode 3: as kMode 1 for a ModDown merged with the switch by q_l (l = nl output limbs, the addend
 //            add_job has l + 1 limbs): out_job[k][i] = acc[z][i] mul_i + add_job[k][i] amul_i - w tmul_i
 //            with mul = (P q_l)^-1, tmul = t q_l^-1, amul = q_l^-1
@@ -651,10 +668,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
                                                                const double* __restrict__ mul,
                                                                const double* __restrict__ tmul,
                                                                const DevPrime* __restrict__ P, int logN, int S1,
-                                                               const double* __restrict__ amul) {
+                                                               const double* __restrict__ amul, Pack mulp) {
   __shared__ double sh[kLdsTile4];
   const int i = blockIdx.y, z = blockIdx.z;
-  constexpr bool kMd = kMode != 2;   // ModDown layout (2 polys per job, accumulator rows)
+  constexpr bool kMd = kMode == 1 || kMode == 3;   // ModDown layout (2 polys per job, accumulator rows)
   const int j = kMd ? (z >> 1) : z / np, k = kMd ? (z & 1) : z % np;
   // kMode 2: job j writes nl = lv[j] & 0xffff limbs per poly from an input with lv[j] >> 16 limbs per poly
   // (nl + 1 when zero: a switch by one prime)
@@ -677,6 +694,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
   // the epilogue's main operand is loaded during the transform, so its latency overlaps it
   double yv[8];
   row4_fwd_tile(wrow + t0, t0, S1, pr, sh, x, yrow + t0, yv);
+  if (kMode == 4) {
+    // the plaintext layer's value of this limb (the input's limb i, the plaintexts' limb i)
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const size_t c = (size_t)i * N + t0 + t + 512 * kk;
+      yv[kk] = mod_mul(yv[kk], gload(mulp.p[j] + c), pr.q, pr.qinv);
+      if (k == 0) yv[kk] = mod_add(yv[kk], gload(add.p[j] + c), pr.q);
+    }
+  }
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) {
     const size_t c = t0 + t + 512 * kk;
@@ -1134,24 +1160,29 @@ void launch_ntt_fwd_rows(Context& c, double* base, const int2* rows, int nrows) 
 }
 
 void launch_ntt_inv_rows_gather(Context& c, double* dst, const std::vector<const double*>& src, int rpj,
-                                size_t src_stride, size_t src_off, int prime_fixed, const std::vector<int>* levels) {
+                                size_t src_stride, size_t src_off, int prime_fixed, const std::vector<int>* levels,
+                                const std::vector<const double*>* mulp, const std::vector<const double*>* addp) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
   if (prime_fixed <= -2 && (!levels || levels->size() != src.size())) fail(COPSE_EINVAL, "internal: levels");
   if (prime_fixed == -3 && (src_stride == 0 || rpj % (int)src_stride != 0)) fail(COPSE_EINVAL, "internal: limbs");
+  if (prime_fixed == -4 && (!mulp || !addp || mulp->size() != src.size() || addp->size() != src.size()))
+    fail(COPSE_EINVAL, "internal: plaintext layer operands");
   const int per = std::max(1, std::min(kPack, kMaxGridY / std::max(1, rpj)));
   for (size_t first = 0; first < src.size(); first += per) {
     const int cnt = (int)std::min<size_t>(per, src.size() - first);
-    Pack pk;
+    Pack pk, pm{}, pa{};
     IPack lv{};
     for (int k = 0; k < cnt; ++k) {
       pk.p[k] = src[first + k];
       lv.v[k] = levels ? (*levels)[first + k] : 0;
+      if (mulp) pm.p[k] = (*mulp)[first + k];
+      if (addp) pa.p[k] = (*addp)[first + k];
     }
     hipEvent_t ev;
     prof_begin(c, 10, &ev);
     hipLaunchKernelGGL(ntt_rowinv_gather_kernel, dim3((unsigned)(c.N / 4096), cnt * rpj), dim3(512), 0, c.stream,
                        dst + first * rpj * c.N, pk, lv, rpj, src_stride, src_off, prime_fixed, c.d_primes, (int)c.log_n,
-                       (int)c.log_n - 12);
+                       (int)c.log_n - 12, pm, pa);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 10, ev, 2.0 * cnt * rpj * (double)c.N * 8.0);
   }
@@ -1179,7 +1210,7 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<1>, dim3((unsigned)(c.N / 4096), nl, 2 * cnt), dim3(512), 0,
                        c.stream, po, pin, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
                        w + first * 2 * nl * c.N, nE, nl, 2, add_mode, 0, pinv, tpinv, c.d_primes, (int)c.log_n,
-                       (int)c.log_n - 12, nullptr);
+                       (int)c.log_n - 12, nullptr, none);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 7, ev, (6.0 + (add_mode == 1 ? 2.0 : add_mode == 2 ? 1.0 : 0.0)) * nl * cnt * (double)c.N * 8.0);
   }
@@ -1208,7 +1239,7 @@ void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<3>, dim3((unsigned)(c.N / 4096), l, 2 * cnt), dim3(512), 0,
                        c.stream, po, pm, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
                        w + first * 2 * l * c.N, nE, l, 2, 0, masks ? mask_np : 0, m1, m2, c.d_primes,
-                       (int)c.log_n, (int)c.log_n - 12, m3);
+                       (int)c.log_n, (int)c.log_n - 12, m3, none);
     COPSE_HIP(hipGetLastError());
     // per output row: the bridge's row, the accumulator and addend rows read, the output written (+ mask)
     prof_end(c, 7, ev, (4.0 * 2 + (masks ? mask_np : 0)) * l * cnt * (double)c.N * 8.0);
@@ -1218,13 +1249,14 @@ void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out
 void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, const std::vector<const double*>& in,
                                    const std::vector<const double*>& w, const std::vector<int>& levels,
                                    const std::vector<const double*>& tabs, int np,
-                                   const std::vector<const double*>* add, int add_np) {
+                                   const std::vector<const double*>* add, int add_np,
+                                   const std::vector<const double*>* mulp) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
   const int per = std::max(1, std::min(kPack, kMaxGridY / np));
   for (size_t first = 0; first < out.size(); first += per) {
     const int cnt = (int)std::min<size_t>(per, out.size() - first);
     MPack po;
-    Pack pi, pa, pw, pt;
+    Pack pi, pa, pw, pt, pm{};
     GPack pg;
     IPack lv{};
     int lmax = 0;
@@ -1233,6 +1265,7 @@ void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, 
       po.p[k] = out[first + k];
       pi.p[k] = in[first + k];
       pa.p[k] = add ? (*add)[first + k] : nullptr;
+      if (mulp) pm.p[k] = (*mulp)[first + k];
       pw.p[k] = w[first + k];
       pt.p[k] = tabs[first + k];
       pg.g[k] = 1;
@@ -1243,9 +1276,14 @@ void launch_ntt_fwd_rows_ms_finish(Context& c, const std::vector<double*>& out, 
     }
     hipEvent_t ev;
     prof_begin(c, 8, &ev);
-    hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<2>, dim3((unsigned)(c.N / 4096), lmax, np * cnt), dim3(512), 0,
-                       c.stream, po, pi, pa, pg, pw, pt, lv, nullptr, nullptr, 0, 0, np, 0, add ? add_np : 0,
-                       nullptr, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12, nullptr);
+    if (mulp)   // the plaintext layer (`add` holds its addends, no post-switch add)
+      hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<4>, dim3((unsigned)(c.N / 4096), lmax, np * cnt), dim3(512), 0,
+                         c.stream, po, pi, pa, pg, pw, pt, lv, nullptr, nullptr, 0, 0, np, 0, 0, nullptr, nullptr,
+                         c.d_primes, (int)c.log_n, (int)c.log_n - 12, nullptr, pm);
+    else
+      hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<2>, dim3((unsigned)(c.N / 4096), lmax, np * cnt), dim3(512), 0,
+                         c.stream, po, pi, pa, pg, pw, pt, lv, nullptr, nullptr, 0, 0, np, 0, add ? add_np : 0,
+                         nullptr, nullptr, c.d_primes, (int)c.log_n, (int)c.log_n - 12, nullptr, pm);
     COPSE_HIP(hipGetLastError());
     prof_end(c, 8, ev, bytes);
   }
