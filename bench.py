@@ -56,7 +56,7 @@ STAGE_NAMES = ("comparison", "reshuffle", "levels", "aggregation")
 # ModDown finishes, alone and merged with the switch)
 KIND_KERNELS = {0: "ntt_rowreg4_kernel<false>", 2: "ntt_rowreg4_kernel<true>", 4: "ks_inner",
                 5: "ntt_bridge_kernel", 7: "ntt_rowfwd_finish_kernel<[13]>", 8: "ntt_rowfwd_finish_kernel<2>",
-                9: "mm_inner_kernel", 10: "ntt_rowinv_gather_kernel"}
+                9: "mm_inner", 10: "ntt_rowinv_gather_kernel"}
 
 
 def measured_traffic(kind: str, workload: str):

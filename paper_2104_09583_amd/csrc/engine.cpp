@@ -356,7 +356,7 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   // small batches of relinearizations (no automorphism) fold the ModUp's forward row pass into the inner
   // products (one launch fewer; the fused kernel holds a whole tile per thread group, so large batches
   // keep the two kernels, which run at higher occupancy)
-  bool no_auto = fused && R <= KsPack::kMax;
+  bool no_auto = fused && R <= KsPack::kRowsMax;
   for (const KsReq& rq : reqs) no_auto = no_auto && rq.g == 1;
   DBuf ext = modup_batch(c, level, inputs, !no_auto);
   // inner products

@@ -358,7 +358,8 @@ struct KsJob2 {
   const double* top = nullptr;
 };
 struct KsPack {
-  static constexpr int kMax = 16;
+  static constexpr int kMax = 32;   // 32 x 56 B of kernel arguments
+  static constexpr int kRowsMax = 16;   // batches the fused-row inner product takes (see ks_batch)
   KsJob2 j[kMax];
 };
 void launch_gather(Context& c, double* dst, const std::vector<const double*>& src, int rows);

@@ -2104,40 +2104,55 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
 //   encrypted model:  out[s][b]     = sum_u tensor(baby[u][b], diag(u, s))       (3 polys)
 // One thread owns one coefficient of one limb of one batch element and keeps the sums of GM giant
 // groups in registers, so each baby-step value is read once per launch (per group chunk) instead of
-// once per term.  A workgroup is 64 coefficients (one per lane) x 4 batch elements (one per wave), so the
-// four waves read the same diagonal values back to back (L1 hits), and the workgroups of one coefficient
-// tile are placed on one XCD back to back so that the other batch elements find them in its L2.  Per baby
-// step the GM diagonal loads are issued together (a zero diagonal loads the baby value again, which is in
-// cache, and its product is skipped by a uniform branch).
-// Sums are lazy (|term| < 0.91 q) and folded back with reduce_sym every kRed baby steps.
-// kSplit (one batch element): the four waves of a workgroup take every fourth baby step of the same
-// coefficients and add their partial sums through LDS at the end, so each wave's chain of dependent
-// loads is a quarter as long.
-// grid: x = (N / 64) x ceil(G / 4) (XCD-aware), y = limbs, z = giant-group chunks of GM.
+// once per term.  Baby steps with no term in the chunk are skipped (uniform); zero diagonals' products
+// are skipped by uniform branches.  The workgroups of one coefficient tile (all batch chunks and all
+// giant-group chunks) run back to back on one XCD, so a baby-step tile is fetched from HBM once and the
+// other chunks find it in that XCD's L2.  Sums are lazy (|term| < 0.91 q) and folded back with
+// reduce_sym every kRed baby steps.
+// grid: x = (N / 64) x giant-group chunks of GM x ceil(G / 4) (XCD-aware, the batch chunk fastest), y = limbs.
 constexpr int kMmLanes = 64, kMmWaves = 4;
-template <int GM, bool kEnc, bool kSplit>
+
+struct MmPlace {
+  size_t i;    // coefficient
+  int b;       // batch element of this wave (may be >= G)
+  int s0, gm;  // the chunk's first giant group and its group count
+};
+template <int GM>
+__device__ __forceinline__ MmPlace mm_place(int ng, int G, int wv) {
+  // consecutive workgroups go to different XCDs: give each XCD a contiguous range of logical blocks
+  unsigned bx = blockIdx.x;
+  const unsigned nbx = gridDim.x;
+  if ((nbx & 7u) == 0) bx = (bx & 7u) * (nbx >> 3) + (bx >> 3);
+  const unsigned bchunks = (unsigned)(G + kMmWaves - 1) / kMmWaves;
+  const unsigned per_tile = bchunks * (unsigned)((ng + GM - 1) / GM);
+  const unsigned rem = bx % per_tile;
+  MmPlace m;
+  m.b = (int)(rem % bchunks) * kMmWaves + wv;
+  m.i = (size_t)(bx / per_tile) * kMmLanes + (threadIdx.x % kMmLanes);
+  m.s0 = (int)(rem / bchunks) * GM;
+  m.gm = min(GM, ng - m.s0);
+  return m;
+}
+
+// One batch element: the four waves of a workgroup take every fourth baby step of the same coefficients
+// (each wave's chain of dependent loads a quarter as long) and add their partial sums through LDS at the
+// end.  Per baby step the GM diagonal loads are issued together (a zero diagonal loads the baby value
+// again, which is in cache).
+template <int GM, bool kEnc>
 __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out, const double* __restrict__ baby,
-                                                       const double* const* __restrict__ tab, int n_u, int ng, int G,
-                                                       int nl, size_t baby_slot, size_t baby_b, const DevPrime* P,
-                                                       int logN, Pack b0, int u0) {
+                                                       const double* const* __restrict__ tab, int n_u, int ng,
+                                                       int nl, size_t baby_slot, const DevPrime* P, int logN,
+                                                       const double* b0, int u0) {
   constexpr int kNp = kEnc ? 3 : 2;
   constexpr int kRed = kEnc ? 3 : 7;
   const size_t N = (size_t)1 << logN;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kMmLanes));
-  // consecutive workgroups go to different XCDs: give each XCD a contiguous range of logical blocks so
-  // that the batch chunks of one coefficient tile run on one XCD together
-  unsigned bx = blockIdx.x;
-  const unsigned nbx = gridDim.x;
-  if ((nbx & 7u) == 0) bx = (bx & 7u) * (nbx >> 3) + (bx >> 3);
-  const unsigned bchunks = kSplit ? 1u : (unsigned)(G + kMmWaves - 1) / kMmWaves;
-  // the batch element is uniform per wave: keep it (and the baby pointers) in scalar registers
-  const int b = kSplit ? 0 : (int)(bx % bchunks) * kMmWaves + wv;
-  const size_t i = (size_t)(bx / bchunks) * kMmLanes + (threadIdx.x % kMmLanes);
+  const MmPlace m = mm_place<GM>(ng, 1, 0);
+  const size_t i = m.i;
   // N is a multiple of 64, so a workgroup is either wholly in range or wholly out (uniform exit)
-  if (i >= N || b >= G) return;
+  if (i >= N) return;
   const int l = blockIdx.y;
-  const int s0 = blockIdx.z * GM;
-  const int gm = min(GM, ng - s0);
+  const int s0 = m.s0, gm = m.gm;
   const DevPrime& pr = P[l];
   const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
   double acc[GM][kNp];
@@ -2146,7 +2161,7 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
 #pragma unroll
     for (int p = 0; p < kNp; ++p) acc[s][p] = 0.0;
   int cnt = 0;
-  for (int u = kSplit ? wv : 0; u < n_u; u += kSplit ? kMmWaves : 1) {
+  for (int u = wv; u < n_u; u += kMmWaves) {
     // tables carry kMmTabPad trailing entries, so all GM pointers of a row can be fetched together
     const double* const* row = tab + (size_t)u * ng + s0;
     const double* ptr[GM];
@@ -2158,8 +2173,8 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
       any |= ptr[s] != nullptr;
     }
     if (!any) continue;   // uniform: this baby step has no term in the chunk
-    // baby step u0 (the rotation by zero) is read from the unrotated inputs
-    const double* bp = u == u0 ? b0.p[b] : baby + (size_t)u * baby_slot + (size_t)b * baby_b;
+    // baby step u0 (the rotation by zero) is read from the unrotated input
+    const double* bp = u == u0 ? b0 : baby + (size_t)u * baby_slot;
     const double x0 = gload(bp + o), x1 = gload(bp + ps + o);
     double d0[GM], d1[GM];
 #pragma unroll
@@ -2189,33 +2204,166 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
         for (int p = 0; p < kNp; ++p) acc[s][p] = reduce_sym(acc[s][p], pr.q, pr.qinv);
     }
   }
-  if (kSplit) {
-    // four groups at a time: every wave leaves its folded partial sums in LDS, wave w completes group w
-    __shared__ double red[kMmWaves][kMmWaves][kNp][kMmLanes];
-    const int lane = threadIdx.x % kMmLanes;
+  // four groups at a time: every wave leaves its folded partial sums in LDS, wave w completes group w
+  __shared__ double red[kMmWaves][kMmWaves][kNp][kMmLanes];
+  const int lane = threadIdx.x % kMmLanes;
 #pragma unroll
-    for (int sb = 0; sb < GM; sb += kMmWaves) {
+  for (int sb = 0; sb < GM; sb += kMmWaves) {
 #pragma unroll
-      for (int q = 0; q < kMmWaves; ++q)
-        if (sb + q < GM)
+    for (int q = 0; q < kMmWaves; ++q)
+      if (sb + q < GM)
 #pragma unroll
-          for (int p = 0; p < kNp; ++p) red[wv][q][p][lane] = reduce_sym(acc[sb + q][p], pr.q, pr.qinv);
-      lds_barrier();
-      const int s = sb + wv;
-      if (s < gm) {
-        double* op = out + ((size_t)(s0 + s) * G + b) * kNp * ps;
+        for (int p = 0; p < kNp; ++p) red[wv][q][p][lane] = reduce_sym(acc[sb + q][p], pr.q, pr.qinv);
+    lds_barrier();
+    const int s = sb + wv;
+    if (s < gm) {
+      double* op = out + (size_t)(s0 + s) * kNp * ps;
 #pragma unroll
-        for (int p = 0; p < kNp; ++p) {
-          double v = 0.0;
+      for (int p = 0; p < kNp; ++p) {
+        double v = 0.0;
 #pragma unroll
-          for (int w2 = 0; w2 < kMmWaves; ++w2) v += red[w2][wv][p][lane];
-          op[(size_t)p * ps + o] = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
+        for (int w2 = 0; w2 < kMmWaves; ++w2) v += red[w2][wv][p][lane];
+        op[(size_t)p * ps + o] = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
+      }
+    }
+    lds_barrier();
+  }
+}
+
+// Several batch elements: a workgroup is 64 coefficients x 4 batch elements (one per wave).  The four
+// waves need the same diagonal values, so a baby step's diagonal tile (GM groups x 1 or 2 polys x 64
+// coefficients) is fetched once per workgroup, each wave loading every fourth group, and staged in LDS,
+// double-buffered: the next baby step's tile and baby values are in flight while the current step's
+// products run, and one barrier per baby step hands the tile over.  Which diagonals of a step are zero
+// is a scalar bitmask.  A wave past the end of the batch still loads its share of the tiles.
+template <int GM, bool kEnc>
+__global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict__ out,
+                                                             const double* __restrict__ baby,
+                                                             const double* const* __restrict__ tab, int n_u, int ng,
+                                                             int G, int nl, size_t baby_slot, size_t baby_b,
+                                                             const DevPrime* P, int logN, Pack b0, int u0) {
+  constexpr int kNp = kEnc ? 3 : 2, kNd = kEnc ? 2 : 1;
+  constexpr int kRed = kEnc ? 3 : 7;
+  constexpr int kPer = (GM + kMmWaves - 1) / kMmWaves;   // groups of a tile one wave loads
+  static_assert(GM <= 32, "one bit per group");
+  __shared__ double dl[2][GM][kNd][kMmLanes];
+  const size_t N = (size_t)1 << logN;
+  const int lane = threadIdx.x % kMmLanes;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kMmLanes));
+  const MmPlace m = mm_place<GM>(ng, G, wv);
+  const size_t i = m.i;
+  if (i >= N) return;   // the whole workgroup (N is a multiple of 64)
+  const int b = m.b;
+  const bool has_b = b < G;   // uniform per wave
+  const int l = blockIdx.y;
+  const int s0 = m.s0, gm = m.gm;
+  // the prime and the table entries as scalar loads: a vector load's wait inside the products would
+  // also wait for the next tile
+  const DevPrime pr = cload_prime(P + l);
+  const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
+  // the first baby step at or after u with a term in the chunk (n_u if none) and its bitmask of groups
+  auto scan = [&](int u, uint32_t& mask) -> int {
+    for (; u < n_u; ++u) {
+      const double* const* row = tab + (size_t)u * ng + s0;
+      // the whole row at once (the table's kMmTabPad trailing entries keep it in bounds), masked to gm
+      uint32_t mk = 0;
+#pragma unroll
+      for (int s = 0; s < GM; ++s) mk |= (cload(row + s) != nullptr ? 1u : 0u) << s;
+      mk &= gm >= 32 ? ~0u : (1u << gm) - 1u;
+      if (mk != 0) {
+        mask = mk;
+        return u;
+      }
+    }
+    mask = 0;
+    return n_u;
+  };
+  // this wave's share of baby step u's tile, and its batch element's baby values, into registers
+  double r[kPer][kNd];
+  double xn0 = 0.0, xn1 = 0.0;
+  auto issue = [&](int u) {
+    const double* const* row = tab + (size_t)u * ng + s0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int s = wv + kMmWaves * k;
+      const double* pv = cload(row + s);   // in bounds as above
+      const double* dp = s < gm ? pv : nullptr;   // uniform
+      if (dp != nullptr) {
+#pragma unroll
+        for (int p = 0; p < kNd; ++p) r[k][p] = gload(dp + p * ps + o);
+      } else {
+#pragma unroll
+        for (int p = 0; p < kNd; ++p) r[k][p] = 0.0;
+      }
+    }
+    // unconditional (a wave past the batch reads the last element), so that the loads are issued here,
+    // before the products; baby step u0 (the rotation by zero) is read from the unrotated inputs
+    const int bl = min(b, G - 1);
+    const double* bp = u == u0 ? b0.p[bl] : baby + (size_t)u * baby_slot + (size_t)bl * baby_b;
+    xn0 = gload(bp + o);
+    xn1 = gload(bp + ps + o);
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int s = wv + kMmWaves * k;
+      if (s < GM)
+#pragma unroll
+        for (int p = 0; p < kNd; ++p) dl[buf][s][p][lane] = r[k][p];
+    }
+  };
+  double acc[GM][kNp];
+#pragma unroll
+  for (int s = 0; s < GM; ++s)
+#pragma unroll
+    for (int p = 0; p < kNp; ++p) acc[s][p] = 0.0;
+  uint32_t mask;
+  int u = scan(0, mask);
+  if (u < n_u) {
+    issue(u);
+    stage(0);
+  }
+  lds_barrier();
+  double x0 = xn0, x1 = xn1;
+  int buf = 0, cnt = 0;
+  while (u < n_u) {   // uniform
+    uint32_t mask_n;
+    const int un = scan(u + 1, mask_n);
+    if (un < n_u) issue(un);   // in flight during this step's products
+    if (has_b) {
+#pragma unroll
+      for (int s = 0; s < GM; ++s) {
+        if ((mask >> s) & 1u) {
+          const double d0 = dl[buf][s][0][lane];
+          if (kEnc) {
+            const double d1 = dl[buf][s][kNd - 1][lane];
+            acc[s][0] += mul_lazy(x0, d0, pr.q, pr.qinv);
+            acc[s][1] += mul_lazy(x0, d1, pr.q, pr.qinv) + mul_lazy(x1, d0, pr.q, pr.qinv);
+            acc[s][kNp - 1] += mul_lazy(x1, d1, pr.q, pr.qinv);
+          } else {
+            acc[s][0] += mul_lazy(x0, d0, pr.q, pr.qinv);
+            acc[s][1] += mul_lazy(x1, d0, pr.q, pr.qinv);
+          }
         }
       }
-      lds_barrier();
+      if (++cnt == kRed) {
+        cnt = 0;
+#pragma unroll
+        for (int s = 0; s < GM; ++s)
+#pragma unroll
+          for (int p = 0; p < kNp; ++p) acc[s][p] = reduce_sym(acc[s][p], pr.q, pr.qinv);
+      }
     }
-    return;
+    if (un < n_u) stage(buf ^ 1);
+    // every wave is done with this step's tile and the next one is in place
+    lds_barrier();
+    buf ^= 1;
+    u = un;
+    mask = mask_n;
+    x0 = xn0;
+    x1 = xn1;
   }
+  if (!has_b) return;
 #pragma unroll
   for (int s = 0; s < GM; ++s) {
     if (s < gm) {
@@ -2231,13 +2379,14 @@ static void mm_inner_launch(Context& c, double* out, const double* baby, const d
                             int G, int nl, size_t baby_slot, size_t baby_b, const Pack& b0, int u0) {
   const unsigned tiles = (unsigned)((c.N + kMmLanes - 1) / kMmLanes);
   const unsigned bchunks = (unsigned)((G + kMmWaves - 1) / kMmWaves);
-  if (G == 1)
-    hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc, true>), dim3(tiles, nl, (ng + GM - 1) / GM), dim3(256), 0,
-                       c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0, u0);
-  else
-    hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc, false>), dim3(tiles * bchunks, nl, (ng + GM - 1) / GM), dim3(256),
-                       0, c.stream, out, baby, tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0,
-                       u0);
+  const unsigned nx = tiles * bchunks * (unsigned)((ng + GM - 1) / GM);
+  if (G == 1) {
+    hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc>), dim3(nx, nl), dim3(256), 0, c.stream, out, baby, tab, n_u, ng,
+                       nl, baby_slot, c.d_primes, (int)c.log_n, b0.p[0], u0);
+  } else {
+    hipLaunchKernelGGL((mm_inner_batch_kernel<GM, kEnc>), dim3(nx, nl), dim3(256), 0, c.stream, out, baby, tab, n_u,
+                       ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0, u0);
+  }
 }
 
 void launch_mm_inner(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng, int G,
@@ -2247,7 +2396,9 @@ void launch_mm_inner(Context& c, double* out, const double* baby, const double* 
   if (u0 >= 0 && (!b0 || (int)b0->size() != G || G > kPack)) fail(COPSE_EINVAL, "internal: unrotated baby inputs");
   Pack p0{};
   for (int b = 0; u0 >= 0 && b < G; ++b) p0.p[b] = (*b0)[b];
-  if ((size_t)((c.N + kMmLanes - 1) / kMmLanes) * (size_t)((G + kMmWaves - 1) / kMmWaves) > 0x7fffffffu)
+  // one grid row holds every (tile, giant-group chunk, batch chunk); chunks of at least 4 groups
+  if ((size_t)((c.N + kMmLanes - 1) / kMmLanes) * (size_t)((G + kMmWaves - 1) / kMmWaves) *
+          (size_t)((ng + 3) / 4) * 256 > 0xffffffffu)
     fail(COPSE_EINVAL, "MatMul batch too large");
   hipEvent_t ev;
   prof_begin(c, 9, &ev);
