@@ -2333,7 +2333,9 @@ __global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict_
     if (has_b) {
 #pragma unroll
       for (int s = 0; s < GM; ++s) {
-        if ((mask >> s) & 1u) {
+        // an encrypted model's diagonals are all present: no branches, so the tile's LDS reads run ahead of
+        // the products (a slot without a diagonal holds 0.0 and adds exactly zero)
+        if (kEnc || ((mask >> s) & 1u)) {
           const double d0 = dl[buf][s][0][lane];
           if (kEnc) {
             const double d1 = dl[buf][s][kNd - 1][lane];
