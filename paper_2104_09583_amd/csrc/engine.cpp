@@ -278,7 +278,10 @@ static std::vector<SCt> b_down(Context& c, std::vector<SCt> v, const std::vector
 // new rows; out [I][D][nE][N] (the digits' own limbs are not copied: readers take them from the input)
 // row_pass false (fused path only): the new rows are left after the column stages, for a consumer that
 // runs the forward row pass itself (launch_ks_inner_rows)
-static DBuf modup_batch(Context& c, int level, const std::vector<const double*>& inputs, bool row_pass = true) {
+// inputs_b (optional): input i is the product inputs[i] (.) inputs_b[i] (a product's third polynomial,
+// not written)
+static DBuf modup_batch(Context& c, int level, const std::vector<const double*>& inputs, bool row_pass = true,
+                        const std::vector<const double*>* inputs_b = nullptr) {
   const size_t N = c.N;
   const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
   const int I = (int)inputs.size();
@@ -286,11 +289,12 @@ static DBuf modup_batch(Context& c, int level, const std::vector<const double*>&
   DBuf cf(&c, (size_t)I * nl * N);
   DBuf ext(&c, (size_t)I * D * nE * N);
   const bool fused = bridge_supported(c, c.alpha);
+  if (inputs_b && !fused) fail(COPSE_EINVAL, "internal: product inputs need the fused column pass");
   if (!fused) launch_gather(c, cf.get(), inputs, nl);
   if (fused) {
     // inverse row pass read straight from the inputs, then per digit the fused column passes with the
     // base conversion, then the forward row pass of every new row
-    launch_ntt_inv_rows_gather(c, cf.get(), inputs, nl, N, 0, -1);
+    launch_ntt_inv_rows_gather(c, cf.get(), inputs, nl, N, 0, -1, nullptr, inputs_b);
     // all digits in one launch (up to four per launch)
     std::vector<BridgeDesc> ds;
     for (int j = 0; j < D; ++j) {
@@ -338,12 +342,15 @@ struct KsReq {
   uint64_t g;
   double* out;          // 2 polys at the level
   const double* add;    // mode 1: (d0, d1) to add; mode 2: c0 to permute and add
+  const double* add_b = nullptr;   // merged mode 1 only: (d0, d1) is the product of the ciphertexts add and add_b
 };
 
 // merge (add_mode 1 only): the ModDown also switches to level - 1, as a relinearization followed by a
 // modulus switch would; each request's out then holds 2 polys of `level` limbs
+// inputs_b (merge only): a product's relinearization with its tensor not written: input i is
+// inputs[i] (.) inputs_b[i] (a1 b1), and each request's addend is the product of add and add_b
 static void ks_batch(Context& c, int level, const std::vector<const double*>& inputs, const std::vector<KsReq>& reqs,
-                     int add_mode, bool merge = false) {
+                     int add_mode, bool merge = false, const std::vector<const double*>* inputs_b = nullptr) {
   if (reqs.empty()) return;
   const size_t N = c.N;
   const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
@@ -353,19 +360,22 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   const bool fused = bridge_supported(c, c.alpha);
   if (merge && !(fused && add_mode == 1 && level >= 1 && T.mm_ok))
     fail(COPSE_EINVAL, "internal: merged switch not available here");
+  if (inputs_b && (!merge || inputs_b->size() != inputs.size()))
+    fail(COPSE_EINVAL, "internal: product inputs only for the merged relinearization");
   // small batches of relinearizations (no automorphism) fold the ModUp's forward row pass into the inner
   // products (one launch fewer; the fused kernel holds a whole tile per thread group, so large batches
   // keep the two kernels, which run at higher occupancy)
   bool no_auto = fused && R <= KsPack::kRowsMax;
   for (const KsReq& rq : reqs) no_auto = no_auto && rq.g == 1;
-  DBuf ext = modup_batch(c, level, inputs, !no_auto);
+  DBuf ext = modup_batch(c, level, inputs, !no_auto, inputs_b);
   // inner products
   DBuf acc(&c, (size_t)R * 2 * nE * N);
   std::vector<KsJob2> jobs;
   for (int q = 0; q < R; ++q) {
     const KsReq& rq = reqs[q];
     jobs.push_back(KsJob2{inputs[rq.input], ext.get() + (size_t)rq.input * D * nE * N, rq.key->b.get(),
-                          rq.key->a.get(), acc.get() + (size_t)q * 2 * nE * N, rq.g, merge ? rq.add : nullptr});
+                          rq.key->a.get(), acc.get() + (size_t)q * 2 * nE * N, rq.g, merge ? rq.add : nullptr,
+                          inputs_b ? (*inputs_b)[rq.input] : nullptr, inputs_b ? rq.add_b : nullptr});
   }
   if (no_auto) launch_ks_inner_rows(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
   else launch_ks_inner2(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
@@ -392,12 +402,14 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
                   rows_cached(c, "mdmsin:" + std::to_string(level), inr), c.alpha + 1, T.d_mm_mult, T.d_mm_mat,
                   2 * R, (size_t)nE * N, (size_t)l * N);
     std::vector<double*> outs;
-    std::vector<const double*> adds;
+    std::vector<const double*> adds, adds_b;
     for (auto& rq : reqs) {
       outs.push_back(rq.out);
       adds.push_back(rq.add);
+      adds_b.push_back(rq.add_b);
     }
-    launch_ntt_fwd_rows_mdms_finish(c, outs, adds, acc.get(), w.get(), nE, l, T.d_mm_m1, T.d_mm_m2, T.d_mm_m3);
+    launch_ntt_fwd_rows_mdms_finish(c, outs, adds, acc.get(), w.get(), nE, l, T.d_mm_m1, T.d_mm_m2, T.d_mm_m3,
+                                    nullptr, 0, inputs_b ? &adds_b : nullptr);
     return;
   }
   // ModDown of all accumulators
@@ -444,16 +456,15 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   launch_md_finish2(c, outs, adds, gal, acc.get(), zh.get(), nE, nl, T.d_md_pinv, T.d_md_tpinv, add_mode);
 }
 
-// relinearize 3-component ciphertexts (any mix of levels); with switch_down, each result is also switched
-// to one level lower, bit-identical to b_modswitch of the relinearized ciphertext
-static std::vector<SCt> b_relin(Context& c, const Keys& k, const std::vector<const Ct*>& in3, bool switch_down = false) {
+// relinearize 3-component ciphertexts (any mix of levels)
+static std::vector<SCt> b_relin(Context& c, const Keys& k, const std::vector<const Ct*>& in3) {
   if (!k.relin) fail(COPSE_EKEY, "relinearization key absent");
   std::vector<SCt> out(in3.size());
   std::map<int, std::vector<size_t>> groups;
   for (size_t i = 0; i < in3.size(); ++i) groups[in3[i]->level].push_back(i);
   for (auto& kv : groups) {
     const int l = kv.first;
-    auto outs = alloc_batch(c, (int)kv.second.size(), switch_down ? l - 1 : l, 2);
+    auto outs = alloc_batch(c, (int)kv.second.size(), l, 2);
     std::vector<const double*> inputs;
     std::vector<KsReq> reqs;
     for (size_t q = 0; q < kv.second.size(); ++q) {
@@ -462,7 +473,7 @@ static std::vector<SCt> b_relin(Context& c, const Keys& k, const std::vector<con
       reqs.push_back(KsReq{(int)q, k.relin.get(), 1, outs[q]->data(), x->data()});
       out[kv.second[q]] = outs[q];
     }
-    ks_batch(c, l, inputs, reqs, 1, switch_down);
+    ks_batch(c, l, inputs, reqs, 1);
   }
   return out;
 }
@@ -489,28 +500,43 @@ std::vector<SCt> b_mul(Context& c, const Keys& k, const std::vector<std::pair<SC
   for (size_t i = 0; i < pairs.size(); ++i) groups[tgt[2 * i]].push_back(i);
   for (auto& kv : groups) {
     const int l = kv.first;
-    auto t3 = alloc_batch(c, (int)kv.second.size(), l, 3);
-    std::vector<double*> d;
     std::vector<const double*> a, b;
     for (size_t q = 0; q < kv.second.size(); ++q) {
       size_t i = kv.second[q];
       if (ops[2 * i]->npolys != 2 || ops[2 * i + 1]->npolys != 2) fail(COPSE_EINVAL, "product of non-linear ciphertexts");
-      d.push_back(t3[q]->data());
       a.push_back(ops[2 * i]->data());
       b.push_back(ops[2 * i + 1]->data());
     }
+    if (merged_switch_ok(c, l)) {
+      // relinearization and switch to l - 1 in one key switch, bit-identical to b_modswitch of the
+      // relinearized tensor; the tensor (a0 b0, a0 b1 + a1 b0, a1 b1) is never written: the ModUp's
+      // inverse row pass and the inner products form a1 b1 from the operands, the finish the other two
+      if (!k.relin) fail(COPSE_EKEY, "relinearization key absent");
+      auto outs = alloc_batch(c, (int)kv.second.size(), l - 1, 2);
+      const size_t ps = (size_t)(l + 1) * c.N;
+      std::vector<const double*> in1, in1b;
+      std::vector<KsReq> reqs;
+      for (size_t q = 0; q < kv.second.size(); ++q) {
+        in1.push_back(a[q] + ps);
+        in1b.push_back(b[q] + ps);
+        KsReq rq{(int)q, k.relin.get(), 1, outs[q]->data(), a[q]};
+        rq.add_b = b[q];
+        reqs.push_back(rq);
+        out[kv.second[q]] = outs[q];
+      }
+      ks_batch(c, l, in1, reqs, 1, true, &in1b);
+      continue;
+    }
+    auto t3 = alloc_batch(c, (int)kv.second.size(), l, 3);
+    std::vector<double*> d;
+    for (auto& x : t3) d.push_back(x->data());
     launch_tensor_multi(c, d, a, b, l + 1);
     std::vector<const Ct*> in3;
     for (auto& x : t3) in3.push_back(x.get());
-    std::vector<SCt> ms;
-    if (merged_switch_ok(c, l)) {
-      ms = b_relin(c, k, in3, true);
-    } else {
-      auto rel = b_relin(c, k, in3);
-      std::vector<const Ct*> rin;
-      for (auto& x : rel) rin.push_back(x.get());
-      ms = b_modswitch(c, rin);
-    }
+    auto rel = b_relin(c, k, in3);
+    std::vector<const Ct*> rin;
+    for (auto& x : rel) rin.push_back(x.get());
+    auto ms = b_modswitch(c, rin);
     for (size_t q = 0; q < kv.second.size(); ++q) out[kv.second[q]] = ms[q];
   }
   return out;

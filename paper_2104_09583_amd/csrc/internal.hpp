@@ -250,10 +250,12 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
 // forward row pass of the merged ModDown + switch rows w (l = level of the inputs, l output limbs) fused
 // with its finish: out_j[k][i] = acc[2j+k][i] m1_i + add_j[k][i] m3_i - w[2j+k][i] m2_i  (i < l)
 // masks (optional): masks[j] (l limbs per poly) is added to the first mask_np polys of out[j]
+// add_b (optional): add_j is the product of the ciphertexts add_j and add_b_j (l + 1 limbs each), computed here
 void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out,
                                      const std::vector<const double*>& add, const double* acc, const double* w,
                                      int nE, int l, const double* m1, const double* m2, const double* m3,
-                                     const std::vector<const double*>* masks = nullptr, int mask_np = 0);
+                                     const std::vector<const double*>* masks = nullptr, int mask_np = 0,
+                                     const std::vector<const double*>* add_b = nullptr);
 // forward row pass of the modulus-switch rows fused with the switch's finish; job j switches from
 // levels[j], its rows w[j] = [np][levels[j]][N], its table tabs[j] (as launch_ms_finish_multi)
 // mulp (optional): the switch of the plaintext layer in * mulp (+ add on polynomial 0): `add` then holds
@@ -356,9 +358,13 @@ struct KsJob2 {
   // optional (relinearization merged with the switch): the 2 polys of the addend (NTT form, nl limbs);
   // P times their top limb is added to the top data row of acc
   const double* top = nullptr;
+  // optional (a product's relinearization without its tensor written): in holds a1 and in_b b1, so the
+  // digit rows are a1 (.) b1; top holds a and top_b b, so the addend is (a0 b0, a0 b1 + a1 b0)
+  const double* in_b = nullptr;
+  const double* top_b = nullptr;
 };
 struct KsPack {
-  static constexpr int kMax = 32;   // 32 x 56 B of kernel arguments
+  static constexpr int kMax = 32;   // 32 x 72 B of kernel arguments
   static constexpr int kRowsMax = 16;   // batches the fused-row inner product takes (see ks_batch)
   KsJob2 j[kMax];
 };

@@ -636,6 +636,14 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
       if (poly == 0) v[k] = mod_add(v[k], gload(addp.p[j] + o2), pr.q);
     }
     row4_inv_tile(a, t0, S1, pr, sh, x, v);
+  } else if (mulp.p[j] != nullptr) {
+    // a product's third polynomial src (.) mulp, computed here (mulp in the layout of src)
+    const double* bs = mulp.p[j] + (size_t)poly * stride + off + t0;
+    const int t = threadIdx.x;
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = mod_mul(gload(a + t + 512 * k), gload(bs + t + 512 * k), pr.q, pr.qinv);
+    row4_inv_tile(a, t0, S1, pr, sh, x, v);
   } else {
     row4_inv_tile(a, t0, S1, pr, sh, x);
   }
@@ -708,7 +716,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void n
     const size_t c = t0 + t + 512 * kk;
     const double wv = reduce_sym(x[kk], pr.q, pr.qinv);
     double v = mul_lazy(yv[kk], m1, pr.q, pr.qinv) - mul_lazy(wv, m2, pr.q, pr.qinv);
-    if (kMode == 3) v += mul_lazy(add.p[j][((size_t)k * (nl + 1) + i) * N + c], m3, pr.q, pr.qinv);
+    if (kMode == 3) {
+      double av;
+      if (mulp.p[j] == nullptr) {
+        av = add.p[j][((size_t)k * (nl + 1) + i) * N + c];
+      } else {
+        // the addend is the product of the ciphertexts add and mulp: its polynomial k (uniform)
+        const size_t r0 = (size_t)i * N + c, r1 = ((size_t)(nl + 1) + i) * N + c;
+        const double a0 = add.p[j][r0], b0 = mulp.p[j][r0];
+        av = k == 0 ? mod_mul(a0, b0, pr.q, pr.qinv)
+                    : mod_add(mod_mul(a0, mulp.p[j][r1], pr.q, pr.qinv),
+                              mod_mul(add.p[j][r1], b0, pr.q, pr.qinv), pr.q);
+      }
+      v += mul_lazy(av, m3, pr.q, pr.qinv);
+    }
     v = canon(reduce_sym(v, pr.q, pr.qinv), pr.q);
     // kMode 3: an optional mask (the `in` pack, l limbs per poly) on the first add_np polys
     if (kMode == 3 && k < add_np && in.p[j] != nullptr) v = mod_add(v, in.p[j][orow + c], pr.q);
@@ -1219,19 +1240,22 @@ void launch_ntt_fwd_rows_md_finish(Context& c, const std::vector<double*>& out, 
 void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out,
                                      const std::vector<const double*>& add, const double* acc, const double* w,
                                      int nE, int l, const double* m1, const double* m2, const double* m3,
-                                     const std::vector<const double*>* masks, int mask_np) {
+                                     const std::vector<const double*>* masks, int mask_np,
+                                     const std::vector<const double*>* add_b) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
   if (l < 1) fail(COPSE_EINVAL, "internal: no switch below level 0");
+  if (add_b && add_b->size() != add.size()) fail(COPSE_EINVAL, "internal: product addends");
   for (size_t first = 0; first < out.size(); first += kPack) {
     const int cnt = (int)std::min<size_t>(kPack, out.size() - first);
     MPack po;
-    Pack pa, pm, none{};
+    Pack pa, pm, pb{}, none{};
     GPack pg;
     IPack nolv{};
     for (int k = 0; k < cnt; ++k) {
       po.p[k] = out[first + k];
       pa.p[k] = add[first + k];
       pm.p[k] = masks ? (*masks)[first + k] : nullptr;
+      if (add_b) pb.p[k] = (*add_b)[first + k];
       pg.g[k] = 1;
     }
     hipEvent_t ev;
@@ -1239,10 +1263,11 @@ void launch_ntt_fwd_rows_mdms_finish(Context& c, const std::vector<double*>& out
     hipLaunchKernelGGL(ntt_rowfwd_finish_kernel<3>, dim3((unsigned)(c.N / 4096), l, 2 * cnt), dim3(512), 0,
                        c.stream, po, pm, pa, pg, none, none, nolv, acc + first * 2 * nE * c.N,
                        w + first * 2 * l * c.N, nE, l, 2, 0, masks ? mask_np : 0, m1, m2, c.d_primes,
-                       (int)c.log_n, (int)c.log_n - 12, m3, none);
+                       (int)c.log_n, (int)c.log_n - 12, m3, pb);
     COPSE_HIP(hipGetLastError());
-    // per output row: the bridge's row, the accumulator and addend rows read, the output written (+ mask)
-    prof_end(c, 7, ev, (4.0 * 2 + (masks ? mask_np : 0)) * l * cnt * (double)c.N * 8.0);
+    // per output row: the bridge's row, the accumulator and addend rows read (a product's addend: its two
+    // ciphertexts' rows, 2 for poly 0 and 4 for poly 1), the output written (+ mask)
+    prof_end(c, 7, ev, ((add_b ? 3.0 * 2 + 6.0 : 4.0 * 2) + (masks ? mask_np : 0)) * l * cnt * (double)c.N * 8.0);
   }
 }
 
@@ -1778,7 +1803,15 @@ void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const s
   }
 }
 
-// key-switch inner product over jobs; digit rows come straight from the job's input poly
+// (t0, t1) <- polynomials 0 and 1 of the product of ciphertexts (t0, t1) and (b0, b1) at one coefficient
+__device__ __forceinline__ void ks_tensor_top(double& t0, double& t1, double b0, double b1, const DevPrime& pr) {
+  const double a0 = t0;
+  t0 = mod_mul(a0, b0, pr.q, pr.qinv);
+  t1 = mod_add(mod_mul(a0, b1, pr.q, pr.qinv), mod_mul(t1, b0, pr.q, pr.qinv), pr.q);
+}
+
+// key-switch inner product over jobs; digit rows come straight from the job's input poly (a product's
+// third polynomial in (.) in_b when in_b is set)
 __global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha, int logN, size_t key_ds,
                                  const DevPrime* P, double ptop) {
   const size_t N = (size_t)1 << logN;
@@ -1793,14 +1826,22 @@ __global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int 
   // lazy sums: each product is in (-0.91 q, 0.91 q); D <= 8 digits stay far below 2^52
   double a0 = 0.0, a1 = 0.0;
   for (int j = 0; j < D; ++j) {
-    const double e = (j == own) ? jb.in[(size_t)o * N + src] : jb.ext[((size_t)j * nE + o) * N + src];
+    double e;
+    if (j == own) {
+      e = jb.in[(size_t)o * N + src];
+      if (jb.in_b != nullptr) e = mod_mul(e, jb.in_b[(size_t)o * N + src], pr.q, pr.qinv);
+    } else {
+      e = jb.ext[((size_t)j * nE + o) * N + src];
+    }
     const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
     a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
     a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
   }
   if (jb.top != nullptr && o == nl - 1) {   // uniform per workgroup
-    a0 += mul_lazy(jb.top[(size_t)o * N + i], ptop, pr.q, pr.qinv);
-    a1 += mul_lazy(jb.top[((size_t)nl + o) * N + i], ptop, pr.q, pr.qinv);
+    double t0 = jb.top[(size_t)o * N + i], t1 = jb.top[((size_t)nl + o) * N + i];
+    if (jb.top_b != nullptr) ks_tensor_top(t0, t1, jb.top_b[(size_t)o * N + i], jb.top_b[((size_t)nl + o) * N + i], pr);
+    a0 += mul_lazy(t0, ptop, pr.q, pr.qinv);
+    a1 += mul_lazy(t1, ptop, pr.q, pr.qinv);
   }
   jb.acc[(size_t)o * N + i] = canon(reduce_sym(a0, pr.q, pr.qinv), pr.q);
   jb.acc[((size_t)nE + o) * N + i] = canon(reduce_sym(a1, pr.q, pr.qinv), pr.q);
@@ -1848,33 +1889,66 @@ __global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, 
 #pragma unroll
   for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
   for (int j = 0; j < D; ++j) {   // uniform per workgroup
+    // the digit's key values first: their loads are in flight while the tile is transformed
+    const size_t ko = (size_t)j * key_ds + (size_t)prime * N + t0 + t;
+    double kb[8], ka[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      kb[k] = gload(jb.kb + ko + 512 * k);
+      ka[k] = gload(jb.ka + ko + 512 * k);
+    }
     double x[8];
     if (j == own) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) x[k] = gload(jb.in + (size_t)o * N + t0 + t + 512 * k);
+      if (jb.in_b != nullptr) {
+        double xb[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xb[k] = gload(jb.in_b + (size_t)o * N + t0 + t + 512 * k);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = mod_mul(x[k], xb[k], pr.q, pr.qinv);
+      }
     } else {
       row4_fwd_tile(jb.ext + ((size_t)j * nE + o) * N + t0, t0, S1, pr, sh, x);
 #pragma unroll
       for (int k = 0; k < 8; ++k) x[k] = reduce_sym(x[k], pr.q, pr.qinv);
     }
-    const size_t ko = (size_t)j * key_ds + (size_t)prime * N + t0 + t;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      a0[k] += mul_lazy(x[k], gload(jb.kb + ko + 512 * k), pr.q, pr.qinv);
-      a1[k] += mul_lazy(x[k], gload(jb.ka + ko + 512 * k), pr.q, pr.qinv);
+      a0[k] += mul_lazy(x[k], kb[k], pr.q, pr.qinv);
+      a1[k] += mul_lazy(x[k], ka[k], pr.q, pr.qinv);
     }
   }
-  const bool top = jb.top != nullptr && o == nl - 1;
+  if (jb.top != nullptr && o == nl - 1) {   // uniform: the addend's top limb, all loads issued together
+    double u0[8], u1[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const size_t c = t0 + t + 512 * k;
+      u0[k] = gload(jb.top + (size_t)o * N + c);
+      u1[k] = gload(jb.top + ((size_t)nl + o) * N + c);
+    }
+    if (jb.top_b != nullptr) {
+      double b0[8], b1[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const size_t c = t0 + t + 512 * k;
+        b0[k] = gload(jb.top_b + (size_t)o * N + c);
+        b1[k] = gload(jb.top_b + ((size_t)nl + o) * N + c);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ks_tensor_top(u0[k], u1[k], b0[k], b1[k], pr);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a0[k] += mul_lazy(u0[k], ptop, pr.q, pr.qinv);
+      a1[k] += mul_lazy(u1[k], ptop, pr.q, pr.qinv);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const size_t c = t0 + t + 512 * k;
-    double v0 = a0[k], v1 = a1[k];
-    if (top) {
-      v0 += mul_lazy(gload(jb.top + (size_t)o * N + c), ptop, pr.q, pr.qinv);
-      v1 += mul_lazy(gload(jb.top + ((size_t)nl + o) * N + c), ptop, pr.q, pr.qinv);
-    }
-    jb.acc[(size_t)o * N + c] = canon(reduce_sym(v0, pr.q, pr.qinv), pr.q);
-    jb.acc[((size_t)nE + o) * N + c] = canon(reduce_sym(v1, pr.q, pr.qinv), pr.q);
+    jb.acc[(size_t)o * N + c] = canon(reduce_sym(a0[k], pr.q, pr.qinv), pr.q);
+    jb.acc[((size_t)nE + o) * N + c] = canon(reduce_sym(a1[k], pr.q, pr.qinv), pr.q);
   }
 }
 
