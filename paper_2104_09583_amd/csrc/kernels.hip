@@ -1812,7 +1812,8 @@ __device__ __forceinline__ void ks_tensor_top(double& t0, double& t1, double b0,
 
 // key-switch inner product over jobs; digit rows come straight from the job's input poly (a product's
 // third polynomial in (.) in_b when in_b is set)
-__global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha, int logN, size_t key_ds,
+template <int kD>
+__global__ void ks_inner2_kernel(KsPack jobs, int D_, int nE, int nl, int L, int alpha, int logN, size_t key_ds,
                                  const DevPrime* P, double ptop) {
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1823,19 +1824,37 @@ __global__ void ks_inner2_kernel(KsPack jobs, int D, int nE, int nl, int L, int 
   const DevPrime& pr = P[prime];
   const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
   const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
+  // digit j's row: the input's own limb, else the ModUp output; a product's own limb is a1 (.) b1, b1's
+  // value (ob) loaded with the others and multiplied in after the loads
+  auto row = [&](int j) -> const double* { return j == own ? jb.in + (size_t)o * N : jb.ext + ((size_t)j * nE + o) * N; };
+  const bool prod = own >= 0 && jb.in_b != nullptr;   // uniform
+  const double ob = prod ? jb.in_b[(size_t)o * N + src] : 0.0;
   // lazy sums: each product is in (-0.91 q, 0.91 q); D <= 8 digits stay far below 2^52
   double a0 = 0.0, a1 = 0.0;
-  for (int j = 0; j < D; ++j) {
-    double e;
-    if (j == own) {
-      e = jb.in[(size_t)o * N + src];
-      if (jb.in_b != nullptr) e = mod_mul(e, jb.in_b[(size_t)o * N + src], pr.q, pr.qinv);
-    } else {
-      e = jb.ext[((size_t)j * nE + o) * N + src];
+  if (kD > 0) {
+    // a known digit count: every digit's loads are issued before the first product
+    double e[kD > 0 ? kD : 1], kb[kD > 0 ? kD : 1], ka[kD > 0 ? kD : 1];
+#pragma unroll
+    for (int j = 0; j < kD; ++j) {
+      const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
+      e[j] = row(j)[src];
+      kb[j] = jb.kb[ko];
+      ka[j] = jb.ka[ko];
     }
-    const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
-    a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
-    a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
+#pragma unroll
+    for (int j = 0; j < kD; ++j) {
+      const double ej = prod && j == own ? mod_mul(e[j], ob, pr.q, pr.qinv) : e[j];
+      a0 += mul_lazy(ej, kb[j], pr.q, pr.qinv);
+      a1 += mul_lazy(ej, ka[j], pr.q, pr.qinv);
+    }
+  } else {
+    for (int j = 0; j < D_; ++j) {
+      double e = row(j)[src];
+      if (prod && j == own) e = mod_mul(e, ob, pr.q, pr.qinv);
+      const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
+      a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
+      a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
+    }
   }
   if (jb.top != nullptr && o == nl - 1) {   // uniform per workgroup
     double t0 = jb.top[(size_t)o * N + i], t1 = jb.top[((size_t)nl + o) * N + i];
@@ -1855,8 +1874,18 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
     for (int k = 0; k < cnt; ++k) pk.j[k] = jobs[first + k];
     hipEvent_t ev;
     prof_begin(c, 4, &ev);
-    hipLaunchKernelGGL(ks_inner2_kernel, dim3((unsigned)((c.N + 255) / 256), nE, cnt), dim3(256), 0, c.stream, pk, D,
-                       nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes, ptop);
+    const dim3 grid((unsigned)((c.N + 255) / 256), nE, cnt);
+#define COPSE_KS2(KD)                                                                                          \
+  hipLaunchKernelGGL(ks_inner2_kernel<KD>, grid, dim3(256), 0, c.stream, pk, D, nE, level + 1, c.L, c.alpha, \
+                     (int)c.log_n, key_ds, c.d_primes, ptop)
+    switch (D) {
+      case 1: COPSE_KS2(1); break;
+      case 2: COPSE_KS2(2); break;
+      case 3: COPSE_KS2(3); break;
+      case 4: COPSE_KS2(4); break;
+      default: COPSE_KS2(0); break;
+    }
+#undef COPSE_KS2
     COPSE_HIP(hipGetLastError());
     // per job and extended row: D digit rows read and 2 rows written; each distinct key's 2 D rows once
     int keys = 0;
@@ -1985,8 +2014,12 @@ struct KsSumPack {
   KsSumJob j[kJobs];
   KsSumOut o[kOuts];
 };
+// kD > 0: the digit count, known at compile time, so the loads of kU jobs (all their digits) are issued
+// together (one thread's chain of dependent loads a kU-th as long); the other jobs one at a time.
+template <int kD>
 __global__ void ks_inner_sum_kernel(KsSumPack pk, int D, int nE, int nl, int L, int alpha, int logN,
                                     size_t key_ds, const DevPrime* P, double ptop) {
+  constexpr int kU = 4;
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -1995,17 +2028,50 @@ __global__ void ks_inner_sum_kernel(KsSumPack pk, int D, int nE, int nl, int L, 
   const int prime = o < nl ? o : L + 1 + (o - nl);
   const DevPrime& pr = P[prime];
   const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
+  auto row = [&](const KsSumJob& jb, int j) -> const double* {
+    return j == own ? jb.in + (size_t)o * N : jb.ext + ((size_t)j * nE + o) * N;
+  };
   double a0 = 0.0, a1 = 0.0;
-  for (int t = ou.first; t < ou.first + ou.count; ++t) {
+  int t = ou.first;
+  const int tend = ou.first + ou.count;
+  if (kD > 0) {
+    constexpr int kDd = kD > 0 ? kD : 1;
+    for (; t + kU <= tend; t += kU) {
+      double e[kU][kDd], kb[kU][kDd], ka[kU][kDd];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const KsSumJob jb = pk.j[t + u];
+        const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
+#pragma unroll
+        for (int j = 0; j < kDd; ++j) {
+          const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
+          e[u][j] = row(jb, j)[src];
+          kb[u][j] = jb.kb[ko];
+          ka[u][j] = jb.ka[ko];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+#pragma unroll
+        for (int j = 0; j < kDd; ++j) {
+          a0 += mul_lazy(e[u][j], kb[u][j], pr.q, pr.qinv);
+          a1 += mul_lazy(e[u][j], ka[u][j], pr.q, pr.qinv);
+        }
+        // D <= 8 lazy products per job: fold back after each job
+        a0 = reduce_sym(a0, pr.q, pr.qinv);
+        a1 = reduce_sym(a1, pr.q, pr.qinv);
+      }
+    }
+  }
+  for (; t < tend; ++t) {
     const KsSumJob jb = pk.j[t];
     const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
     for (int j = 0; j < D; ++j) {
-      const double e = (j == own) ? jb.in[(size_t)o * N + src] : jb.ext[((size_t)j * nE + o) * N + src];
+      const double e = row(jb, j)[src];
       const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
       a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
       a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
     }
-    // D <= 8 lazy products per job: fold back after each job
     a0 = reduce_sym(a0, pr.q, pr.qinv);
     a1 = reduce_sym(a1, pr.q, pr.qinv);
   }
@@ -2051,8 +2117,17 @@ void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const st
     }
     hipEvent_t ev;
     prof_begin(c, 4, &ev);
-    hipLaunchKernelGGL(ks_inner_sum_kernel, dim3((unsigned)((c.N + 255) / 256), nE, nu), dim3(256), 0, c.stream, pk,
-                       D, nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes, ptop);
+    const dim3 grid((unsigned)((c.N + 255) / 256), nE, nu);
+#define COPSE_KSS(KD)                                                                                            \
+  hipLaunchKernelGGL(ks_inner_sum_kernel<KD>, grid, dim3(256), 0, c.stream, pk, D, nE, level + 1, c.L, c.alpha, \
+                     (int)c.log_n, key_ds, c.d_primes, ptop)
+    switch (D) {
+      case 1: COPSE_KSS(1); break;
+      case 2: COPSE_KSS(2); break;
+      case 3: COPSE_KSS(3); break;
+      default: COPSE_KSS(0); break;
+    }
+#undef COPSE_KSS
     COPSE_HIP(hipGetLastError());
     // per job: D digit rows read; per output: 2 rows written; each distinct key's 2 D rows once
     int keys = 0;
