@@ -1866,6 +1866,18 @@ __global__ void ks_inner2_kernel(KsPack jobs, int D_, int nE, int nl, int L, int
   jb.acc[((size_t)nE + o) * N + i] = canon(reduce_sym(a1, pr.q, pr.qinv), pr.q);
 }
 
+// algorithmic bytes of one pack: per job and extended row D digit rows read and 2 rows written; each
+// distinct key's 2 D rows once; a product's own limbs read b1 too (nl rows); the addend's top limb 2 rows
+// (4 for a product's, formed from both operands)
+static double ks_pack_bytes(const Context& c, const KsPack& pk, int cnt, int D, int nE, int nl, int keys) {
+  double rows = (double)(D + 2) * cnt * nE + 2.0 * D * keys * nE;
+  for (int k = 0; k < cnt; ++k) {
+    if (pk.j[k].in_b != nullptr) rows += nl;
+    if (pk.j[k].top != nullptr) rows += pk.j[k].top_b != nullptr ? 4 : 2;
+  }
+  return rows * (double)c.N * 8.0;
+}
+
 void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
                       double ptop) {
   for (size_t first = 0; first < jobs.size(); first += KsPack::kMax) {
@@ -1887,14 +1899,13 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
     }
 #undef COPSE_KS2
     COPSE_HIP(hipGetLastError());
-    // per job and extended row: D digit rows read and 2 rows written; each distinct key's 2 D rows once
     int keys = 0;
     for (int k = 0; k < cnt; ++k) {
       bool seen = false;
       for (int k2 = 0; k2 < k; ++k2) seen |= pk.j[k2].kb == pk.j[k].kb;
       keys += !seen;
     }
-    prof_end(c, 4, ev, ((D + 2.0) * cnt + 2.0 * D * keys) * nE * (double)c.N * 8.0);
+    prof_end(c, 4, ev, ks_pack_bytes(c, pk, cnt, D, nE, level + 1, keys));
   }
 }
 
@@ -2003,7 +2014,7 @@ void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, in
       for (int k2 = 0; k2 < k; ++k2) seen |= pk.j[k2].kb == pk.j[k].kb;
       keys += !seen;
     }
-    prof_end(c, 4, ev, ((D + 2.0) * cnt + 2.0 * D * keys) * nE * (double)c.N * 8.0);
+    prof_end(c, 4, ev, ks_pack_bytes(c, pk, cnt, D, nE, level + 1, keys));
   }
 }
 
@@ -2129,14 +2140,17 @@ void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const st
     }
 #undef COPSE_KSS
     COPSE_HIP(hipGetLastError());
-    // per job: D digit rows read; per output: 2 rows written; each distinct key's 2 D rows once
+    // per job: D digit rows read; per output: 2 rows written and the addend's top limb (2 rows) read, or
+    // a later chunk's accumulator (2 rows); each distinct key's 2 D rows once
     int keys = 0;
     for (int t = 0; t < nj; ++t) {
       bool seen = false;
       for (int t2 = 0; t2 < t; ++t2) seen |= pk.j[t2].kb == pk.j[t].kb;
       keys += !seen;
     }
-    prof_end(c, 4, ev, ((double)D * nj + 2.0 * nu + 2.0 * D * keys) * nE * (double)c.N * 8.0);
+    double extra = 0.0;
+    for (int u = 0; u < nu; ++u) extra += pk.o[u].accum ? 2.0 * nE : 2.0;
+    prof_end(c, 4, ev, (((double)D * nj + 2.0 * nu + 2.0 * D * keys) * nE + extra) * (double)c.N * 8.0);
     u0 += nu;
   }
 }
