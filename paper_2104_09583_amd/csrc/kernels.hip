@@ -2021,7 +2021,8 @@ void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, in
 // Per-output sums of key-switch inner products (see launch_ks_inner_sum).  grid: x over coefficients,
 // y over extended rows, z over the outputs of the pack; each thread runs through its output's jobs.
 struct KsSumPack {
-  static constexpr int kJobs = 48, kOuts = 16;
+  // 80 x 40 + 16 x 32 bytes: within the 4 KiB of kernel arguments with the other parameters
+  static constexpr int kJobs = 80, kOuts = 16;
   KsSumJob j[kJobs];
   KsSumOut o[kOuts];
 };

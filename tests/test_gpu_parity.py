@@ -330,12 +330,12 @@ def test_end_to_end_fused_ring(C, fold, enc):
 
 def test_long_products_in_chunks(C):
     """With one baby step per product the giant steps per output exceed what one launch of the per-output
-    sums takes (48 key switches, 64 automorphism terms): the chunked sums give the op-at-a-time path's bits,
+    sums takes (80 key switches, 64 automorphism terms): the chunked sums give the op-at-a-time path's bits,
     and the labels of the plain forest."""
     shape = synth.ForestShape(8, 5, 0.7, 4, 4, 3)
     text = synth.gen_forest_text(shape, 72)
     oc = OC.compile_forest(text, 4, 4)
-    assert oc.q > 64 and oc.b > 64
+    assert oc.q > 81 and oc.b > 81
     need = CI.seccomp_depth(4) + 2 + math.ceil(math.log2(oc.d))
     ctx = C.Context(log_n=13, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=4,
                     special_max=1 << 49)
