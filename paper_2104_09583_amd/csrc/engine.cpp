@@ -377,7 +377,8 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
                           rq.key->a.get(), acc.get() + (size_t)q * 2 * nE * N, rq.g, merge ? rq.add : nullptr,
                           inputs_b ? (*inputs_b)[rq.input] : nullptr, inputs_b ? rq.add_b : nullptr});
   }
-  if (no_auto) launch_ks_inner_rows(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
+  // the fused inner product also runs the ModDown's inverse row pass on the rows that need it
+  if (no_auto) launch_ks_inner_rows(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0, merge ? nl - 1 : nl);
   else launch_ks_inner2(c, jobs, D, nE, level, (size_t)Lt * N, merge ? T.mm_ptop : 0.0);
   if (merge) {
     // ModDown by P and switch by q_l in one pass: the top data row (now y_l + P a_l) joins the special rows
@@ -392,7 +393,7 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
       }
       return h;
     }());
-    launch_ntt_inv_rows(c, acc.get(), r, 2 * R * (c.alpha + 1));
+    if (!no_auto) launch_ntt_inv_rows(c, acc.get(), r, 2 * R * (c.alpha + 1));
     std::vector<int2> inr, outr;
     for (int s2 = 0; s2 < c.alpha; ++s2) inr.push_back(make_int2(nl + s2, c.L + 1 + s2));
     inr.push_back(make_int2(l, l));
@@ -425,8 +426,13 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
         for (int s = 0; s < c.alpha; ++s) h.push_back(make_int2(k * nE + nl + s, c.L + 1 + s));
       r = c.rows(key, h);
     }
-    if (fused) launch_ntt_inv_rows(c, acc.get(), r, 2 * R * c.alpha);
-    else launch_ntt_inv(c, acc.get(), r, 2 * R * c.alpha);
+    if (no_auto) {
+      // done by the fused inner product
+    } else if (fused) {
+      launch_ntt_inv_rows(c, acc.get(), r, 2 * R * c.alpha);
+    } else {
+      launch_ntt_inv(c, acc.get(), r, 2 * R * c.alpha);
+    }
   }
   DBuf zh(&c, (size_t)2 * R * nl * N);
   std::vector<int2> inr, outr;

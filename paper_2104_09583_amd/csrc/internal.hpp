@@ -380,9 +380,10 @@ void launch_ms_finish_multi(Context& c, const std::vector<double*>& out, const s
 void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
                       double ptop = 0.0);
 // the same for jobs without automorphism (g = 1) whose ext holds the ModUp rows after the column stages
-// only: the forward row pass is done inside (relinearizations)
+// only: the forward row pass is done inside (relinearizations); extended rows inv_from.. nE - 1 of acc
+// are written after the inverse row pass (the rows the ModDown transforms back; nE: none)
 void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
-                          double ptop = 0.0);
+                          double ptop, int inv_from);
 // Key-switch inner products summed per output (giant steps of a product, one ModDown for their sum):
 // output u accumulates, over its jobs, sum_j digit_j(sigma_g(in)) key_j in the extended basis, plus
 // P times the top limb of its addend (2 polys, NTT form, nl limbs) on the top data row.

@@ -1915,7 +1915,7 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
 // digit x key in registers, so the extended rows are never written in NTT form.
 __global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha,
                                                             int logN, int S1, size_t key_ds, const DevPrime* P,
-                                                            double ptop) {
+                                                            double ptop, int inv_from) {
   __shared__ double sh[kLdsTile4];
   const size_t N = (size_t)1 << logN;
   const int o = blockIdx.y;
@@ -1986,14 +1986,31 @@ __global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, 
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
+    a0[k] = canon(reduce_sym(a0[k], pr.q, pr.qinv), pr.q);
+    a1[k] = canon(reduce_sym(a1[k], pr.q, pr.qinv), pr.q);
+  }
+  if (o >= inv_from) {
+    // rows the ModDown transforms back (the special rows, and the top data row of a ModDown merged with
+    // the switch): the inverse row pass of the tile here, as the separate row pass would run it
+    double x[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      lds_barrier();   // the tile buffer's previous use is over in every wave
+      row4_inv_tile(jb.acc + (size_t)o * N + t0, t0, S1, pr, sh, x, h == 0 ? a0 : a1);   // src unread
+#pragma unroll
+      for (int k = 0; k < 8; ++k) (h == 0 ? a0 : a1)[k] = reduce_sym(x[k], pr.q, pr.qinv);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
     const size_t c = t0 + t + 512 * k;
-    jb.acc[(size_t)o * N + c] = canon(reduce_sym(a0[k], pr.q, pr.qinv), pr.q);
-    jb.acc[((size_t)nE + o) * N + c] = canon(reduce_sym(a1[k], pr.q, pr.qinv), pr.q);
+    jb.acc[(size_t)o * N + c] = a0[k];
+    jb.acc[((size_t)nE + o) * N + c] = a1[k];
   }
 }
 
 void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
-                          double ptop) {
+                          double ptop, int inv_from) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
   if (D > 8) fail(COPSE_EINVAL, "internal: too many digits for the fused inner product");
   for (size_t first = 0; first < jobs.size(); first += KsPack::kMax) {
@@ -2006,7 +2023,8 @@ void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, in
     hipEvent_t ev;
     prof_begin(c, 4, &ev);
     hipLaunchKernelGGL(ks_inner_rows_kernel, dim3((unsigned)(c.N / 4096), nE, cnt), dim3(512), 0, c.stream, pk, D, nE,
-                       level + 1, c.L, c.alpha, (int)c.log_n, (int)c.log_n - 12, key_ds, c.d_primes, ptop);
+                       level + 1, c.L, c.alpha, (int)c.log_n, (int)c.log_n - 12, key_ds, c.d_primes, ptop,
+                       inv_from);
     COPSE_HIP(hipGetLastError());
     int keys = 0;
     for (int k = 0; k < cnt; ++k) {
