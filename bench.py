@@ -92,7 +92,7 @@ def cpu_baseline(w, text, queries, seed, budget_s: float = 25.0):
     sc = B.BGV(nt.make_chain(ch["log_n"], 65537, ch["n_data_primes"], ch["q0_max"], ch["data_max"],
                              ch["alpha"], ch["special_max"]))
     oc = OC.compile_forest(text, w.shape.n_features, w.shape.precision)
-    pl = CI.make_plan(oc, sc.N, sc.L, fold=w.fold)
+    pl = CI.make_plan(oc, sc.N, sc.L, fold=w.fold, n1_R=w.n1[0], n1_L=w.n1[1])
     log("cpu baseline: oracle keygen (untimed)")
     keys = sc.keygen(seed, rotations=pl.rotations())
     X = CI.encrypt_queries(sc, keys, pl, queries[:1], seed, 0)

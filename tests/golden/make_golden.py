@@ -39,7 +39,7 @@ def make(name: str, group: int = 0):
     sc = B.BGV(nt.make_chain(ch["log_n"], 65537, ch["n_data_primes"], ch["q0_max"], ch["data_max"], ch["alpha"],
                              ch["special_max"]))
     oc = OC.compile_forest(text, w.shape.n_features, w.shape.precision)
-    pl = CI.make_plan(oc, sc.N, sc.L, fold=w.fold, encrypted_model=w.encrypted_model)
+    pl = CI.make_plan(oc, sc.N, sc.L, fold=w.fold, encrypted_model=w.encrypted_model, n1_R=w.n1[0], n1_L=w.n1[1])
     t0 = time.time()
     keys = sc.keygen(seed, rotations=pl.rotations())
     nq = min(pl.layout.Qs, len(queries) - group * pl.layout.Qs)

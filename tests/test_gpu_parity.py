@@ -470,7 +470,8 @@ def test_workload_full_size_against_stored_oracle(C, name):
     text, queries, seed = synth.workload_inputs(w)
     say("full size", name)
     ctx = C.Context(**w.chain)
-    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold)
+    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
+                                  n1_R=w.n1[0], n1_L=w.n1[1])
     keys = ctx.keygen(seed, C.compiled_rotations(meta))
     model = ctx.model_encode(comp)
     nq = gold["n_queries"]
@@ -486,7 +487,7 @@ def test_workload_full_size_against_stored_oracle(C, name):
     assert h.hexdigest() == gold["sha256"]
     bits = ctx.decrypt_labels(keys, meta, res, nq)
     assert bits.tolist() == gold["labels"]
-    # the captured evaluation the benchmark times gives the same bits, replay after replay
+    # the captured evaluation gives the same bits, replay after replay
     ex = ctx.exec_create(model, ctx.export_eval(keys), 1)
     for rep in range(2):
         got = ctx.export(ex.run([qct])[0])[0]
