@@ -663,7 +663,8 @@ __global__ __launch_bounds__(512) void ntt_rowinv_gather_kernel(double* __restri
 //            (+ add_job on k = 0), computed here (no post-switch add)
 //   kMode 3: as kMode 1 for a ModDown merged with the switch by q_l (l = nl output limbs, the addend
 //            add_job has l + 1 limbs): out_job[k][i] = acc[z][i] mul_i + add_job[k][i] amul_i - w tmul_i
-//            with mul = (P q_l)^-1, tmul = t q_l^-1, amul = q_l^-1
+//            with mul = (P q_l)^-1, tmul = t q_l^-1, amul = q_l^-1; when mulp_job is set the addend is
+//            polynomial k of the product of the ciphertexts add_job and mulp_job, formed here
 // mul/tmul are P^-1 and t P^-1 per limb (kMode 1) or the modulus-switch table (q_l^-1 at 2 + 2 i,
 // t q_l^-1 at 3 + 2 i).  Outputs are canonical.
 // at most 80 VGPRs: three workgroups per CU, as for the plain row pass
@@ -1811,7 +1812,8 @@ __device__ __forceinline__ void ks_tensor_top(double& t0, double& t1, double b0,
 }
 
 // key-switch inner product over jobs; digit rows come straight from the job's input poly (a product's
-// third polynomial in (.) in_b when in_b is set)
+// third polynomial in (.) in_b when in_b is set).  kD > 0: the digit count, known at compile time, so every
+// digit's loads are issued before the first product (kD = 0: any count, one digit at a time).
 template <int kD>
 __global__ void ks_inner2_kernel(KsPack jobs, int D_, int nE, int nl, int L, int alpha, int logN, size_t key_ds,
                                  const DevPrime* P, double ptop) {
@@ -1911,8 +1913,9 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
 
 // Relinearization inner products (no automorphism) with the ModUp's forward row pass folded in: block
 // (tile, extended row o, job) transforms the tile of row o of every digit that targets o (the bridge left
-// them after the column stages; a digit's own limbs come from the input in NTT form) and accumulates
-// digit x key in registers, so the extended rows are never written in NTT form.
+// them after the column stages; a digit's own limbs come from the input in NTT form, a product's formed
+// from both operands) and accumulates digit x key in registers, so the extended rows are never written in
+// NTT form.  Rows o >= inv_from (the rows the ModDown transforms back) leave after the inverse row pass.
 __global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha,
                                                             int logN, int S1, size_t key_ds, const DevPrime* P,
                                                             double ptop, int inv_from) {
