@@ -362,10 +362,9 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
     fail(COPSE_EINVAL, "internal: merged switch not available here");
   if (inputs_b && (!merge || inputs_b->size() != inputs.size()))
     fail(COPSE_EINVAL, "internal: product inputs only for the merged relinearization");
-  // small batches of relinearizations (no automorphism) fold the ModUp's forward row pass into the inner
-  // products (one launch fewer; the fused kernel holds a whole tile per thread group, so large batches
-  // keep the two kernels, which run at higher occupancy)
-  bool no_auto = fused && R <= KsPack::kRowsMax;
+  // relinearizations (no automorphism) fold the ModUp's forward row pass and the ModDown's inverse row
+  // pass into the inner products (two launches fewer, the extended rows never written in NTT form)
+  bool no_auto = fused;
   for (const KsReq& rq : reqs) no_auto = no_auto && rq.g == 1;
   DBuf ext = modup_batch(c, level, inputs, !no_auto, inputs_b);
   // inner products

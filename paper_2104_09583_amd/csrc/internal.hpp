@@ -365,7 +365,6 @@ struct KsJob2 {
 };
 struct KsPack {
   static constexpr int kMax = 32;   // 32 x 72 B of kernel arguments
-  static constexpr int kRowsMax = 16;   // batches the fused-row inner product takes (see ks_batch)
   KsJob2 j[kMax];
 };
 void launch_gather(Context& c, double* dst, const std::vector<const double*>& src, int rows);
