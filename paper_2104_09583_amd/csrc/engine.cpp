@@ -354,7 +354,7 @@ static void ks_batch(Context& c, int level, const std::vector<const double*>& in
   if (reqs.empty()) return;
   const size_t N = c.N;
   const int nl = level + 1, nE = nl + c.alpha, D = c.n_digits(level);
-  const int I = (int)inputs.size(), R = (int)reqs.size();
+  const int R = (int)reqs.size();
   const int Lt = c.n_primes();
   KSTables& T = c.kstab(level);
   const bool fused = bridge_supported(c, c.alpha);
