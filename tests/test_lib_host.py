@@ -79,13 +79,15 @@ def test_encoder_matches_oracle(log_n):
     assert raw.min() >= -32768 and raw.max() <= 32768
 
 
-def _meta_vs_oracle(text, F, p, log_n, fold):
-    ch, meta = C.forest_compile(text, F, p, log_n, fold=fold)
+def _meta_vs_oracle(text, F, p, log_n, fold, n1=(0, 0)):
+    ch, meta = C.forest_compile(text, F, p, log_n, fold=fold, n1_R=n1[0], n1_L=n1[1])
     oc = OC.compile_forest(text, F, p)
     assert (meta.K, meta.q, meta.b, meta.m, meta.d) == (oc.K, oc.q, oc.b, oc.m, oc.d)
     assert meta.block_w == oc.W and meta.queries_per_ct == (1 << log_n) // oc.W
-    pl = CI.make_plan(oc, 1 << log_n, 40, fold=fold)
+    pl = CI.make_plan(oc, 1 << log_n, 40, fold=fold, n1_R=n1[0], n1_L=n1[1])
     assert (meta.n1_R, meta.n1_L) == (pl.n1_R, pl.n1_L)
+    for given, got in zip(n1, (meta.n1_R, meta.n1_L)):
+        assert given == 0 or got == given
     assert C.compiled_rotations(meta) == pl.rotations()
     depth = CI.seccomp_depth(p) + (1 if fold else 2) + (int(np.ceil(np.log2(oc.d))) if oc.d > 1 else 0)
     assert meta.depth == depth
@@ -97,6 +99,15 @@ def test_compiler_matches_oracle_on_workloads(name):
     text, _, _ = synth.workload_inputs(w)
     _meta_vs_oracle(text, w.shape.n_features, w.shape.precision, w.log_n, w.fold)
     _meta_vs_oracle(text, w.shape.n_features, w.shape.precision, w.log_n, not w.fold)
+
+
+@pytest.mark.parametrize("name", [k for k, w in synth.WORKLOADS.items() if w.n1 != (0, 0)])
+def test_workload_baby_steps_reach_both_sides(name):
+    """A workload's measured baby-step split (where it is not the compiler's rule) is what the library
+    compiles and what the oracle plans, so both evaluate the same schedule (the stored goldens rely on it)."""
+    w = synth.WORKLOADS[name]
+    text, _, _ = synth.workload_inputs(w)
+    _meta_vs_oracle(text, w.shape.n_features, w.shape.precision, w.log_n, w.fold, w.n1)
 
 
 @pytest.mark.parametrize("seed", range(6))
