@@ -2589,8 +2589,10 @@ void launch_mm_inner(Context& c, double* out, const double* baby, const double* 
     fail(COPSE_EINVAL, "MatMul batch too large");
   hipEvent_t ev;
   prof_begin(c, 9, &ev);
-  // giant groups in chunks of at most 24 (12 with three accumulators each), split evenly
-  const int cap = enc ? 12 : 24;   // at most 165 VGPRs: three waves per SIMD
+  // giant groups in chunks of at most 24 (12 with three accumulators each, or for one batch element, whose
+  // kernel holds a step's loads for every group: more, smaller chunks at higher occupancy measured faster),
+  // split evenly
+  const int cap = enc || G == 1 ? 12 : 24;
   const int chunks = (ng + cap - 1) / cap;
   const int per = (ng + chunks - 1) / chunks;
   auto run = [&](auto gm_tag) {
