@@ -39,7 +39,7 @@ import numpy as np
 
 from . import slotsim as S
 from .bgv import BGV, Ciphertext, Keys
-from .compiler import Compiled, bsgs_n1, extended_reshuffle
+from .compiler import Compiled, bsgs_n1, extended_reshuffle, generalized_diagonal
 
 OBJ_QUERY = 1
 OBJ_THRESH = 2
@@ -116,22 +116,53 @@ class PlainModel:
     C: List[np.ndarray]        # encode(1 - th)
     G: List[np.ndarray]        # encode(-th)
     TH: List[np.ndarray]       # encode(th)
-    rdiag: List[Optional[np.ndarray]]
-    ldiag: List[List[Optional[np.ndarray]]]
+    rdiag: "Diagonals"                  # [] when the reshuffle is folded
+    ldiag: List["Diagonals"]
     masks: List[np.ndarray]
-    rep: List[Optional[np.ndarray]] = field(default_factory=list)   # replication diagonals
+    rep: object = field(default_factory=list)   # replication diagonals (Diagonals) or []
 
 
 @dataclass
 class EncModel:
     TH: List[Ciphertext]
-    rdiag: List[Ciphertext]
-    ldiag: List[List[Ciphertext]]
+    rdiag: "Diagonals"
+    ldiag: List["Diagonals"]
     masks: List[Ciphertext]
 
 
-def _diag_slots(pl: Plan, A: np.ndarray, n1: int, t: int):
-    return S.prerotated_diagonals(A % t, pl.layout, n1)
+class Diagonals:
+    """The pre-rotated generalized diagonals of one MatMul matrix (Section 4.1, "Matrix
+    Multiplication"), each encoded or encrypted when it is read and then dropped.
+
+    Entry k is exactly what a list of every encoded (encrypted) diagonal would hold at k, so the
+    evaluation sees the same values; only no whole model is held at once (an encrypted model of the
+    64-tree, depth-8 shape is tens of GB).  A plaintext entry is None when the diagonal is all zero
+    (the product with it is skipped); an encrypted model hides its sparsity, so every entry is a
+    ciphertext."""
+
+    def __init__(self, A: np.ndarray, layout: S.Layout, n1: int, t: int, make, encrypted: bool):
+        self.A = A % t
+        self.layout, self.n1, self.make, self.encrypted = layout, n1, make, encrypted
+
+    def __len__(self) -> int:
+        return self.A.shape[1]
+
+    def present(self, k: int) -> bool:
+        return self.encrypted or bool(generalized_diagonal(self.A, k).any())
+
+    def slots(self, k: int) -> np.ndarray:
+        return S.prerotated_diagonal(self.A, self.layout, self.n1, k)
+
+    def __getitem__(self, k: int):
+        if not 0 <= k < len(self):
+            raise IndexError(k)
+        return self.make(k, self.slots(k)) if self.present(k) else None
+
+
+def _present(diags, k: int) -> bool:
+    if isinstance(diags, Diagonals):
+        return diags.present(k)
+    return diags[k] is not None
 
 
 def encode_model(sc: BGV, pl: Plan) -> PlainModel:
@@ -142,40 +173,40 @@ def encode_model(sc: BGV, pl: Plan) -> PlainModel:
     G = [sc.encode((-th) % t) for th in tp]
     TH = [sc.encode(th) for th in tp]
 
-    def enc_all(slots_list):
-        return [None if not s.any() else sc.encode(s) for s in slots_list]
+    def plain(A, n1):
+        return Diagonals(A, pl.layout, n1, t, lambda k, slots: sc.encode(slots), False)
     if pl.fold:
         rdiag = []
-        ldiag = [enc_all(_diag_slots(pl, c.Lfold[l] @ c.R, pl.n1_L, t)) for l in range(c.d)]
+        ldiag = [plain(c.Lfold[l] @ c.R, pl.n1_L) for l in range(c.d)]
     else:
-        rdiag = enc_all(_diag_slots(pl, extended_reshuffle(c), pl.n1_R, t))
-        ldiag = [enc_all(_diag_slots(pl, c.Lfold[l], pl.n1_L, t)) for l in range(c.d)]
+        rdiag = plain(extended_reshuffle(c), pl.n1_R)
+        ldiag = [plain(c.Lfold[l], pl.n1_L) for l in range(c.d)]
     masks = [sc.encode(pl.layout.replicate(mk)) for mk in c.masks]
     rep = []
     if pl.server_rep:
         from .compiler import replication_matrix
-        rep = enc_all(_diag_slots(pl, replication_matrix(c), pl.n1_F, t))
+        rep = plain(replication_matrix(c), pl.n1_F)
     return PlainModel(E, Cc, G, TH, rdiag, ldiag, masks, rep)
 
 
 def encrypt_model(sc: BGV, keys: Keys, pl: Plan, seed: bytes) -> EncModel:
     """Model owner encrypts thresholds, diagonals and masks under the data
-    owner's key, each at the level where the schedule consumes it."""
+    owner's key, each at the level where the schedule consumes it; diagonal i
+    of level l has object id (OBJ_LDIAG, l, i), of the reshuffle (OBJ_RDIAG, 0, i)."""
     c, t = pl.c, sc.t
     lv = pl.levels
     tp = S.threshold_planes(c, pl.layout)
     TH = [sc.encrypt_slots(keys, th, seed, obj_id(OBJ_THRESH, 0, k), pl.L) for k, th in enumerate(tp)]
+
+    def enc(A, n1, kind, a, level):
+        return Diagonals(A, pl.layout, n1, t,
+                         lambda k, slots: sc.encrypt_slots(keys, slots, seed, obj_id(kind, a, k), level), True)
     if pl.fold:
         rdiag = []
-        ld_slots = [_diag_slots(pl, c.Lfold[l] @ c.R, pl.n1_L, t) for l in range(c.d)]
-        ld_level = lv["dec"]
+        ldiag = [enc(c.Lfold[l] @ c.R, pl.n1_L, OBJ_LDIAG, l, lv["dec"]) for l in range(c.d)]
     else:
-        rs = _diag_slots(pl, extended_reshuffle(c), pl.n1_R, t)
-        rdiag = [sc.encrypt_slots(keys, s, seed, obj_id(OBJ_RDIAG, 0, i), lv["dec"]) for i, s in enumerate(rs)]
-        ld_slots = [_diag_slots(pl, c.Lfold[l], pl.n1_L, t) for l in range(c.d)]
-        ld_level = lv["branches"]
-    ldiag = [[sc.encrypt_slots(keys, s, seed, obj_id(OBJ_LDIAG, l, i), ld_level) for i, s in enumerate(ls)]
-             for l, ls in enumerate(ld_slots)]
+        rdiag = enc(extended_reshuffle(c), pl.n1_R, OBJ_RDIAG, 0, lv["dec"])
+        ldiag = [enc(c.Lfold[l], pl.n1_L, OBJ_LDIAG, l, lv["branches"]) for l in range(c.d)]
     masks = [sc.encrypt_slots(keys, pl.layout.replicate(mk), seed, obj_id(OBJ_MASK, 0, l), lv["levels"])
              for l, mk in enumerate(c.masks)]
     return EncModel(TH, rdiag, ldiag, masks)
@@ -242,10 +273,10 @@ class Evaluator:
         sc = self.sc
         n = len(diags)
         n2 = -(-n // n1)
-        used = sorted({k % n1 for k, d in enumerate(diags) if d is not None})
+        used = sorted({k % n1 for k in range(n) if _present(diags, k)})
         baby = sc.rotate_hoisted(v, used, self.keys)
         idx = sc.data_idx(v.level)
-        enc = any(isinstance(d, Ciphertext) for d in diags)
+        enc = diags.encrypted if isinstance(diags, Diagonals) else any(isinstance(d, Ciphertext) for d in diags)
         baby_ntt = {}
         if not enc:
             for j, ct in baby.items():
@@ -253,7 +284,7 @@ class Evaluator:
         parts = []
         for g in range(n2):
             terms = [(j, diags[g * n1 + j]) for j in range(n1)
-                     if g * n1 + j < n and diags[g * n1 + j] is not None]
+                     if g * n1 + j < n and _present(diags, g * n1 + j)]
             if not terms:
                 continue
             if enc:

@@ -186,18 +186,19 @@ def seccomp_slots(xp: List[np.ndarray], tp: List[np.ndarray], t: int) -> np.ndar
     return dec
 
 
-def prerotated_diagonals(A: np.ndarray, lay: Layout, n1: int) -> List[np.ndarray]:
+def prerotated_diagonal(A: np.ndarray, lay: Layout, n1: int, k: int) -> np.ndarray:
     """Diagonal k = g n1 + j of A, placed at block offsets g n1 .. g n1 + rows - 1
     (that is rot(d_k, -g n1) inside every block)."""
     rows, n = A.shape
-    out = []
-    for k in range(n):
-        g = k // n1
-        dk = generalized_diagonal(A, k)
-        vec = np.zeros(g * n1 + rows, dtype=np.int64)
-        vec[g * n1:] = dk
-        out.append(lay.replicate(vec))
-    return out
+    g = k // n1
+    vec = np.zeros(g * n1 + rows, dtype=np.int64)
+    vec[g * n1:] = generalized_diagonal(A, k)
+    return lay.replicate(vec)
+
+
+def prerotated_diagonals(A: np.ndarray, lay: Layout, n1: int) -> List[np.ndarray]:
+    """Every pre-rotated diagonal of A (see prerotated_diagonal)."""
+    return [prerotated_diagonal(A, lay, n1, k) for k in range(A.shape[1])]
 
 
 def matmul_bsgs(v: np.ndarray, diags: List[np.ndarray], n1: int, t: int) -> np.ndarray:
