@@ -2319,6 +2319,17 @@ __device__ __forceinline__ MmPlace mm_place(int ng, int G, int wv) {
   return m;
 }
 
+// Encrypted diagonals (Karatsuba): acc = {sum x0 d0, sum (x0 + x1)(d0 + d1), sum x1 d1}; the middle sum
+// becomes sum (x0 d1 + x1 d0) = acc[1] - acc[0] - acc[2].  Every term is a lazy product of operands below 2q,
+// |term| < 1.25 q (the quotient estimate is off by at most 0.75 for products below 4 q^2 < 2^100); sums are
+// folded back with reduce_sym every kRed = 3 terms, so every partial sum stays far below 2^53 (exact).
+__device__ __forceinline__ void mm_karatsuba_mid(double (&a)[3], double q, double qinv) {
+  const double lo = reduce_sym(a[0], q, qinv), hi = reduce_sym(a[2], q, qinv);
+  a[1] = reduce_sym(a[1], q, qinv) - lo - hi;
+  a[0] = lo;
+  a[2] = hi;
+}
+
 // One batch element: the four waves of a workgroup take every fourth baby step of the same coefficients
 // (each wave's chain of dependent loads a quarter as long) and add their partial sums through LDS at the
 // end.  Per baby step the GM diagonal loads are issued together (a zero diagonal loads the baby value
@@ -2373,7 +2384,7 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
       if (ptr[s] != nullptr) {
         if (kEnc) {
           acc[s][0] += mul_lazy(x0, d0[s], pr.q, pr.qinv);
-          acc[s][1] += mul_lazy(x0, d1[s], pr.q, pr.qinv) + mul_lazy(x1, d0[s], pr.q, pr.qinv);
+          acc[s][1] += mul_lazy(x0 + x1, d0[s] + d1[s], pr.q, pr.qinv);
           acc[s][kNp - 1] += mul_lazy(x1, d1[s], pr.q, pr.qinv);
         } else {
           acc[s][0] += mul_lazy(x0, d0[s], pr.q, pr.qinv);
@@ -2396,9 +2407,11 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
   for (int sb = 0; sb < GM; sb += kMmWaves) {
 #pragma unroll
     for (int q = 0; q < kMmWaves; ++q)
-      if (sb + q < GM)
+      if (sb + q < GM) {
+        if constexpr (kEnc) mm_karatsuba_mid(acc[sb + q], pr.q, pr.qinv);
 #pragma unroll
         for (int p = 0; p < kNp; ++p) red[wv][q][p][lane] = reduce_sym(acc[sb + q][p], pr.q, pr.qinv);
+      }
     lds_barrier();
     const int s = sb + wv;
     if (s < gm) {
@@ -2515,6 +2528,7 @@ __global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict_
     uint32_t mask_n;
     const int un = scan(u + 1, mask_n);
     if (un < n_u) issue(un);   // in flight during this step's products
+    const double xs = x0 + x1;   // < 2 q (encrypted model only)
     if (has_b) {
 #pragma unroll
       for (int s = 0; s < GM; ++s) {
@@ -2523,9 +2537,11 @@ __global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict_
         if (kEnc || ((mask >> s) & 1u)) {
           const double d0 = dl[buf][s][0][lane];
           if (kEnc) {
+            // three products (Karatsuba): acc[1] holds sum (x0 + x1)(d0 + d1), and a0 b1 + a1 b0 is formed
+            // from it and the other two sums at the end (exact mod q)
             const double d1 = dl[buf][s][kNd - 1][lane];
             acc[s][0] += mul_lazy(x0, d0, pr.q, pr.qinv);
-            acc[s][1] += mul_lazy(x0, d1, pr.q, pr.qinv) + mul_lazy(x1, d0, pr.q, pr.qinv);
+            acc[s][1] += mul_lazy(xs, d0 + d1, pr.q, pr.qinv);
             acc[s][kNp - 1] += mul_lazy(x1, d1, pr.q, pr.qinv);
           } else {
             acc[s][0] += mul_lazy(x0, d0, pr.q, pr.qinv);
@@ -2555,6 +2571,7 @@ __global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict_
   for (int s = 0; s < GM; ++s) {
     if (s < gm) {
       double* op = out + ((size_t)(s0 + s) * G + b) * kNp * ps;
+      if constexpr (kEnc) mm_karatsuba_mid(acc[s], pr.q, pr.qinv);
 #pragma unroll
       for (int p = 0; p < kNp; ++p) op[(size_t)p * ps + o] = canon(reduce_sym(acc[s][p], pr.q, pr.qinv), pr.q);
     }

@@ -460,43 +460,71 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["c2_forest16_d5", "c5_serve_8x_d4"])
-def test_workload_full_size_against_stored_oracle(C, name):
-    """Full-size workloads: the result ciphertext's SHA-256 and sampled
-    coefficients equal the oracle's (stored by tests/golden/make_golden.py)."""
+def _digest(polys):
     import hashlib
+    h = hashlib.sha256()
+    for p in polys:
+        h.update(np.ascontiguousarray(p, dtype="<u8").tobytes())
+    return h.hexdigest()
+
+
+# Full-size workloads against stored oracle results (tests/golden/make_golden.py: query group 0), each in the
+# launch configuration the benchmark times: batch = query groups per evaluate_batch call (1: evaluate).  With
+# label_groups > batch, the remaining groups of the workload follow in calls of the same batch size and their
+# decrypted labels are checked against the plain forest (every query of the workload).
+FULL_SIZE = [("c2_forest16_d5", 1, 1), ("c5_serve_8x_d4", 1, 1), ("c5_serve_32x_d6", 1, 1),
+             ("c5_serve_64x_d8", 1, 1), ("c3_batched_32x_d6", 16, 64), ("c4_encmodel_64x_d8", 4, 64)]
+
+
+@pytest.mark.parametrize("name,batch,label_groups", FULL_SIZE)
+def test_workload_full_size_against_stored_oracle(C, name, batch, label_groups):
+    """Full-size workloads: the result ciphertext of query group 0 (its SHA-256 and sampled coefficients)
+    equals the oracle's, evaluated inside a batch of the benchmark's size; every evaluated query's labels
+    equal the plain forest's."""
     gold = _golden(name)
+    assert gold["group"] == 0
     w = synth.WORKLOADS[name]
     text, queries, seed = synth.workload_inputs(w)
-    say("full size", name)
+    say("full size", name, "batch", batch, "label groups", label_groups)
     ctx = C.Context(**w.chain)
     comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
                                   n1_R=w.n1[0], n1_L=w.n1[1])
     keys = ctx.keygen(seed, C.compiled_rotations(meta))
-    model = ctx.model_encode(comp)
+    evk = ctx.export_eval(keys)
+    if w.encrypted_model:
+        model = ctx.model_encode(comp, keys, encrypt=True, seed=seed)
+    else:
+        model = ctx.model_encode(comp)
+    qs = meta.queries_per_ct
     nq = gold["n_queries"]
-    qct = ctx.query_encrypt(keys, meta, queries[:nq], seed, group=gold["group"])
-    res = ctx.evaluate(model, ctx.export_eval(keys), qct)
-    ex = ctx.export(res)[0]
-    assert ex["level"] == gold["level"]
-    h = hashlib.sha256()
-    for p in ex["polys"]:
-        h.update(np.ascontiguousarray(p, dtype="<u8").tobytes())
-    assert [int(ex["polys"][0][0, i]) for i in gold["sample_index"]] == gold["sample_c0"]
-    assert [int(ex["polys"][1][0, i]) for i in gold["sample_index"]] == gold["sample_c1"]
-    assert h.hexdigest() == gold["sha256"]
-    bits = ctx.decrypt_labels(keys, meta, res, nq)
-    assert bits.tolist() == gold["labels"]
-    # the captured evaluation gives the same bits, replay after replay
-    ex = ctx.exec_create(model, ctx.export_eval(keys), 1)
-    for rep in range(2):
-        got = ctx.export(ex.run([qct])[0])[0]
-        hg = hashlib.sha256()
-        for p in got["polys"]:
-            hg.update(np.ascontiguousarray(p, dtype="<u8").tobytes())
-        assert hg.hexdigest() == gold["sha256"], f"replay {rep}"
-        ctx.evaluate(model, ctx.export_eval(keys), qct)   # eager work between replays
-    ex.close()
+    assert nq == min(qs, len(queries))
+    _, trees = F.parse_forest(text)
+    qct0 = None
+    for g0 in range(0, label_groups, batch):
+        qsets = [queries[g * qs:(g + 1) * qs] for g in range(g0, min(label_groups, g0 + batch))]
+        cts = [ctx.query_encrypt(keys, meta, q, seed, group=g0 + i) for i, q in enumerate(qsets)]
+        res = ctx.evaluate_batch(model, evk, cts) if batch > 1 else [ctx.evaluate(model, evk, cts[0])]
+        if g0 == 0:
+            ex = ctx.export(res[0])[0]
+            assert ex["level"] == gold["level"]
+            assert [int(ex["polys"][0][0, i]) for i in gold["sample_index"]] == gold["sample_c0"]
+            assert [int(ex["polys"][1][0, i]) for i in gold["sample_index"]] == gold["sample_c1"]
+            assert _digest(ex["polys"]) == gold["sha256"]
+            assert ctx.decrypt_labels(keys, meta, res[0], nq).tolist() == gold["labels"]
+            qct0 = cts[0]
+        for q, r in zip(qsets, res):
+            bits = ctx.decrypt_labels(keys, meta, r, len(q))
+            assert (bits == np.array([F.evaluate(trees, list(x)) for x in q])).all()
+        if label_groups > batch:
+            say("groups", g0, "..", g0 + len(qsets) - 1, "ok")
+    if batch == 1 and name in ("c2_forest16_d5", "c5_serve_8x_d4"):
+        # the captured evaluation gives the same bits, replay after replay
+        ex = ctx.exec_create(model, evk, 1)
+        for rep in range(2):
+            got = ctx.export(ex.run([qct0])[0])[0]
+            assert _digest(got["polys"]) == gold["sha256"], f"replay {rep}"
+            ctx.evaluate(model, evk, qct0)   # eager work between replays
+        ex.close()
 
 
 def test_captured_evaluation_replays_match_batch(C):
@@ -536,31 +564,61 @@ def test_captured_evaluation_replays_match_batch(C):
     ex.close()
 
 
-# Full-size workloads whose oracle run is too long for a test: every decrypted label of the evaluated
-# queries against the plain forest (a property that holds at any size), in the batched launch
-# configuration the benchmark times; the decryption's noise check must pass too.
-@pytest.mark.parametrize("name,groups,batch", [("c3_batched_32x_d6", 64, 16), ("c4_encmodel_64x_d8", 2, 2)])
-def test_workload_full_size_labels(C, name, groups, batch):
-    w = synth.WORKLOADS[name]
-    text, queries, seed = synth.workload_inputs(w)
-    say("full-size labels", name, "groups", groups, "batch", batch)
-    ctx = C.Context(**w.chain)
-    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
-                                  n1_R=w.n1[0], n1_L=w.n1[1])
-    keys = ctx.keygen(seed, C.compiled_rotations(meta))
-    evk = ctx.export_eval(keys)
-    if w.encrypted_model:
-        model = ctx.model_encode(comp, keys, encrypt=True, seed=seed)
-    else:
-        model = ctx.model_encode(comp)
-    qs = meta.queries_per_ct
-    assert groups * qs <= len(queries)
+def _mm_chunk_gm(ng, enc, G):
+    """The register-tile width (giant groups per thread) the library's MatMul inner-sum launcher picks for
+    ng giant groups: chunks of at most 24 groups (12 for an encrypted model or one batch element), split
+    evenly, rounded up to the next instantiated width."""
+    cap = 12 if enc or G == 1 else 24
+    chunks = -(-ng // cap)
+    per = -(-ng // chunks)
+    return next(gm for gm in (4, 8, 12, 16, 24, 32) if per <= gm)
+
+
+def _giant_groups(A, n1, enc):
+    """Giant groups of a product with matrix A and n1 baby steps that hold a term (every group for an
+    encrypted model, whose zero diagonals are encrypted too)."""
+    n = A.shape[1]
+    n2 = -(-n // n1)
+    if enc:
+        return n2
+    return sum(1 for g in range(n2)
+               if any(OC.generalized_diagonal(A % T, g * n1 + j).any() for j in range(n1) if g * n1 + j < n))
+
+
+@pytest.mark.parametrize("enc", [False, True])
+def test_matmul_wide_chunks_bit_exact(C, enc):
+    """Two query groups through the batched MatMul inner sums with the wide register tiles the full-size
+    workloads run (plaintext model: 16 and 24 giant groups per thread; encrypted model: 12), on the ring
+    of the fused passes (log N = 13): result ciphertexts equal the oracle's bit for bit, labels equal the
+    plain forest.  The baby-step counts are picked so that the products reach those tile widths."""
+    shape = synth.ForestShape(6, 4, 0.85, 3, 4, 3)
+    text = synth.gen_forest_text(shape, 71)
+    oc = OC.compile_forest(text, 3, 4)
+    G = 2
+    Rext = OC.extended_reshuffle(oc)
+    want_R, want_L = ((16,), (24,)) if not enc else ((12, 8), (12,))
+    n1_R = next(n for n in range(2, 41) if _mm_chunk_gm(_giant_groups(Rext, n, enc), enc, G) in want_R)
+    n1_L = next(n for n in range(2, 41)
+                if _mm_chunk_gm(sum(_giant_groups(oc.Lfold[l], n, enc) for l in range(oc.d)), enc, G) in want_L)
+    say("wide chunks enc", enc, "b", oc.b, "q", oc.q, "d", oc.d, "n1_R", n1_R, "n1_L", n1_L)
+    need = CI.seccomp_depth(4) + 2 + math.ceil(math.log2(oc.d))
+    ch = dict(log_n=13, n_data_primes=need + 1, q0_max=1 << 49, data_max=1 << 42, alpha=3, special_max=1 << 49)
+    ctx = C.Context(**ch)
+    comp, meta = C.forest_compile(text, 3, 4, 13, n1_R=n1_R, n1_L=n1_L)
+    assert (meta.n1_R, meta.n1_L) == (n1_R, n1_L)
+    kseed = b"\x47" * 32
+    keys = ctx.keygen(kseed, C.compiled_rotations(meta))
+    model = ctx.model_encode(comp, keys if enc else None, encrypt=enc, seed=kseed if enc else None)
+    qsets = [synth.gen_queries(meta.queries_per_ct, 3, 4, 940 + g) for g in range(G)]
+    groups = [ctx.query_encrypt(keys, meta, qsets[g], kseed, group=g) for g in range(G)]
+    batch = ctx.evaluate_batch(model, ctx.export_eval(keys), groups)
+    sc = B.BGV(nt.make_chain(13, T, need + 1, 1 << 49, 1 << 42, 3, 1 << 49))
+    pl = CI.make_plan(oc, sc.N, sc.L, encrypted_model=enc, n1_R=n1_R, n1_L=n1_L)
+    okeys = sc.keygen(kseed, rotations=pl.rotations())
+    omodel = CI.encrypt_model(sc, okeys, pl, kseed) if enc else CI.encode_model(sc, pl)
     _, trees = F.parse_forest(text)
-    for g0 in range(0, groups, batch):
-        qsets = [queries[g * qs:(g + 1) * qs] for g in range(g0, min(groups, g0 + batch))]
-        cts = [ctx.query_encrypt(keys, meta, q, seed, group=g0 + i) for i, q in enumerate(qsets)]
-        res = ctx.evaluate_batch(model, evk, cts)
-        for q, r in zip(qsets, res):
-            bits = ctx.decrypt_labels(keys, meta, r, len(q))
-            assert (bits == np.array([F.evaluate(trees, list(x)) for x in q])).all()
-        say("groups", g0, "..", g0 + len(qsets) - 1, "ok")
+    for g in range(G):
+        X = CI.encrypt_queries(sc, okeys, pl, qsets[g], kseed, g)
+        same(ctx.export(batch[g])[0], CI.Evaluator(sc, okeys, pl).run(X, omodel)["result"])
+        bits = ctx.decrypt_labels(keys, meta, batch[g], len(qsets[g]))
+        assert (bits == np.array([F.evaluate(trees, list(x)) for x in qsets[g]])).all()
