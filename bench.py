@@ -1,20 +1,26 @@
 """Benchmark of the encrypted decision-forest evaluation on one MI355X.
 
-Workload (default): 16 random unbalanced trees of maximum depth 5, 16 features,
-8-bit values, 4 classes, plaintext model held by the server, one encrypted
-query per evaluation, ring N = 32768 with an 11-prime chain (synthetic forest
-and query from the pinned generator).  A step is one complete evaluation of
-Algorithm 1 on one encrypted query group: comparison, reshuffle, level
-products with masks, product tree, switch to q_0.  Encrypted queries are
-resident in device memory before the timed region starts.
+Workload (default): 64 random unbalanced trees of maximum depth 8, 32
+features, 16-bit values, 10 classes, with the thresholds, the reshuffle and
+level diagonals and the masks encrypted under the data owner's key (45 GiB of
+ciphertexts resident in HBM), ring N = 32768 with 11 data primes and 4 special
+primes; all 256 encrypted queries of the workload (64 query groups of 4) per
+step, in batched calls of 8 groups.  A step is the complete Algorithm 1 on
+every query: comparison, reshuffle, level products with masks, product tree,
+switch to q_0.  Encrypted queries are resident in device memory before the
+timed region starts.  Inputs are synthetic (the pinned generator).
 
 Prints one JSON line: throughput (encrypted queries/s), per-step latency
 percentiles, the roofline of the dominant kernel (its per-launch time taken
-with HIP events on the stream it runs on) and the CPU oracle's throughput on
-a bounded sample of the same workload.
+with HIP events on the stream it runs on; against HBM bandwidth and, for an
+encrypted model's MatMul inner sums, against the fp64 pipe's rate of exact
+modular products), the unbatched path's rate on one group of the same
+workload (batched / plain), the CPU oracle's throughput on a bounded sample
+(single thread and one process per core), and extra lines for the batched
+32-tree workload (1024 queries per step) and the one-query 16-tree workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--batch G] [--no-cpu-baseline]
+                    [--batch G] [--groups N] [--no-cpu-baseline] [--no-extras]
 """
 from __future__ import annotations
 
@@ -76,13 +82,196 @@ def measured_traffic(kind: str, workload: str):
     return doc["bytes_per_dispatch"]
 
 
-def cpu_baseline(w, text, queries, seed, budget_s: float = 25.0):
-    """The oracle, timed on a bounded sample of one evaluation of the same
-    workload: the comparison, the reshuffle product and the first level
-    product are run in full; the remaining d-1 level products (same shape,
-    scaled by their count of nonzero diagonals) and the d-1 products of the
-    product tree (scaled from the comparison's measured product time) are
-    extrapolated from those measurements."""
+def _dry_ct(level, npolys=2):
+    """Stand-in ciphertext of the schedule's dry run: only its level and component count."""
+    from oracle.bgv import Ciphertext
+    return Ciphertext([None] * npolys, level)
+
+
+class _DryBGV:
+    """Runs the oracle's evaluation schedule (circuit.Evaluator) without arithmetic and records every
+    operation it would perform as (name, level[, size]): the operation counts of one query group, taken
+    from the schedule code itself."""
+
+    def __init__(self, sc):
+        self.N, self.t, self.L = sc.N, sc.t, sc.L
+        self.ops = {}
+
+    def _rec(self, *key):
+        self.ops[key] = self.ops.get(key, 0) + 1
+
+    def data_idx(self, level):
+        return list(range(level + 1))
+
+    # model and query set-up (not part of an evaluation)
+    def encode(self, slots):
+        return None
+
+    def encrypt_slots(self, keys, slots, seed, obj, level=None):
+        return _dry_ct(self.L if level is None else level)
+
+    # the operations the evaluation performs
+    def modswitch(self, ct):
+        self._rec("modswitch", ct.level, len(ct.polys))
+        return _dry_ct(ct.level - 1, len(ct.polys))
+
+    def modswitch_to(self, ct, level):
+        while ct.level > level:
+            ct = self.modswitch(ct)
+        return ct
+
+    def _bin(self, name, a, b):
+        lv = min(a.level, b.level)
+        a, b = self.modswitch_to(a, lv), self.modswitch_to(b, lv)
+        self._rec(name, lv, max(len(a.polys), len(b.polys)))
+        return _dry_ct(lv, max(len(a.polys), len(b.polys)))
+
+    def add(self, a, b):
+        return self._bin("add", a, b)
+
+    def sub(self, a, b):
+        return self._bin("sub", a, b)
+
+    def tensor(self, a, b):
+        self._bin("tensor", a, b)
+        return _dry_ct(min(a.level, b.level), 3)
+
+    def mul(self, a, b, keys):
+        lv = min(a.level, b.level)
+        self.modswitch_to(a, lv), self.modswitch_to(b, lv)
+        self._rec("mul", lv)
+        return _dry_ct(lv - 1)
+
+    def relinearize(self, ct, keys):
+        self._rec("relin", ct.level)
+        return _dry_ct(ct.level)
+
+    def mul_int(self, a, k):
+        self._rec("mul_int", a.level)
+        return _dry_ct(a.level, len(a.polys))
+
+    def add_plain(self, a, m):
+        self._rec("add_plain", a.level)
+        return _dry_ct(a.level, len(a.polys))
+
+    def mul_plain(self, a, m):
+        self._rec("mul_plain", a.level)
+        return _dry_ct(a.level, len(a.polys))
+
+    def rotate_hoisted(self, ct, rs, keys):
+        nz = [r for r in rs if r % (self.N // 2)]
+        if nz:
+            self._rec("rot_hoisted", ct.level, len(nz))
+        return {r: _dry_ct(ct.level) for r in rs}
+
+    def rotate_sum(self, items, keys):
+        lv = items[0][0].level
+        self._rec("rotate_sum", lv, sum(1 for _, r in items if r % (self.N // 2)), len(items))
+        return _dry_ct(lv)
+
+    # plaintext-model inner sums (rows of residues)
+    def ntt(self, a, idx):
+        self._rec("ntt", len(idx))
+
+    def intt(self, a, idx):
+        self._rec("intt", len(idx))
+
+    def plain_ntt(self, m, level):
+        self._rec("plain_ntt", level)
+
+    def pmul_ntt(self, a, b, idx):
+        self._rec("pmul", len(idx))
+
+    def padd(self, a, b, idx):
+        return None
+
+
+def _time_ops(sc, keys, ops, seed, reps=1):
+    """Seconds of each recorded operation (by name and level) on the oracle, on fresh encryptions."""
+    from oracle import bgv as B
+    rng = np.random.default_rng(5)
+    cache = {}
+
+    def ct(level, npolys=2, obj=0):
+        k = (level, npolys, obj)
+        if k not in cache:
+            v = rng.integers(0, 2, size=(2, sc.N // 2))
+            c = sc.encrypt_slots(keys, v, seed, 10_000 + 100 * level + obj, level)
+            cache[k] = c if npolys == 2 else sc.tensor(c, ct(level, 2, obj + 1))
+        return cache[k]
+
+    pt = sc.encode(rng.integers(0, 2, size=(2, sc.N // 2)))
+
+    def best(f):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t0)
+        return min(ts)
+
+    rows = {}
+    for key in ops:
+        name, lv = key[0], key[1]
+        if name in ("modswitch", "add", "sub", "tensor"):
+            np_ = key[2]
+            a, b = ct(lv, np_ if name != "tensor" else 2), ct(lv, np_ if name != "tensor" else 2, 1)
+            f = {"modswitch": lambda: sc.modswitch(a), "add": lambda: sc.add(a, b), "sub": lambda: sc.sub(a, b),
+                 "tensor": lambda: sc.tensor(a, b)}[name]
+            rows[key] = best(f)
+        elif name == "mul":
+            a, b = ct(lv), ct(lv, 2, 1)
+            rows[key] = best(lambda: sc.mul(a, b, keys))
+        elif name == "relin":
+            a = ct(lv, 3)
+            rows[key] = best(lambda: sc.relinearize(a, keys))
+        elif name == "mul_int":
+            a = ct(lv)
+            rows[key] = best(lambda: sc.mul_int(a, 2))
+        elif name == "add_plain":
+            a = ct(lv)
+            rows[key] = best(lambda: sc.add_plain(a, pt))
+        elif name == "mul_plain":
+            a = ct(lv)
+            rows[key] = best(lambda: sc.mul_plain(a, pt))
+        elif name == "plain_ntt":
+            rows[key] = best(lambda: sc.plain_ntt(pt, lv))
+        elif name in ("ntt", "intt", "pmul"):
+            idx = list(range(lv))
+            x = np.zeros((lv, sc.N), dtype=np.uint64)
+            f = {"ntt": lambda: sc.ntt(x, idx), "intt": lambda: sc.intt(x, idx),
+                 "pmul": lambda: sc.pmul_ntt(x, x, idx)}[name]
+            rows[key] = best(f)
+    # rotations: the hoisted set costs one ModUp plus a per-rotation part; a rotation sum a per-term part
+    # plus the final ModDowns; both are fitted from one and two rotations at each level
+    for lv in sorted({k[1] for k in ops if k[0] in ("rot_hoisted", "rotate_sum")}):
+        a = ct(lv)
+        t1 = best(lambda: sc.rotate_hoisted(a, [1], keys))
+        t2 = best(lambda: sc.rotate_hoisted(a, [1, 2], keys))
+        s1 = best(lambda: sc.rotate_sum([(a, 1)], keys))
+        s2 = best(lambda: sc.rotate_sum([(a, 1), (a, 2)], keys))
+        rows[("rot_each", lv)], rows[("rot_base", lv)] = t2 - t1, 2 * t1 - t2
+        rows[("rsum_each", lv)], rows[("rsum_base", lv)] = s2 - s1, 2 * s1 - s2
+    return rows
+
+
+def _group_seconds(ops, rows):
+    total = 0.0
+    for key, n in ops.items():
+        name, lv = key[0], key[1]
+        if name == "rot_hoisted":
+            total += n * (rows[("rot_base", lv)] + key[2] * rows[("rot_each", lv)])
+        elif name == "rotate_sum":
+            total += n * (rows[("rsum_base", lv)] + key[2] * rows[("rsum_each", lv)])
+        else:
+            total += n * rows[key]
+    return total
+
+
+def _cpu_sample(w, text, seed, reps=1):
+    """One query group of the workload on the oracle: every operation of the evaluation schedule counted
+    by a dry run of the oracle's own schedule code, each distinct (operation, level) timed once on the
+    oracle, the group's time = sum of count x time.  Returns (seconds per group, sampled seconds, counts)."""
     from oracle import bgv as B
     from oracle import circuit as CI
     from oracle import compiler as OC
@@ -92,37 +281,58 @@ def cpu_baseline(w, text, queries, seed, budget_s: float = 25.0):
     sc = B.BGV(nt.make_chain(ch["log_n"], 65537, ch["n_data_primes"], ch["q0_max"], ch["data_max"],
                              ch["alpha"], ch["special_max"]))
     oc = OC.compile_forest(text, w.shape.n_features, w.shape.precision)
-    pl = CI.make_plan(oc, sc.N, sc.L, fold=w.fold, n1_R=w.n1[0], n1_L=w.n1[1])
-    log("cpu baseline: oracle keygen (untimed)")
-    keys = sc.keygen(seed, rotations=pl.rotations())
-    X = CI.encrypt_queries(sc, keys, pl, queries[:1], seed, 0)
-    model = CI.encode_model(sc, pl)
-    ev = CI.Evaluator(sc, keys, pl)
-    log("cpu baseline: timing the sample")
+    pl = CI.make_plan(oc, sc.N, sc.L, fold=w.fold, encrypted_model=w.encrypted_model, n1_R=w.n1[0], n1_L=w.n1[1])
+    dry = _DryBGV(sc)
+    X = CI.encrypt_queries(dry, None, pl, np.zeros((1, oc.n_features), dtype=np.uint32), seed, 0)
+    model = CI.encrypt_model(dry, None, pl, seed) if w.encrypted_model else CI.encode_model(dry, pl)
+    CI.Evaluator(dry, None, pl).run(X, model)
+    keys = sc.keygen(seed, rotations=[1, 2])            # untimed set-up
     t0 = time.perf_counter()
-    dec = ev.seccomp(X, model)
-    t_sec = time.perf_counter() - t0
-    n_mul = ev.counts["mul"]
-    if w.fold:
-        src, t_r = dec, 0.0
-    else:
-        t1 = time.perf_counter()
-        src = ev.matmul(dec, model.rdiag, pl.n1_R)
-        t_r = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    lv0 = ev.add_mask(ev.matmul(src, model.ldiag[0], pl.n1_L), model.masks[0])
-    t_l0 = time.perf_counter() - t2
-    nz = [sum(d is not None for d in model.ldiag[l]) for l in range(oc.d)]
-    t_levels = t_l0 * sum(nz) / max(1, nz[0])
-    t_tree = (oc.d - 1) * (t_sec / max(1, n_mul))
-    sampled = t_sec + t_r + t_l0
-    total = t_sec + t_r + t_levels + t_tree
-    return {"value": 1.0 / total, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one query of the same workload: comparison ({t_sec:.1f}s), reshuffle product "
-                       f"({t_r:.1f}s) and first level product ({t_l0:.1f}s) run in full ({sampled:.1f}s); "
-                       f"the other {oc.d - 1} level products scaled by nonzero-diagonal count and the "
-                       f"{oc.d - 1} tree products by the measured product time; extrapolated step "
-                       f"{total:.1f}s, single thread")}
+    rows = _time_ops(sc, keys, dry.ops, seed, reps)
+    sampled = time.perf_counter() - t0
+    return _group_seconds(dry.ops, rows), sampled, dry.ops
+
+
+def _cpu_worker(args):
+    name, text, seed = args
+    from paper_2104_09583_amd import synth
+    sec, sampled, _ = _cpu_sample(synth.WORKLOADS[name], text, seed)
+    return sec, sampled
+
+
+def cpu_baseline(w, text, queries, seed, all_cores: bool = True):
+    """The oracle on a bounded sample of the workload: per query group, the operation counts of its whole
+    evaluation (a dry run of the oracle's schedule) times the oracle's measured time of each distinct
+    operation and level.  Single thread, and the same sample in one process per host core at once
+    (all-core throughput: the sum of the processes' rates)."""
+    import multiprocessing as mp
+    from oracle import compiler as OC
+    oc = OC.compile_forest(text, w.shape.n_features, w.shape.precision)
+    qpg = min(w.n_queries, (1 << w.log_n) // oc.W)      # queries per group (slot blocks per ciphertext)
+    log("cpu baseline: single thread")
+    sec, sampled, ops = _cpu_sample(w, text, seed)
+    n_ops = sum(ops.values())
+    out = {"value": qpg / sec, "unit": "queries/s", "cores": 1, "kind": "oracle",
+           "sample": (f"one query group ({qpg} queries): the {n_ops} operations of its evaluation counted by a dry "
+                      f"run of the oracle's schedule, each distinct operation and level ({len(ops)} kinds) timed once "
+                      f"on the oracle ({sampled:.1f}s of CPU work), group time = sum of count x time = {sec:.1f}s "
+                      "(extrapolated), single thread"),
+           "seconds_per_group": round(sec, 2)}
+    if all_cores:
+        # one process per core of this host's share, at most 16 (forked before the GPU is touched)
+        P = max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"cpu baseline: {P} processes at once")
+        ctx = mp.get_context("fork")
+        t0 = time.perf_counter()
+        with ctx.Pool(P) as pool:
+            res = pool.map(_cpu_worker, [(w.name, text, seed)] * P)
+        wall = time.perf_counter() - t0
+        rate = sum(qpg / s for s, _ in res)
+        out["all_cores"] = {"value": rate, "unit": "queries/s", "cores": P, "nproc": P,
+                            "sample": f"the same sample in {P} processes at once ({wall:.1f}s wall); rate = sum of "
+                                      "the processes' extrapolated rates",
+                            "seconds_per_group_mean": round(sum(s for s, _ in res) / P, 2)}
+    return out
 
 
 def serve_bench(args):
@@ -339,16 +549,197 @@ def micro_bench(args):
     print(json.dumps(out))
 
 
+# exact modular product-accumulate on the fp64 pipe: h = a b, l = fma(a, b, -h), k = rint(h / q) (a product and a
+# rounding), r = fma(-k, q, h) + l, acc += r: 7 fp64 instructions; MI355X issues 256 CUs x 4 SIMDs x 16 fp64
+# lanes per clock at 2.4 GHz = 3.93e13 lane-instructions/s (78.6 TFLOP/s counting an fma as two flops)
+FP64_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
+MODMUL_INSTR = 7
+MODMUL_PEAK_T = FP64_LANE_INSTR_PER_S / MODMUL_INSTR / 1e12
+
+
+def _matmul_modmuls(meta, encrypted, G, levels):
+    """Algorithmic modular products of the MatMul inner sums of one evaluation of G query groups: per nonzero
+    diagonal, baby step, group, coefficient and limb, 2 (plaintext diagonal: c0 d, c1 d) or 3 (encrypted
+    diagonal: the tensor's a0 b0, a1 b1 and (a0 + a1)(b0 + b1)).  Every diagonal counts for an encrypted
+    model (its zero diagonals are encrypted too); for a plaintext model `levels` gives the nonzero counts."""
+    N = 1 << meta.log_n
+    per = 3 if encrypted else 2
+    return sum(n * per * G * nl * N for n, nl in levels)
+
+
+def run_workload(w, args, steps, warmup, batch, n_groups, profile=True, plain_groups=0, check_labels=True):
+    """Times `steps` steps of the workload on the GPU; a step evaluates n_groups query groups (every query of
+    the workload by default) in calls of `batch` groups, with the encrypted queries resident in HBM."""
+    import torch
+
+    from paper_2104_09583_amd import copse as C
+    from paper_2104_09583_amd import synth
+
+    text, queries, seed = synth.workload_inputs(w)
+    ch = dict(w.chain)
+    if args.server_rep:
+        ch["n_data_primes"] += 1   # the replication product takes one level
+    n1_r = args.n1_r or w.n1[0]
+    n1_l = args.n1_l or w.n1[1]
+    log("workload", w.name, "chain", ch)
+    t0 = time.perf_counter()
+    ctx = C.Context(**ch)
+    stream = torch.cuda.Stream()
+    ctx.set_stream(stream.cuda_stream)
+    if args.server_rep:
+        comp, meta = C.forest_compile_ex(
+            text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold, n1_R=n1_r, n1_L=n1_l,
+            server_replication=True,
+            privacy_seed=synth.crypto_seed(f"COPSE-shuffle-{w.seed_index}") if args.result_pad >= 0 else None,
+            n_pad=max(0, args.result_pad))
+    elif args.result_pad < 0:
+        comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
+                                      n1_R=n1_r, n1_L=n1_l)
+    else:
+        # result privacy: shuffled result slots and codebook, padded with never-selected labels
+        comp, meta = C.forest_compile_private(text, w.shape.n_features, w.shape.precision, w.log_n,
+                                              synth.crypto_seed(f"COPSE-shuffle-{w.seed_index}"), args.result_pad,
+                                              fold=w.fold, n1_R=n1_r, n1_L=n1_l)
+    rots = C.compiled_rotations(meta)
+    keys = ctx.keygen(seed, rots)
+    evk = ctx.export_eval(keys)
+    log(f"keygen {time.perf_counter() - t0:.1f}s ({len(rots)} rotation keys, {keys.nbytes() / 2**30:.2f} GiB)")
+    t1 = time.perf_counter()
+    model = ctx.model_encode(comp, keys, encrypt=True, seed=seed) if w.encrypted_model else ctx.model_encode(comp)
+    log(f"model encode {time.perf_counter() - t1:.1f}s ({model.nbytes() / 2**30:.2f} GiB)")
+    qs = meta.queries_per_ct
+    n_groups = n_groups or -(-w.n_queries // qs)        # 0: every query of the workload
+    batch = min(batch or (w.batch if not args.plain else 1), n_groups)
+    qsets = []
+    for g in range(n_groups):
+        qi = queries[(g * qs) % len(queries):][:qs]
+        qsets.append(qi if len(qi) else queries[:qs])
+    groups = [ctx.query_encrypt(keys, meta, qsets[g], seed, group=g) for g in range(n_groups)]
+    queries_per_step = sum(len(q) for q in qsets)
+    log(f"{n_groups} query groups ({queries_per_step} queries) resident, {batch} per call")
+
+    ex = None
+    if args.graph:
+        t2 = time.perf_counter()
+        ex = ctx.exec_create(model, evk, batch)
+        log(f"captured evaluation of {batch} group(s) in {time.perf_counter() - t2:.1f}s")
+
+    def call(gs, eager=False):
+        if args.plain:
+            return [ctx.evaluate_plain(model, evk, g) for g in gs]
+        if ex is not None and not eager and len(gs) == batch:
+            return ex.run(gs)
+        if len(gs) == 1:
+            return [ctx.evaluate(model, evk, gs[0])]
+        return ctx.evaluate_batch(model, evk, gs)
+
+    def step(eager=False, keep=False):
+        out = []
+        for g0 in range(0, n_groups, batch):
+            r = call(groups[g0:g0 + batch], eager)
+            if keep:
+                out.extend(r)
+        return out
+
+    # the first warmup's results: every query's decrypted labels against the oracle's plain forest walk (part of
+    # the CPU-baseline leg: skipped with it)
+    res = step(keep=True)
+    labels_ok = None
+    if check_labels:
+        from oracle import forest as F
+        _, trees = F.parse_forest(text)
+        book = C.compiled_codebook(comp)
+        oracle_book = F.codebook(trees)
+        for q, r in zip(qsets, res):
+            bits = ctx.decrypt_labels(keys, meta, r, len(q))
+            for x, b in zip(q, bits):
+                plain = F.evaluate(trees, list(x))
+                if args.result_pad < 0:
+                    assert list(b) == list(plain), "decrypted labels differ from plain evaluation"
+                else:
+                    assert sorted(book[s] for s in range(len(book)) if b[s]) == \
+                        sorted(oracle_book[i] for i in range(len(plain)) if plain[i]), "decrypted labels differ"
+        labels_ok = queries_per_step
+    del res
+    for _ in range(max(0, warmup - 1)):
+        step()
+    ctx.sync()
+    torch.cuda.synchronize()
+
+    prof = None
+    per_step = []
+    if profile:
+        ctx.profile_enable(True)
+        for k in range(C.PROF_KINDS):
+            ctx.profile_read(k, reset=True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        # per-kernel timings need one event pair per launch: this loop runs the same schedule eagerly
+        for _ in range(steps):
+            with torch.cuda.stream(stream):
+                ev0.record(stream)
+            step(eager=True)
+            with torch.cuda.stream(stream):
+                ev1.record(stream)
+            ev1.synchronize()
+            per_step.append(ev0.elapsed_time(ev1))
+        ctx.sync()
+        torch.cuda.synchronize()
+        prof = {k: ctx.profile_read(k) for k in range(C.PROF_KINDS)}
+        ctx.profile_enable(False)
+    # Headline: an unprofiled loop, bracketed by device synchronization, timed on the host clock.
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall_clean = time.perf_counter() - wall1
+    lat = [e0.elapsed_time(e1) for e0, e1 in evs]
+    ms_per_step = wall_clean * 1000.0 / steps
+
+    plain = None
+    if plain_groups:
+        # the unbatched path on the same slot layout: one group per call, one homomorphic operation per launch
+        ctx.evaluate_plain(model, evk, groups[0])
+        ctx.sync()
+        t3 = time.perf_counter()
+        for g in range(plain_groups):
+            ctx.evaluate_plain(model, evk, groups[g])
+        ctx.sync()
+        pms = (time.perf_counter() - t3) * 1000.0 / plain_groups
+        plain = {"ms_per_group": round(pms, 3), "queries_per_s": round(qs / (pms / 1000.0), 3),
+                 "groups_timed": plain_groups}
+
+    out = {"ctx": ctx, "meta": meta, "queries_per_step": queries_per_step, "n_groups": n_groups, "batch": batch, "ms_per_step": ms_per_step,
+           "lat": lat, "per_step": per_step, "prof": prof, "plain": plain, "labels_checked": labels_ok,
+           "chain": ch, "model_bytes": model.nbytes(), "keys_bytes": keys.nbytes()}
+    for h in groups:
+        h.close()
+    for h in (ex, model, evk, keys, comp):
+        if h is not None:
+            h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2_forest16_d5")
-    ap.add_argument("--batch", type=int, default=1, help="query groups evaluated together per step")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c4_encmodel_64x_d8")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="query groups evaluated together per call (0: the workload's choice)")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="query groups per step (0: every query of the workload)")
     ap.add_argument("--plain", action="store_true",
                     help="the unbatched path: each group alone, one homomorphic operation per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the c3 and c2 lines of the default run")
     ap.add_argument("--graph", action="store_true",
                     help="replay the captured evaluation (HIP graph) instead of launching eagerly; on this "
                          "ROCm stack a replay costs about 1 us more per kernel than the eager launches")
@@ -372,166 +763,97 @@ def main():
     if args.workload == "f2_table6":
         return micro_bench(args)
 
-    import torch
-
-    from paper_2104_09583_amd import copse as C
     from paper_2104_09583_amd import synth
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
     w = synth.WORKLOADS[args.workload]
     text, queries, seed = synth.workload_inputs(w)
-    ch = dict(w.chain)
-    if args.server_rep:
-        ch["n_data_primes"] += 1   # the replication product takes one level
-    # baby-step counts: the command line, else the workload's measured choice, else the compiler's rule
-    args.n1_r = args.n1_r or w.n1[0]
-    args.n1_l = args.n1_l or w.n1[1]
-    log("workload", w.name, "chain", ch)
-    t0 = time.perf_counter()
-    ctx = C.Context(**ch)
-    stream = torch.cuda.Stream()
-    ctx.set_stream(stream.cuda_stream)
-    if args.server_rep:
-        # queries hold each feature once; the server replicates them (one more level)
-        comp, meta = C.forest_compile_ex(
-            text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold, n1_R=args.n1_r, n1_L=args.n1_l,
-            server_replication=True,
-            privacy_seed=synth.crypto_seed(f"COPSE-shuffle-{w.seed_index}") if args.result_pad >= 0 else None,
-            n_pad=max(0, args.result_pad))
-    elif args.result_pad < 0:
-        comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n, fold=w.fold,
-                                      n1_R=args.n1_r, n1_L=args.n1_l)
-    else:
-        # result privacy: shuffled result slots and codebook, padded with never-selected labels
-        comp, meta = C.forest_compile_private(text, w.shape.n_features, w.shape.precision, w.log_n,
-                                              synth.crypto_seed(f"COPSE-shuffle-{w.seed_index}"), args.result_pad,
-                                              fold=w.fold, n1_R=args.n1_r, n1_L=args.n1_l)
-    rots = C.compiled_rotations(meta)
-    keys = ctx.keygen(seed, rots)
-    evk = ctx.export_eval(keys)
-    log(f"keygen {time.perf_counter() - t0:.1f}s ({len(rots)} rotation keys, {keys.nbytes() / 2**30:.2f} GiB)")
-    t1 = time.perf_counter()
-    if w.encrypted_model:
-        model = ctx.model_encode(comp, keys, encrypt=True, seed=seed)
-    else:
-        model = ctx.model_encode(comp)
-    log(f"model encode {time.perf_counter() - t1:.1f}s ({model.nbytes() / 2**30:.2f} GiB)")
-    nq_group = min(w.n_queries, meta.queries_per_ct)
-    groups = []
-    for g in range(args.batch):
-        qi = queries[(g * nq_group) % len(queries):][:nq_group]
-        if len(qi) < nq_group:
-            qi = queries[:nq_group]
-        groups.append(ctx.query_encrypt(keys, meta, qi, seed, group=g))
-    queries_per_step = nq_group * args.batch
+    # the oracle's CPU baseline first, before anything touches the GPU (its all-core leg forks processes)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, text, queries, seed)
+        log(f"cpu baseline {cpu['value']:.5f} queries/s single thread")
 
-    ex = None
-    if not args.plain and args.graph:
-        t2 = time.perf_counter()
-        ex = ctx.exec_create(model, evk, len(groups))
-        log(f"captured evaluation of {len(groups)} group(s) in {time.perf_counter() - t2:.1f}s")
+    import torch
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    from paper_2104_09583_amd import copse as C
 
-    def step_eager():
-        if args.plain:
-            return [ctx.evaluate_plain(model, evk, g) for g in groups]
-        if args.batch == 1:
-            return [ctx.evaluate(model, evk, groups[0])]
-        return ctx.evaluate_batch(model, evk, groups)
-
-    def step():
-        return ex.run(groups) if ex is not None else step_eager()
-
-    # the first warmup result is kept for the label check of the CPU-baseline leg
-    res = step()
-    first_bits = ctx.decrypt_labels(keys, meta, res[0], nq_group)
-    del res
-    for _ in range(max(0, args.warmup - 1)):
-        step()
-    ctx.sync()
-    torch.cuda.synchronize()
-
-    ctx.profile_enable(True)
-    for k in range(C.PROF_KINDS):
-        ctx.profile_read(k, reset=True)
-    per_step = []
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    # per-kernel timings need one event pair per launch: this loop runs the same schedule eagerly
-    for _ in range(args.steps):
-        with torch.cuda.stream(stream):
-            ev0.record(stream)
-        step_eager()
-        with torch.cuda.stream(stream):
-            ev1.record(stream)
-        ev1.synchronize()
-        per_step.append(ev0.elapsed_time(ev1))
-    ctx.sync()
-    torch.cuda.synchronize()
-    prof = {k: ctx.profile_read(k) for k in range(C.PROF_KINDS)}
-    ctx.profile_enable(False)
-    # Headline: an unprofiled loop, bracketed by device synchronization, timed on the host clock.
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall1 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        step()
-        e1.record(stream)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall_clean = time.perf_counter() - wall1
-    lat = [e0.elapsed_time(e1) for e0, e1 in evs]
-    ms_per_step = wall_clean * 1000.0 / args.steps
-    # reference copy of known size for the byte counters of a separate --pmc run
-    ctx.calib_copy(256 << 20)
+    headline_default = args.workload == "c4_encmodel_64x_d8" and not (args.plain or args.graph)
+    check = not args.no_cpu_baseline
+    r = run_workload(w, args, args.steps, args.warmup, args.batch, args.groups,
+                     plain_groups=1 if headline_default else 0, check_labels=check)
+    meta, prof, per_step = r["meta"], r["prof"], r["per_step"]
+    n_groups, batch = r["n_groups"], r["batch"]
+    steps = args.steps
 
     # roofline of the dominant kernel (the class with the largest total time among the single-kernel
-    # classes): algorithmic bytes per launch / average launch time, both from the profiled loop
+    # classes): algorithmic bytes (or modular products) per launch / average launch time, from the profiled loop
     cands = [k for k in KIND_KERNELS if prof[k]["launches"] > 0]
     dom = max(cands, key=lambda k: prof[k]["ms"])
     p = prof[dom]
     avg_ms = p["ms"] / max(1, p["launches"])
     bytes_per_launch = p["bytes"] / max(1, p["launches"])
     achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(KIND_NAMES[dom], w.name),
-                "kernel": KIND_KERNELS[dom], "class": KIND_NAMES[dom], "avg_launch_ms": round(avg_ms, 5),
-                "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                "share_of_step": round(p["ms"] / sum(per_step), 3)}
-    kernels = {KIND_NAMES[k]: {"launches_per_step": prof[k]["launches"] / args.steps,
-                               "ms_per_step": round(prof[k]["ms"] / args.steps, 3),
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(KIND_NAMES[dom], w.name)}
+    roofline = dict(hbm)
+    if KIND_NAMES[dom] == "matmul_inner" and w.encrypted_model:
+        # an encrypted model's inner sums: modular products on the fp64 pipe against the same launch time
+        nl_r = r["chain"]["n_data_primes"] - (1 + math.ceil(math.log2(meta.precision)))   # dec level + 1
+        mods = _matmul_modmuls(meta, True, n_groups, [(meta.q, nl_r), (meta.d * meta.b, nl_r - 1)])
+        mods_per_launch = mods * steps / max(1, p["launches"])
+        alu_t = mods_per_launch / (avg_ms / 1000.0) / 1e12
+        alu = {"bound": "alu", "achieved": round(alu_t, 3), "peak": round(MODMUL_PEAK_T, 3), "unit": "Tmodmul/s",
+               "frac": round(alu_t / MODMUL_PEAK_T, 4), "traffic": hbm["traffic"],
+               "modmuls_per_launch": round(mods_per_launch)}
+        roofline = dict(alu) if alu["frac"] >= hbm["frac"] else dict(hbm)
+        roofline["hbm"] = hbm
+        roofline["alu"] = alu
+    roofline.update({"kernel": KIND_KERNELS[dom], "class": KIND_NAMES[dom], "avg_launch_ms": round(avg_ms, 5),
+                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                     "share_of_step": round(p["ms"] / sum(per_step), 3)})
+    kernels = {KIND_NAMES[k]: {"launches_per_step": prof[k]["launches"] / steps,
+                               "ms_per_step": round(prof[k]["ms"] / steps, 3),
                                "avg_launch_us": round(1000 * prof[k]["ms"] / max(1, prof[k]["launches"]), 2),
                                "algorithmic_bytes_per_launch": round(prof[k]["bytes"] / max(1, prof[k]["launches"])),
                                "achieved_GBps": round(prof[k]["bytes"] / max(1e-9, prof[k]["ms"]) / 1e6, 1)}
                for k in range(C.PROF_KERNEL_KINDS) if prof[k]["launches"] > 0}
-    stages = {STAGE_NAMES[k - C.PROF_KERNEL_KINDS]: round(prof[k]["ms"] / args.steps, 3)
+    stages = {STAGE_NAMES[k - C.PROF_KERNEL_KINDS]: round(prof[k]["ms"] / steps, 3)
               for k in range(C.PROF_KERNEL_KINDS, C.PROF_KINDS) if prof[k]["launches"] > 0}
+    ms_per_step = r["ms_per_step"]
+    value = r["queries_per_step"] / (ms_per_step / 1000.0)
+    # reference copy of known size for the byte counters of a separate --pmc run
+    r["ctx"].calib_copy(256 << 20)
+    r["ctx"].sync()
+    r["ctx"].close()
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        # the oracle's plain forest evaluation checks the labels of what was timed (decoded through the
-        # codebook, so that shuffled and padded results compare too)
-        from oracle import forest as F
-        _, trees = F.parse_forest(text)
-        book = C.compiled_codebook(comp)
-        oracle_book = F.codebook(trees)
-        for x, bits in zip(queries[:nq_group], first_bits):
-            plain = F.evaluate(trees, list(x))
-            if args.result_pad < 0:
-                assert list(bits) == list(plain), "decrypted labels differ from plain evaluation"
-            else:
-                assert sorted(book[s] for s in range(len(book)) if bits[s]) == \
-                    sorted(oracle_book[i] for i in range(len(plain)) if plain[i]), "decrypted labels differ"
-        cpu = cpu_baseline(w, text, queries, seed)
+    extra = {}
+    if r["plain"]:
+        extra["plain_path"] = dict(r["plain"], workload=w.name)
+        extra["batched_over_plain"] = round(value / r["plain"]["queries_per_s"], 2)
+    if headline_default and not args.no_extras:
+        for name, plain_g, stx in (("c3_batched_32x_d6", 1, 3), ("c2_forest16_d5", 0, 20)):
+            wx = synth.WORKLOADS[name]
+            rx = run_workload(wx, args, stx, 2, 0, 0, profile=False, plain_groups=plain_g, check_labels=check)
+            vx = rx["queries_per_step"] / (rx["ms_per_step"] / 1000.0)
+            e = {"value": round(vx, 3), "unit": "queries/s", "ms_per_step": round(rx["ms_per_step"], 3),
+                 "steps": stx, "queries_per_step": rx["queries_per_step"], "query_groups_per_step": rx["n_groups"],
+                 "groups_per_call": rx["batch"],
+                 "latency_ms": {"p50": round(percentile(rx["lat"], 50), 3),
+                                "p99": round(percentile(rx["lat"], 99), 3)},
+                 "labels_checked": rx["labels_checked"]}
+            if rx["plain"]:
+                e["plain_path"] = rx["plain"]
+                e["batched_over_plain"] = round(vx / rx["plain"]["queries_per_s"], 2)
+            extra[name] = e
+            rx["ctx"].close()
+            log(name, e)
 
     out = {
         "metric": METRIC,
-        "value": round(queries_per_step / (ms_per_step / 1000.0), 3),
+        "value": round(value, 3),
         "unit": "queries/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
@@ -541,22 +863,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "trees": w.shape.n_trees, "max_depth": w.shape.max_depth,
                    "features": w.shape.n_features, "precision": w.shape.precision, "classes": w.shape.n_classes,
-                   "queries_per_step": queries_per_step, "query_groups_per_step": args.batch,
+                   "queries_per_step": r["queries_per_step"], "query_groups_per_step": n_groups,
+                   "groups_per_call": batch,
                    "path": "plain (one group per call, one operation per launch)" if args.plain else
-                           (("batched" if args.batch > 1 else "single group") +
-                            (", captured graph" if args.graph else ", eager")),
-                   "N": 1 << w.log_n, "data_primes": ch["n_data_primes"], "special_primes": ch["alpha"],
+                           ("batched" if batch > 1 else "single group") + (", captured graph" if args.graph else ", eager"),
+                   "N": 1 << w.log_n, "data_primes": r["chain"]["n_data_primes"], "special_primes": r["chain"]["alpha"],
                    "model": "plaintext" if not w.encrypted_model else "encrypted",
+                   "model_GiB": round(r["model_bytes"] / 2**30, 2), "keys_GiB": round(r["keys_bytes"] / 2**30, 2),
                    "b": meta.b, "m": meta.m, "q": meta.q, "d": meta.d, "W": meta.block_w,
                    "result_pad": args.result_pad, "server_replication": bool(args.server_rep),
                    "n1_R": meta.n1_R, "n1_L": meta.n1_L},
-        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
+        "labels_checked": r["labels_checked"],
+        "latency_ms": {"p50": round(percentile(r["lat"], 50), 3), "p99": round(percentile(r["lat"], 99), 3),
                        "profiled_mean": round(sum(per_step) / len(per_step), 3)},
         "roofline": roofline,
         "kernels": kernels,
         "stages_ms_per_step": stages,
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     print(json.dumps(out))
 
 

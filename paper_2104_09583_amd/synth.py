@@ -53,6 +53,8 @@ class Workload:
     # baby steps of the reshuffle and level products (0: the compiler's square-root rule); a measured
     # choice where it beats the rule on the GPU
     n1: tuple = (0, 0)
+    # query groups evaluated together per batched call when every group of the workload is timed
+    batch: int = 1
 
 
 def _gen_tree(rng: np.random.Generator, shape: ForestShape, depth: int, out: list) -> None:
@@ -119,10 +121,11 @@ WORKLOADS = {
         "16 random unbalanced trees, max depth 5, one query, N=32768", CHAIN_32K_P8, n1=(16, 0)),
     "c3_batched_32x_d6": Workload(
         "c3_batched_32x_d6", ForestShape(32, 6, 0.7, 16, 8, 8), 1024, 15, False, 3,
-        "1024 queries against 32 trees of max depth 6, N=32768", CHAIN_32K_P8, n1=(0, 16)),
+        "1024 queries against 32 trees of max depth 6, N=32768", CHAIN_32K_P8, n1=(0, 16), batch=16),
     "c4_encmodel_64x_d8": Workload(
         "c4_encmodel_64x_d8", ForestShape(64, 8, 0.7, 32, 16, 10), 256, 15, True, 4,
-        "encrypted model and queries, 64 trees max depth 8, 16-bit, N=32768", CHAIN_32K_P16, n1=(0, 128)),
+        "encrypted model and queries, 64 trees max depth 8, 16-bit, N=32768", CHAIN_32K_P16, n1=(0, 128),
+        batch=8),
     "c5_serve_8x_d4": Workload(
         "c5_serve_8x_d4", ForestShape(8, 4, 0.7, 16, 8, 4), 1, 15, False, 5,
         "serving mix member: 8 trees of depth 4", CHAIN_32K_P16),
