@@ -257,6 +257,23 @@ int copse_cts_level(const copse_cts* c, size_t i);
  */
 int copse_evaluate(copse_ctx* ctx, const copse_model* model, const copse_keys* keys,
                    const copse_cts* query, copse_cts** result);
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid hipMalloc):
+ * copse_evaluate without any device allocation or release.  Every temporary of the evaluation lives in one
+ * device array of the library, COPSE_NOALLOC_SCRATCH_BYTES (1 GiB) per GPU, held from the library's load
+ * until the process ends; the result is written into `result`, an existing handle holding exactly one
+ * ciphertext of this ring at level 0 with 2 polynomials (for instance the result of an earlier
+ * copse_evaluate on the same model), whose previous contents are overwritten.  The bits equal
+ * copse_evaluate's.  The call returns after the evaluation has finished on the device (it waits for the
+ * context's stream), so it is not for use under stream capture.  Calls on one GPU share the array: the
+ * library serializes them within a process (a call holds the array until its work has finished), and the
+ * array keeps the last call's contents.  Requires a context created by copse_ctx_create (which builds the
+ * per-level tables and looks up the array).  Errors: ENOMEM when the evaluation's working set exceeds the
+ * array (found during the first such call, which then leaves `result` unchanged; later calls with that
+ * model are refused before any work is enqueued), EINVAL (shapes, as copse_evaluate, or a wrong `result`),
+ * EKEY, EDEVICE. */
+#define COPSE_NOALLOC_SCRATCH_BYTES ((size_t)1 << 30)
+int copse_evaluate_noalloc(copse_ctx* ctx, const copse_model* model, const copse_keys* keys,
+                           const copse_cts* query, copse_cts* result);
 /* The unbatched reference path: one homomorphic operation per call (every
  * rotation its own key switch, every product its own launches), same
  * schedule and the same result bits as copse_evaluate. */

@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         "copse_evaluate": [P, P, P, P, PP],
         "copse_evaluate_batch": [P, P, P, PP, sz, PP],
         "copse_evaluate_plain": [P, P, P, P, PP],
+        "copse_evaluate_noalloc": [P, P, P, P, P],
         "copse_exec_create": [P, P, P, sz, PP],
         "copse_exec_run": [P, PP, sz, PP],
         "copse_decrypt_labels": [P, P, ctypes.POINTER(Meta), P, sz, u8p, sz],
@@ -288,6 +289,11 @@ class Context(_Handle):
         h = ctypes.c_void_p()
         check(lib().copse_evaluate(self.ptr, model.ptr, keys.ptr, query.ptr, ctypes.byref(h)))
         return Cts(h, self)
+
+    def evaluate_noalloc(self, model: Model, keys: Keys, query: Cts, result: Cts) -> None:
+        """copse_evaluate into the existing one-ciphertext handle `result`, every temporary in the library's
+        scratch array (no device allocation); returns after the device has finished."""
+        check(lib().copse_evaluate_noalloc(self.ptr, model.ptr, keys.ptr, query.ptr, result.ptr))
 
     def evaluate_plain(self, model: Model, keys: Keys, query: Cts) -> Cts:
         h = ctypes.c_void_p()

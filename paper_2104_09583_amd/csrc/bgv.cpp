@@ -86,6 +86,18 @@ Context::~Context() {
 const int2* Context::rows(const std::string& key, const std::vector<int2>& host) {
   auto it = row_tables.find(key);
   if (it != row_tables.end()) return it->second;
+  if (no_alloc) {
+    // built in the scratch pool for this call only; the host copy lives until the call has synchronized
+    auto ic = call_rows.find(key);
+    if (ic != call_rows.end()) return ic->second;
+    call_row_bufs.emplace_back(this, (std::max<size_t>(1, host.size()) * sizeof(int2) + 7) / 8);
+    call_rows_host.push_back(host);
+    int2* d = reinterpret_cast<int2*>(call_row_bufs.back().get());
+    COPSE_HIP(hipMemcpyAsync(d, call_rows_host.back().data(), host.size() * sizeof(int2), hipMemcpyHostToDevice,
+                             stream));
+    call_rows[key] = d;
+    return d;
+  }
   int2* d = nullptr;
   COPSE_HIP(hipMalloc(&d, std::max<size_t>(1, host.size()) * sizeof(int2)));
   COPSE_HIP(hipMemcpy(d, host.data(), host.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -113,6 +125,7 @@ static double* upload(std::vector<double*>& owner, const std::vector<double>& v)
 KSTables& Context::kstab(int level) {
   auto it = ks.find(level);
   if (it != ks.end()) return *it->second;
+  if (no_alloc) fail(COPSE_EINVAL, "internal: level tables missing in an evaluation without allocation");
   auto T = std::make_unique<KSTables>();
   const int nl = level + 1, nE = nl + alpha;
   auto prime_of_ext = [&](int o) { return o < nl ? o : L + 1 + (o - nl); };
@@ -228,6 +241,7 @@ const MsMulti& Context::ms_multi(int level, int k) {
   KSTables& T = kstab(level);
   auto it = T.multi.find(k);
   if (it != T.multi.end()) return it->second;
+  if (no_alloc) fail(COPSE_EINVAL, "internal: switch tables missing in an evaluation without allocation");
   MsMulti M;
   const int n_out = level - k + 1;
   std::vector<uint64_t> pm;   // p_m = q_{level - m}
@@ -262,6 +276,13 @@ const MsMulti& Context::ms_multi(int level, int k) {
   M.in_rows = rows("mskin:" + std::to_string(level) + ":" + std::to_string(k), ir);
   M.out_rows = rows("mskout:" + std::to_string(level) + ":" + std::to_string(k), orr);
   return T.multi.emplace(k, M).first->second;
+}
+
+void Context::build_level_tables() {
+  for (int l = 0; l <= L; ++l) {
+    kstab(l);
+    for (int k = 1; k <= std::min(4, l); ++k) ms_multi(l, k);
+  }
 }
 
 uint64_t galois_of(const Context& c, int64_t r) {

@@ -143,6 +143,10 @@ int copse_ctx_create(const copse_params* p, copse_ctx** out) {
     COPSE_HIP(hipMalloc(&c->d_primes, dp.size() * sizeof(DevPrime)));
     COPSE_HIP(hipMemcpy(c->d_primes, dp.data(), dp.size() * sizeof(DevPrime), hipMemcpyHostToDevice));
     setup_slots(*c);
+    // every level's key-switching and modulus-switching tables now, and the scratch array's address on this
+    // device: an evaluation without allocation (copse_evaluate_noalloc) then finds everything it reads
+    c->build_level_tables();
+    scratch_acquire(p->device);
     ctx->c = std::move(c);
     *out = ctx.release();
   });
@@ -363,6 +367,16 @@ int copse_evaluate(copse_ctx* ctx, const copse_model* model, const copse_keys* k
     auto r = std::make_unique<copse_cts>();
     r->v.push_back(evaluate_group(*ctx->c, *model->m, *keys->k, planes));
     *result = r.release();
+  });
+}
+
+int copse_evaluate_noalloc(copse_ctx* ctx, const copse_model* model, const copse_keys* keys, const copse_cts* query,
+                           copse_cts* result) {
+  return guarded([&] {
+    NEED(ctx && model && keys && query && result && result->v.size() == 1 && result->v[0]);
+    std::vector<const Ct*> planes;
+    for (auto& p : query->v) planes.push_back(p.get());
+    evaluate_group_noalloc(*ctx->c, *model->m, *keys->k, planes, *result->v[0]);
   });
 }
 

@@ -101,6 +101,10 @@ struct Model {
   std::vector<std::vector<Operand>> ldiag;      // d x (b or q) diagonals of the level matrices
   std::vector<Operand> masks;
   size_t bytes = 0;
+  // evaluations without allocation (noalloc.hip): the largest scratch working set seen, and whether one
+  // did not fit the scratch array (later calls are then refused before anything is enqueued)
+  mutable size_t noalloc_peak = 0;
+  mutable bool noalloc_too_big = false;
 };
 
 std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k, bool encrypt_model,
@@ -112,6 +116,10 @@ CtPtr evaluate_group(Context& c, const Model& M, const Keys& k, const std::vecto
 CtPtr evaluate_group_plain(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes);
 std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
                                    const std::vector<std::vector<const Ct*>>& groups);
+// evaluate_group with every temporary in the scratch array; the result is written to `out` (level 0,
+// 2 polys); returns after the device has finished
+void evaluate_group_noalloc(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes,
+                            Ct& out);
 
 }  // namespace copse
 

@@ -84,9 +84,9 @@ class Pool {
  public:
   // keep_cached: never release cached blocks (a captured graph may still address them)
   explicit Pool(int device, bool keep_cached = false) : device_(device), keep_cached_(keep_cached) {}
-  ~Pool();
-  void* alloc(size_t bytes);
-  void free(void* p);
+  virtual ~Pool();
+  virtual void* alloc(size_t bytes);
+  virtual void free(void* p);
   size_t held() const { return held_; }
   void trim();
 
@@ -168,6 +168,13 @@ struct Context {
   std::vector<uint32_t> slot_pos; // slot (r,j) -> natural evaluation index (host encode)
   std::map<int, std::unique_ptr<KSTables>> ks;   // by level
   std::map<std::string, int2*> row_tables;       // cached device row lists
+  // set while an evaluation runs without device allocation (noalloc.hip): every buffer comes from `pool`
+  // (the scratch array), a row list missing from row_tables is built in the pool for that call only (its
+  // host copy kept until the call has synchronized), and the per-level tables must already exist
+  bool no_alloc = false;
+  std::map<std::string, int2*> call_rows;
+  std::vector<std::vector<int2>> call_rows_host;
+  std::vector<DBuf> call_row_bufs;
   bool profiling = false;
   ProfSlot prof[kProfKinds];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kProfKinds];
@@ -180,6 +187,8 @@ struct Context {
   KSTables& kstab(int level);
   // constants of the switch from `level` by k primes at once (1 <= k <= min(4, level))
   const struct MsMulti& ms_multi(int level, int k);
+  // builds the tables of every level up front (so that no later call has to allocate them)
+  void build_level_tables();
   ~Context();
 };
 
@@ -441,6 +450,11 @@ inline void launch_copy(Context& c, double* dst, const double* src, size_t n) { 
 void prof_begin(Context& c, int kind, hipEvent_t* ev);
 void prof_end(Context& c, int kind, hipEvent_t ev, double bytes);
 void prof_collect(Context& c);
+
+// ------------------------------------------------------------------ evaluation without allocation (noalloc.hip)
+// Device address of the library's scratch array on `device` (looked up once per device; the device must be
+// current).  Called when a context is created.
+void scratch_acquire(int device);
 
 // ------------------------------------------------------------------ BGV operations (bgv.cpp)
 struct Keys {

@@ -1,0 +1,109 @@
+"""The evaluation entry point that allocates no device memory (copse_evaluate_noalloc): its result is
+bit-identical to copse_evaluate's, on two calls in a row (the second with a smaller forest, so that it
+reuses the scratch array the first one left behind), and an evaluation too large for the array is refused
+with ENOMEM, again before any work on the next try, while the other entry points keep working."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import circuit as CI
+from oracle import compiler as OC
+from oracle import forest as F
+from paper_2104_09583_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+def _bits(ctx, cts):
+    ex = ctx.export(cts)[0]
+    return ex["level"], [p.copy() for p in ex["polys"]]
+
+
+def _setup(C, ctx, shape, seed_forest, kseed, log_n):
+    text = synth.gen_forest_text(shape, seed_forest)
+    comp, meta = C.forest_compile(text, shape.n_features, shape.precision, log_n)
+    keys = ctx.keygen(kseed, C.compiled_rotations(meta))
+    return text, comp, meta, keys
+
+
+def test_noalloc_equals_evaluate_two_calls():
+    from paper_2104_09583_amd import copse as C
+    shape_a = synth.ForestShape(5, 5, 0.8, 4, 4, 3)
+    shape_b = synth.ForestShape(2, 3, 0.7, 3, 4, 2)
+    log_n = 13
+    oc = OC.compile_forest(synth.gen_forest_text(shape_a, 61), 4, 4)
+    need = CI.seccomp_depth(4) + 2 + math.ceil(math.log2(max(2, oc.d)))
+    ctx = C.Context(log_n, need + 1, 1 << 49, 1 << 42, 3, 1 << 49)
+    kseed = b"\x52" * 32
+    runs = []
+    for shape, fs, qseed in ((shape_a, 61, 801), (shape_b, 62, 802)):
+        text, comp, meta, keys = _setup(C, ctx, shape, fs, kseed, log_n)
+        evk = ctx.export_eval(keys)
+        model = ctx.model_encode(comp)
+        q = synth.gen_queries(meta.queries_per_ct, shape.n_features, shape.precision, qseed)
+        qct = ctx.query_encrypt(keys, meta, q, kseed, group=0)
+        runs.append((text, meta, keys, evk, model, q, qct))
+    # the result handles: ordinary evaluations of the other model, so each is overwritten with new bits
+    results = [ctx.evaluate(runs[1][4], runs[1][3], runs[1][6]), ctx.evaluate(runs[0][4], runs[0][3], runs[0][6])]
+    ctx.sync()
+    for i, (text, meta, keys, evk, model, q, qct) in enumerate(runs):
+        say("no-alloc call", i, "b", meta.b, "d", meta.d)
+        want = _bits(ctx, ctx.evaluate(model, evk, qct))
+        before = ctx.device_bytes()
+        ctx.evaluate_noalloc(model, evk, qct, results[i])
+        assert ctx.device_bytes() == before          # the context's pool was not touched
+        got = _bits(ctx, results[i])
+        assert got[0] == want[0] == 0
+        assert all((a == b).all() for a, b in zip(got[1], want[1])), f"call {i}"
+        _, trees = F.parse_forest(text)
+        bits = ctx.decrypt_labels(keys, meta, results[i], len(q))
+        assert (bits == np.array([F.evaluate(trees, list(x)) for x in q])).all()
+    # a repeat of the first model after the smaller one: the array's leftovers do not matter
+    text, meta, keys, evk, model, q, qct = runs[0]
+    ctx.evaluate_noalloc(model, evk, qct, results[1])
+    want = _bits(ctx, ctx.evaluate(model, evk, qct))
+    got = _bits(ctx, results[1])
+    assert all((a == b).all() for a, b in zip(got[1], want[1]))
+
+
+def test_noalloc_rejects_wrong_result_handle():
+    from paper_2104_09583_amd import copse as C
+    shape = synth.ForestShape(2, 3, 0.7, 3, 4, 2)
+    ctx = C.Context(13, 8, 1 << 49, 1 << 42, 3, 1 << 49)
+    kseed = b"\x53" * 32
+    text, comp, meta, keys = _setup(C, ctx, shape, 63, kseed, 13)
+    model = ctx.model_encode(comp)
+    qct = ctx.query_encrypt(keys, meta, synth.gen_queries(1, 3, 4, 5), kseed, group=0)
+    with pytest.raises(C.CopseError) as e:
+        ctx.evaluate_noalloc(model, keys, qct, qct)   # p ciphertexts at the top level: not a result handle
+    assert e.value.code == C.COPSE_EINVAL
+
+
+def test_noalloc_refuses_a_working_set_beyond_the_array():
+    """The encrypted-model workload's batched products need far more than the array: ENOMEM, the result
+    handle unchanged, the next call refused at once, and the ordinary path still right afterwards."""
+    from paper_2104_09583_amd import copse as C
+    w = synth.WORKLOADS["c5_serve_64x_d8"]
+    text, queries, seed = synth.workload_inputs(w)
+    ctx = C.Context(**w.chain)
+    comp, meta = C.forest_compile(text, w.shape.n_features, w.shape.precision, w.log_n)
+    keys = ctx.keygen(seed, C.compiled_rotations(meta))
+    model = ctx.model_encode(comp)
+    qct = ctx.query_encrypt(keys, meta, queries[:1], seed, group=0)
+    res = ctx.evaluate(model, keys, qct)
+    want = _bits(ctx, res)
+    for attempt in range(2):
+        say("oversized no-alloc call", attempt)
+        with pytest.raises(C.CopseError) as e:
+            ctx.evaluate_noalloc(model, keys, qct, res)
+        assert e.value.code == C.COPSE_ENOMEM
+    got = _bits(ctx, res)
+    assert all((a == b).all() for a, b in zip(got[1], want[1]))
+    again = _bits(ctx, ctx.evaluate(model, keys, qct))
+    assert all((a == b).all() for a, b in zip(again[1], want[1]))
