@@ -315,10 +315,15 @@ void copse_exec_destroy(copse_exec* exec);
 
 /* ---------------------------------------------------------------- decrypt */
 /*
- * Data owner: decrypts a level-0 result, checks the noise (the centered
+ * Data owner (Section 4.1, "Classification Result"; Section 3.2, "The
+ * Workflow"): decrypts a level-0 result, checks the noise (the centered
  * phase must stay below q_0 / 2^11, else ENOISE), decodes the slots and
  * writes bits[i*m + j] = label j of query i (0/1; any other value -> ENOISE)
- * for i < n_queries.  cap = size of bits.
+ * for i < n_queries, and checks that each query's vector is N-hot: exactly
+ * meta->n_trees ones, one label per tree (else ENOISE; padding labels of a
+ * private result are never set).  cap = size of bits.  Errors: EINVAL
+ * (layout of another ring, too many queries, small buffer, keys or result of
+ * another context), ENOISE.
  */
 int copse_decrypt_labels(copse_ctx* ctx, const copse_keys* keys, const copse_public_meta* meta,
                          const copse_cts* result, size_t n_queries, uint8_t* bits, size_t cap);

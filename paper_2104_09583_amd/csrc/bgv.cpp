@@ -424,6 +424,7 @@ std::unique_ptr<Keys> keygen(Context& c, const uint8_t seed[32], const std::vect
   const size_t N = c.N;
   const int Lt = c.n_primes();
   auto K = std::make_unique<Keys>();
+  K->primes = c.primes;
   K->has_secret = true;
   K->s_host.resize(N);
   sample_ternary(seed, "sk.s", 0, N, K->s_host.data());

@@ -31,6 +31,19 @@ static int guarded(F f) {
     if (!(x)) fail(COPSE_EINVAL, "invalid argument: " #x);           \
   } while (0)
 
+// handles made by another context would make the kernels read past their buffers: refuse them
+static const Keys& keys_of(const Context& c, const copse_keys* k) {
+  if (k->k->primes != c.primes) fail(COPSE_EINVAL, "keys belong to another context");
+  return *k->k;
+}
+static const Ct& ct_of(const Context& c, const copse_cts* x, size_t i) {
+  if (!x || i >= x->v.size() || !x->v[i]) fail(COPSE_EINVAL, "invalid argument: ciphertext index");
+  const Ct& ct = *x->v[i];
+  if (ct.n != c.N || ct.level < 0 || ct.level > c.L || ct.npolys < 2 || ct.npolys > 3)
+    fail(COPSE_EINVAL, "ciphertext of another ring or chain");
+  return ct;
+}
+
 namespace {
 std::vector<uint64_t> primes_below(uint64_t bound, uint64_t modulus, int count, const std::vector<uint64_t>& taken) {
   std::vector<uint64_t> out;
@@ -285,7 +298,9 @@ int copse_keys_export_eval(copse_ctx* ctx, const copse_keys* k, copse_keys** out
         COPSE_HIP(hipMemcpyAsync(d.get(), src.get(), src.size() * 8, hipMemcpyDeviceToDevice, c.stream));
       return d;
     };
+    if (k->k->primes != c.primes) fail(COPSE_EINVAL, "keys belong to another context");
     auto e = std::make_unique<Keys>();
+    e->primes = c.primes;
     e->has_secret = false;
     e->pk_a = copy(k->k->pk_a);
     e->pk_b = copy(k->k->pk_b);
@@ -346,7 +361,7 @@ int copse_query_encrypt(copse_ctx* ctx, const copse_keys* keys, const copse_publ
       query_plane_slots(*meta, c.N, features, n_queries, k, slots);
       std::vector<int64_t> poly;
       encode_slots(c, slots.data(), poly);
-      cts->v.push_back(encrypt(c, *keys->k, poly, c.L, seed, (1ULL << 56) | ((uint64_t)group << 32) | k));
+      cts->v.push_back(encrypt(c, keys_of(c, keys), poly, c.L, seed, (1ULL << 56) | ((uint64_t)group << 32) | k));
     }
     *out = cts.release();
   });
@@ -448,8 +463,11 @@ int copse_decrypt_labels(copse_ctx* ctx, const copse_keys* keys, const copse_pub
   return guarded([&] {
     NEED(ctx && keys && meta && result && bits && result->v.size() == 1);
     Context& c = *ctx->c;
-    const Ct& ct = *result->v[0];
-    if (ct.level != 0) fail(COPSE_EINVAL, "result must be at level 0");
+    const Ct& ct = ct_of(c, result, 0);
+    keys_of(c, keys);
+    if (ct.level != 0 || ct.npolys != 2) fail(COPSE_EINVAL, "result must be at level 0");
+    if ((1ULL << meta->log_n) != c.N || meta->block_w == 0 || meta->block_w > c.N / 2 || meta->m > meta->block_w)
+      fail(COPSE_EINVAL, "layout made for another ring size");
     if (n_queries > meta->queries_per_ct) fail(COPSE_EINVAL, "more queries than blocks");
     if (cap < n_queries * meta->m) fail(COPSE_EINVAL, "bits buffer too small");
     std::vector<uint64_t> ph;
@@ -471,11 +489,17 @@ int copse_decrypt_labels(copse_ctx* ctx, const copse_keys* keys, const copse_pub
     size_t bpr = (c.N / 2) / meta->block_w;
     for (size_t k = 0; k < n_queries; ++k) {
       size_t row = k / bpr, col0 = (k % bpr) * meta->block_w;
+      uint32_t ones = 0;
       for (uint32_t j = 0; j < meta->m; ++j) {
         uint64_t v = slots[row * (c.N / 2) + col0 + j];
         if (v > 1) fail(COPSE_ENOISE, "decrypted label slot is not a bit");
         bits[k * meta->m + j] = (uint8_t)v;
+        ones += (uint32_t)v;
       }
+      // the result is N-hot: exactly one label per tree (Section 4.1, "Classification Result")
+      if (ones != meta->n_trees)
+        fail(COPSE_ENOISE, "query " + std::to_string(k) + " decrypts to " + std::to_string(ones) + " labels for " +
+                               std::to_string(meta->n_trees) + " trees");
     }
   });
 }
@@ -490,7 +514,7 @@ int copse_encrypt_slots(copse_ctx* ctx, const copse_keys* keys, const uint64_t* 
     std::vector<int64_t> poly;
     encode_slots(c, slots, poly);
     auto r = std::make_unique<copse_cts>();
-    r->v.push_back(encrypt(c, *keys->k, poly, level, seed, obj));
+    r->v.push_back(encrypt(c, keys_of(c, keys), poly, level, seed, obj));
     *out = r.release();
   });
 }
@@ -499,9 +523,9 @@ int copse_decrypt_slots(copse_ctx* ctx, const copse_keys* keys, const copse_cts*
   return guarded([&] {
     NEED(ctx && keys && cts && slots && i < cts->v.size());
     Context& c = *ctx->c;
-    const Ct& ct = *cts->v[i];
+    const Ct& ct = ct_of(c, cts, i);
     std::vector<uint64_t> ph;
-    phase_coef(c, *keys->k, ct, ph);
+    phase_coef(c, keys_of(c, keys), ct, ph);
     // exact CRT of each coefficient over q_0..q_level, centered, mod t (Garner's mixed radix)
     const int nl = ct.level + 1;
     std::vector<uint64_t> coef(c.N);
@@ -600,14 +624,14 @@ int copse_ct_op(copse_ctx* ctx, const copse_keys* keys, int op, const copse_cts*
     NEED(ctx && a && ia < a->v.size() && out);
     *out = nullptr;
     Context& c = *ctx->c;
-    const Ct& x = *a->v[ia];
+    const Ct& x = ct_of(c, a, ia);
     auto needb = [&]() -> const Ct& {
-      NEED(b && ib < b->v.size());
-      return *b->v[ib];
+      NEED(b);
+      return ct_of(c, b, ib);
     };
     auto needk = [&]() -> const Keys& {
       NEED(keys);
-      return *keys->k;
+      return keys_of(c, keys);
     };
     CtPtr r;
     switch (op) {
@@ -644,7 +668,7 @@ int copse_ct_rotate_many(copse_ctx* ctx, const copse_keys* keys, const copse_cts
   return guarded([&] {
     NEED(ctx && keys && a && ia < a->v.size() && rots && out);
     std::vector<int32_t> r(rots, rots + n);
-    auto v = op_rotate_hoisted(*ctx->c, *keys->k, *a->v[ia], r);
+    auto v = op_rotate_hoisted(*ctx->c, keys_of(*ctx->c, keys), ct_of(*ctx->c, a, ia), r);
     auto res = std::make_unique<copse_cts>();
     for (auto& x : v) res->v.push_back(std::move(x));
     COPSE_HIP(hipStreamSynchronize(ctx->c->stream));

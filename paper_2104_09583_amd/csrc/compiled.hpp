@@ -84,6 +84,7 @@ struct MatPlan {
 };
 
 struct Model {
+  std::vector<uint64_t> primes;                 // chain of the context the model was encoded for
   copse_public_meta meta;
   MatPlan plan_R;
   std::vector<MatPlan> plan_L;
@@ -116,6 +117,9 @@ CtPtr evaluate_group(Context& c, const Model& M, const Keys& k, const std::vecto
 CtPtr evaluate_group_plain(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes);
 std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
                                    const std::vector<std::vector<const Ct*>>& groups);
+// EINVAL unless the model, the keys and every query plane belong to this context and fit its chain
+void check_evaluation(const Context& c, const Model& M, const Keys& k,
+                      const std::vector<std::vector<const Ct*>>& groups);
 // evaluate_group with every temporary in the scratch array; the result is written to `out` (level 0,
 // 2 polys); returns after the device has finished
 void evaluate_group_noalloc(Context& c, const Model& M, const Keys& k, const std::vector<const Ct*>& planes,

@@ -769,16 +769,27 @@ static std::vector<SCt> b_sum_all(Context& c, const std::vector<std::vector<SCt>
 }
 
 // ------------------------------------------------------------------ the evaluation
+void check_evaluation(const Context& c, const Model& M, const Keys& k,
+                      const std::vector<std::vector<const Ct*>>& groups) {
+  if (M.primes != c.primes || (1ULL << M.meta.log_n) != c.N || M.top_level > c.L)
+    fail(COPSE_EINVAL, "model encoded for another context");
+  if (k.primes != c.primes) fail(COPSE_EINVAL, "keys belong to another context");
+  const size_t p = M.meta.precision;
+  for (auto& g : groups) {
+    if (g.size() != p) fail(COPSE_EINVAL, "query group must hold one ciphertext per bit plane");
+    for (auto* x : g) {
+      if (!x || x->n != c.N) fail(COPSE_EINVAL, "query ciphertext of another ring");
+      if (x->npolys != 2 || x->level != c.L) fail(COPSE_EINVAL, "query ciphertexts must be fresh (top level)");
+    }
+  }
+}
+
 std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
                                    const std::vector<std::vector<const Ct*>>& groups) {
   const int G = (int)groups.size();
   const int p = (int)M.meta.precision;
   const size_t N = c.N;
-  for (auto& g : groups) {
-    if ((int)g.size() != p) fail(COPSE_EINVAL, "query group must hold one ciphertext per bit plane");
-    for (auto* x : g)
-      if (x->npolys != 2 || x->level != c.L) fail(COPSE_EINVAL, "query ciphertexts must be fresh (top level)");
-  }
+  check_evaluation(c, M, k, groups);
   auto view = [](const Ct* x) { return SCt(const_cast<Ct*>(x), [](Ct*) {}); };
   // stage timings for the profiler (comparison, reshuffle, levels, aggregation; Section 8's breakdown)
   hipEvent_t stage_ev = nullptr;

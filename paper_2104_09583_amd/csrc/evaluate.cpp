@@ -35,7 +35,9 @@ std::unique_ptr<Model> build_model(Context& c, const Compiled& C, const Keys* k,
   const copse_public_meta& meta = C.meta;
   if ((1ULL << meta.log_n) != c.N) fail(COPSE_EINVAL, "forest compiled for another ring size");
   if (encrypt_model && (!k || !k->pk_b.get())) fail(COPSE_EKEY, "public key needed to encrypt the model");
+  if (k && k->primes != c.primes) fail(COPSE_EINVAL, "keys belong to another context");
   auto M = std::make_unique<Model>();
+  M->primes = c.primes;
   M->meta = meta;
   M->encrypted = encrypt_model;
   if (meta.server_rep && encrypt_model) fail(COPSE_EINVAL, "server-side replication is for a server-held model");

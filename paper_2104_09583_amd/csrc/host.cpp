@@ -279,6 +279,8 @@ void* Pool::alloc(size_t bytes) {
     held_ += sz;
   }
   live_[p] = sz;
+  live_bytes_ += sz;
+  peak_bytes_ = std::max(peak_bytes_, live_bytes_);
   return p;
 }
 
@@ -288,7 +290,23 @@ void Pool::free(void* p) {
   auto it = live_.find(p);
   if (it == live_.end()) return;
   cache_[it->second].push_back(p);
+  live_bytes_ -= it->second;
   live_.erase(it);
+}
+
+size_t Pool::live_bytes() {
+  std::lock_guard<std::mutex> lk(mu_);
+  return live_bytes_;
+}
+
+size_t Pool::peak_bytes() {
+  std::lock_guard<std::mutex> lk(mu_);
+  return peak_bytes_;
+}
+
+void Pool::reset_peak() {
+  std::lock_guard<std::mutex> lk(mu_);
+  peak_bytes_ = live_bytes_;
 }
 
 void Pool::trim() {

@@ -89,13 +89,17 @@ class Pool {
   virtual void free(void* p);
   size_t held() const { return held_; }
   void trim();
+  // bytes handed out and not yet freed, and the most that has been since the last reset_peak
+  size_t live_bytes();
+  size_t peak_bytes();
+  void reset_peak();
 
  private:
   int device_;
   bool keep_cached_;
   std::map<size_t, std::vector<void*>> cache_;
   std::map<void*, size_t> live_;
-  size_t held_ = 0;
+  size_t held_ = 0, live_bytes_ = 0, peak_bytes_ = 0;
   std::mutex mu_;
 };
 
@@ -458,6 +462,7 @@ void scratch_acquire(int device);
 
 // ------------------------------------------------------------------ BGV operations (bgv.cpp)
 struct Keys {
+  std::vector<uint64_t> primes;   // chain of the context the keys belong to
   bool has_secret = false;
   DBuf s;          // NTT form over all primes [Ltot][N]
   std::vector<int64_t> s_host;   // ternary coefficients

@@ -133,9 +133,7 @@ struct Plain1 {
   }
 
   CtPtr run(const std::vector<const Ct*>& X) {
-    if (X.size() != M.meta.precision) fail(COPSE_EINVAL, "query group must hold one ciphertext per bit plane");
-    for (auto* x : X)
-      if (x->npolys != 2 || x->level != c.L) fail(COPSE_EINVAL, "query ciphertexts must be fresh (top level)");
+    check_evaluation(c, M, k, {X});
     std::vector<SCt> rep;
     std::vector<const Ct*> planes = X;
     if (M.meta.server_rep) {
