@@ -103,13 +103,19 @@ typedef struct {
   uint32_t fold;         /* 1: level matrices composed with R (one product less) */
   uint32_t depth;        /* modulus switches the evaluation consumes */
   uint32_t log_n;        /* ring the layout was made for */
-  uint32_t server_rep;   /* 1: queries hold each feature once; the server replicates (Section 6) */
+  uint32_t server_rep;   /* 1: queries hold each feature once; the server replicates (Section 7.2.1) */
   uint32_t n1_F;         /* baby steps of the replication product */
 } copse_public_meta;
 
 /* ---------------------------------------------------------------- context */
-/* Creates the prime chain and device tables.  Errors: EINVAL (t not 1 mod
- * 2N, bounds too small, alpha 0, more than 48 primes), EDEVICE. */
+/* Creates the prime chain and device tables: the encryption parameters of
+ * Section 8.1 (Table 5: security level, modulus bits, key-switching columns),
+ * reinterpreted as a ring, an RNS chain within the HE-standard bound and
+ * digits of alpha primes.  Also builds every level's key-switching and
+ * modulus-switching tables and looks up the scratch array of
+ * copse_evaluate_noalloc on params->device.  Ownership: the context owns its
+ * stream, tables and memory pool until copse_ctx_destroy.  Errors: EINVAL
+ * (t not 1 mod 2N, bounds too small, alpha 0, more than 48 primes), EDEVICE. */
 int copse_ctx_create(const copse_params* params, copse_ctx** out);
 void copse_ctx_destroy(copse_ctx* ctx);
 /* Writes the primes (q_0..q_L then p_0..p_{alpha-1}) to out[0..cap); *n gets
@@ -144,7 +150,8 @@ int copse_forest_compile(const char* text, size_t len, uint32_t n_features, uint
                          uint32_t log_n, int fold, uint32_t n1_R, uint32_t n1_L,
                          copse_compiled** out, copse_public_meta* meta);
 /* All compile options at once (the calls above and below are shorthands).
- * server_replication (Section 6, alternative to replicated queries): queries
+ * server_replication (Section 7.2.1, "Feature padding": the alternative to
+ * replicated queries): queries
  * hold each feature once, extended with period F over B_in + F - 1 slots, so
  * the feature multiplicity K is not revealed; the server maps them onto the
  * padded layout with one plaintext matrix product before the comparison (one
@@ -161,7 +168,7 @@ typedef struct {
 } copse_compile_options;
 int copse_forest_compile_ex(const char* text, size_t len, uint32_t n_features, uint32_t precision, uint32_t log_n,
                             const copse_compile_options* opts, copse_compiled** out, copse_public_meta* meta);
-/* Result privacy (Section 6, "Returning classification bitvectors"): as
+/* Result privacy (Section 7.2.2, "Returning classification bitvectors"): as
  * copse_forest_compile, then the result slots are shuffled by a permutation
  * drawn from `seed` (32 bytes, the model owner's) and padded with n_pad
  * labels that are never selected, folded into the level matrices and masks
@@ -182,7 +189,8 @@ int copse_compiled_rotations(const copse_public_meta* meta, int32_t* out, size_t
 
 /* ---------------------------------------------------------------- keys */
 /*
- * Key generation (data owner).  All randomness comes from SHAKE-256 streams
+ * Key generation (data owner; Section 3.2, "The Workflow": the data owner
+ * holds the secret key, the server receives only what it needs to evaluate).  All randomness comes from SHAKE-256 streams
  * SHAKE256(seed[32] || domain || le64(object) || le32(limb)) read from the
  * start: uniform mod q = 8 bytes LE masked to bitlen(q), accepted if < q;
  * ternary = one byte, 255 rejected, b mod 3 -> {0, 1, -1}; error = centered
@@ -200,13 +208,16 @@ int copse_compiled_rotations(const copse_public_meta* meta, int32_t* out, size_t
 int copse_keygen(copse_ctx* ctx, const uint8_t seed[32], const int32_t* rots, size_t n_rots,
                  int relin, copse_keys** out);
 void copse_keys_destroy(copse_keys* k);
-/* Copy without the secret key (what the server receives). */
+/* Copy without the secret key (what the server receives; Section 3.2, "The
+ * Workflow").  Errors: EINVAL (keys of another context). */
 int copse_keys_export_eval(copse_ctx* ctx, const copse_keys* k, copse_keys** out);
 /* Device bytes held by the keys. */
 size_t copse_keys_bytes(const copse_keys* k);
 
 /* ---------------------------------------------------------------- model */
 /*
+ * Section 5, "COPSE Runtime" (encrypting a model) and Table 1e (the model
+ * owner encrypts thresholds, reshuffle and level matrices and masks once).
  * Encodes the compiled model (server-held plaintext model, encrypt_model=0)
  * or encrypts it under `keys` (encrypt_model=1, seed for its randomness).
  * Plaintext slot vectors are encoded as m(X) with slot (r, j) = m(zeta^e),
@@ -222,7 +233,9 @@ size_t copse_model_bytes(const copse_model* m);
 
 /* ---------------------------------------------------------------- queries */
 /*
- * Data owner: replicates each feature K times (feature-major), slices the p
+ * Data owner (Section 3.3, "Step 0: Features": the feature vector is
+ * replicated K times; Section 4.1.2, "Representing Non-integral Values":
+ * fixed-point values sliced into p bit planes): replicates each feature K times (feature-major), slices the p
  * bit-planes (plane k = bit k), extends each block cyclically (slot s of a
  * block holds padded position s mod q for s < m+b+q-2, 0 beyond), puts
  * query i of the group in block i (row i / (N/2W), offset (i mod N/2W) W),

@@ -208,7 +208,7 @@ class _Draws:
 
 
 def privatize(c: Compiled, seed: bytes, n_pad: int, n_classes: int) -> Compiled:
-    """Result privacy (Section 6, "Returning classification bitvectors"): the server shuffles the
+    """Result privacy (Section 7.2.2, "Returning classification bitvectors"): the server shuffles the
     result bitvector and the codebook by one random permutation and pads both with n_pad extra labels
     that are never selected.  Folded into the level products: slot s of every level matrix, mask and
     the codebook takes original row arr[s], where arr is the identity on m + n_pad rows shuffled by
@@ -242,7 +242,7 @@ def privatize(c: Compiled, seed: bytes, n_pad: int, n_classes: int) -> Compiled:
 
 
 def server_replicated(c: Compiled) -> Compiled:
-    """Server-side feature replication (Section 6, the alternative to Diane replicating her features):
+    """Server-side feature replication (Section 7.2.1, "Feature padding": the alternative to Diane replicating her features):
     the query holds each feature once, cyclically extended with period F (block slot s < B_in + F - 1
     holds feature s mod F), so that no multiplicity is revealed; the server maps it onto the padded
     layout by one plaintext matrix product with replication_matrix(c).  The block must hold the

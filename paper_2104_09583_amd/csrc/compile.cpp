@@ -203,7 +203,7 @@ std::unique_ptr<Compiled> compile_forest(const char* text, size_t len, uint32_t 
   return C;
 }
 
-// Result privacy (Section 6, "Returning classification bitvectors"): the server shuffles the result
+// Result privacy (Section 7.2.2, "Returning classification bitvectors"): the server shuffles the result
 // bitvector and the codebook by one random permutation and pads both with n_pad labels that are never
 // selected; here the shuffle is folded into the level products by permuting the rows of every level
 // matrix and mask (a padding row is all zero with mask 0, so its level results and its product are 0),
@@ -255,7 +255,7 @@ void privatize(Compiled& C, const uint8_t seed[32], uint32_t n_pad) {
   set_block(C);
 }
 
-// Server-side feature replication (Section 6): the query holds feature s mod F in block slot s for
+// Server-side feature replication (Section 7.2.1, "Feature padding"): the query holds feature s mod F in block slot s for
 // s < B_in + F - 1; the server multiplies by Rep (B_in x F, Rep[s][f] = 1 iff padded slot s mod q
 // belongs to feature f) with the diagonal method before the comparison: one more level.
 void server_replicate(Compiled& C, uint32_t n1F) {
