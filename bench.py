@@ -53,16 +53,16 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-KIND_NAMES = {0: "ntt_fwd_rows", 1: "ntt_fwd_cols", 2: "ntt_inv_rows", 3: "ntt_inv_cols", 4: "ks_inner",
+KIND_NAMES = {0: "ntt_fwd_rows", 1: "ntt_fwd_cols", 2: "ntt_inv_rows", 3: "ntt_inv_cols", 4: "ks_inner_rot",
               5: "bconv_colpass", 6: "elementwise", 7: "ntt_fwd_rows_moddown", 8: "ntt_fwd_rows_modswitch",
-              9: "matmul_inner", 10: "ntt_inv_rows_gather"}
+              9: "matmul_inner", 10: "ntt_inv_rows_gather", 15: "ks_inner_relin", 16: "ks_inner_giant"}
+KERNEL_KINDS = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 15, 16)
 STAGE_NAMES = ("comparison", "reshuffle", "levels", "aggregation")
 # kernel of each class (for the counter runs); class 6 is a family of small kernels and is not a roofline
-# (name patterns for rocprofv3's kernel filter: class 4 is ks_inner2_kernel and ks_inner_sum_kernel, class 7 the
-# ModDown finishes, alone and merged with the switch)
-KIND_KERNELS = {0: "ntt_rowreg4_kernel<false>", 2: "ntt_rowreg4_kernel<true>", 4: "ks_inner",
+# (name patterns for rocprofv3's kernel filter: class 7 is the ModDown finishes, alone and merged with the switch)
+KIND_KERNELS = {0: "ntt_rowreg4_kernel<false>", 2: "ntt_rowreg4_kernel<true>", 4: "ks_inner2",
                 5: "ntt_bridge_kernel", 7: "ntt_rowfwd_finish_kernel<[13]>", 8: "ntt_rowfwd_finish_kernel<2>",
-                9: "mm_inner", 10: "ntt_rowinv_gather_kernel"}
+                9: "mm_inner", 10: "ntt_rowinv_gather_kernel", 15: "ks_inner_rows", 16: "ks_inner_gsum"}
 
 
 def measured_traffic(kind: str, workload: str):
@@ -516,7 +516,7 @@ def micro_bench(args):
             e1.synchronize()
             totals.append(e0.elapsed_time(e1))
             for j, n in enumerate(STAGE_NAMES):
-                per_stage[n].append(ctx.profile_read(C.PROF_KERNEL_KINDS + j)["ms"])
+                per_stage[n].append(ctx.profile_read(C.PROF_STAGES[j])["ms"])
         ctx.profile_enable(False)
         results[mf.name] = {"max_depth": mf.max_depth, "precision": mf.precision, "trees": len(mf.branches),
                             "branches": sum(mf.branches), "b": meta.b, "q": meta.q, "d": meta.d,
@@ -816,9 +816,9 @@ def main():
                                "avg_launch_us": round(1000 * prof[k]["ms"] / max(1, prof[k]["launches"]), 2),
                                "algorithmic_bytes_per_launch": round(prof[k]["bytes"] / max(1, prof[k]["launches"])),
                                "achieved_GBps": round(prof[k]["bytes"] / max(1e-9, prof[k]["ms"]) / 1e6, 1)}
-               for k in range(C.PROF_KERNEL_KINDS) if prof[k]["launches"] > 0}
-    stages = {STAGE_NAMES[k - C.PROF_KERNEL_KINDS]: round(prof[k]["ms"] / steps, 3)
-              for k in range(C.PROF_KERNEL_KINDS, C.PROF_KINDS) if prof[k]["launches"] > 0}
+               for k in KERNEL_KINDS if prof[k]["launches"] > 0}
+    stages = {STAGE_NAMES[j]: round(prof[k]["ms"] / steps, 3)
+              for j, k in enumerate(C.PROF_STAGES) if prof[k]["launches"] > 0}
     ms_per_step = r["ms_per_step"]
     value = r["queries_per_step"] / (ms_per_step / 1000.0)
     # reference copy of known size for the byte counters of a separate --pmc run

@@ -388,7 +388,10 @@ int copse_poly_mul(copse_ctx* ctx, int prime, const uint64_t* a, const uint64_t*
  * 10 = inverse row pass reading ciphertext rows in place; 11..14 = the
  * stages of an evaluation (comparison, reshuffle product, level products with
  * masks, product tree with the final switch: the breakdown of Section 8),
- * bracketed on the evaluating stream, bytes 0.  reset clears the counters. */
+ * bracketed on the evaluating stream, bytes 0; 15 = relinearization inner
+ * products with the ModUp's forward and the ModDown's inverse row passes
+ * inside, 16 = giant-step sums of key-switch inner products (kind 4 is then
+ * the rotations' inner products).  reset clears the counters. */
 int copse_profile_enable(copse_ctx* ctx, int on);
 int copse_profile_read(copse_ctx* ctx, int kind, uint64_t* launches, double* total_ms,
                        double* bytes, int reset);

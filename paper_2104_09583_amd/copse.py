@@ -31,8 +31,10 @@ OP_ADD, OP_SUB, OP_TENSOR, OP_RELIN, OP_MODSWITCH, OP_MUL, OP_ROTATE, OP_MUL_PLA
  PROF_ELEMENTWISE, PROF_NTT_FWD_ROWS_MODDOWN, PROF_NTT_FWD_ROWS_MODSWITCH, PROF_MATMUL_INNER,
  PROF_NTT_INV_ROWS_GATHER, PROF_STAGE_COMPARISON, PROF_STAGE_RESHUFFLE, PROF_STAGE_LEVELS,
  PROF_STAGE_AGGREGATION) = range(15)
-PROF_KERNEL_KINDS = 11
-PROF_KINDS = 15
+PROF_KERNEL_KINDS = 11                 # kernel classes 0..10
+PROF_STAGES = (11, 12, 13, 14)         # comparison, reshuffle, levels, aggregation
+PROF_MORE_KERNEL_KINDS = (15, 16)      # relinearization inner products, giant-step sums
+PROF_KINDS = 17
 
 
 class CopseError(RuntimeError):

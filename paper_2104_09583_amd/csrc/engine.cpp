@@ -636,9 +636,9 @@ static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, co
     KSTables& T = c.kstab(level);
     const int nE = nl + c.alpha, D = c.n_digits(level);
     std::vector<const double*> inputs;
-    std::vector<KsSumJob> jobs;
+    std::vector<GsumStep> steps;
+    std::vector<GsumProd> prods;
     std::vector<AutoTerm> terms;
-    std::vector<KsSumOut> kouts;
     std::vector<AutoOut> aouts;
     std::vector<double*> outs;
     std::vector<const double*> addp, maskp;
@@ -647,10 +647,10 @@ static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, co
     auto res = alloc_batch(c, np * G, level - 1, 2);
     for (int i = 0; i < np; ++i) {
       const MatPlan& P = *plans[i];
+      // per output: the sigma(c0) parts and the unrotated inner sum (the addend)
       for (int b = 0; b < G; ++b) {
         const int u = i * G + b;
         AutoOut ao{addend.get() + (size_t)u * ps2, nullptr, nullptr, (int)terms.size(), 0};
-        KsSumOut ko{acc.get() + (size_t)u * 2 * nE * N, addend.get() + (size_t)u * ps2, (int)jobs.size(), 0};
         for (size_t s2 = 0; s2 < P.groups.size(); ++s2) {
           const uint32_t g = P.groups[s2];
           const int z = (off[i] + (int)s2) * G + b;
@@ -659,27 +659,37 @@ static std::vector<std::vector<SCt>> b_matmul_many(Context& c, const Keys& k, co
             ao.f1 = ptr2(z) + (size_t)nl * N;
             continue;
           }
-          const uint64_t gal = galois_of(c, (int64_t)g * P.n1);
-          auto it = k.rot.find(gal);
-          if (it == k.rot.end()) fail(COPSE_EKEY, "giant-step key absent");
-          inputs.push_back(ptr2(z) + (size_t)nl * N);
-          jobs.push_back(KsSumJob{ptr2(z) + (size_t)nl * N, nullptr, it->second->b.get(), it->second->a.get(), gal});
-          terms.push_back(AutoTerm{ptr2(z), gal});
+          terms.push_back(AutoTerm{ptr2(z), galois_of(c, (int64_t)g * P.n1)});
           ++ao.count;
-          ++ko.count;
         }
         aouts.push_back(ao);
-        kouts.push_back(ko);
         outs.push_back(res[u]->data());
         addp.push_back(addend.get() + (size_t)u * ps2);
         maskp.push_back(adds ? (*adds)[u] : nullptr);
         out[i][b] = res[u];
       }
+      // per giant step: one key for every batch element; the ModUp inputs in (step, batch element) order, so
+      // that element b of a step sits b ModUp outputs after element 0 (the inner sums are ps2 apart)
+      GsumProd pd{(int)steps.size(), 0, acc.get() + (size_t)i * G * 2 * nE * N, addend.get() + (size_t)i * G * ps2, 0};
+      for (size_t s2 = 0; s2 < P.groups.size(); ++s2) {
+        const uint32_t g = P.groups[s2];
+        if (g == 0) continue;
+        const uint64_t gal = galois_of(c, (int64_t)g * P.n1);
+        auto it = k.rot.find(gal);
+        if (it == k.rot.end()) fail(COPSE_EKEY, "giant-step key absent");
+        const int z0 = (off[i] + (int)s2) * G;
+        steps.push_back(GsumStep{gal, it->second->b.get(), it->second->a.get(), ptr2(z0) + (size_t)nl * N, nullptr});
+        for (int b = 0; b < G; ++b) inputs.push_back(ptr2(z0 + b) + (size_t)nl * N);
+        ++pd.count;
+      }
+      prods.push_back(pd);
     }
     DBuf ext = inputs.empty() ? DBuf(&c, 1) : modup_batch(c, level, inputs);
-    for (size_t t = 0; t < jobs.size(); ++t) jobs[t].ext = ext.get() + t * (size_t)D * nE * N;
+    const size_t ext_bs = (size_t)D * nE * N;
+    for (size_t t = 0; t < steps.size(); ++t) steps[t].ext = ext.get() + t * G * ext_bs;
     launch_auto_sum(c, terms, aouts, nl);
-    launch_ks_inner_sum(c, jobs, kouts, D, nE, level, (size_t)c.n_primes() * N, T.mm_ptop);
+    launch_ks_inner_gsum(c, steps, prods, G, ps2, ext_bs, (size_t)2 * nE * N, ps2, D, nE, level,
+                         (size_t)c.n_primes() * N, T.mm_ptop);
     const int l = level, R = np * G;
     const int2* r = rows_cached(c, "mdmsrows:" + std::to_string(level) + ":" + std::to_string(2 * R), [&] {
       std::vector<int2> h;

@@ -144,8 +144,9 @@ using CtPtr = std::unique_ptr<Ct>;
 // 2 inverse NTT (row pass), 3 inverse NTT (column pass), 4 key-switch inner product,
 // 5 base conversion, 6 elementwise.
 // kernel classes 0..10; 11..14: the evaluation's stages (comparison, reshuffle, levels, aggregation)
+// 15: relinearization inner products with the fused row passes, 16: giant-step sums of inner products
 constexpr int kProfStage0 = 11;
-constexpr int kProfKinds = 15;
+constexpr int kProfKinds = 17;
 struct ProfSlot {
   uint64_t launches = 0;
   double ms = 0;
@@ -396,24 +397,27 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
 // are written after the inverse row pass (the rows the ModDown transforms back; nE: none)
 void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
                           double ptop, int inv_from);
-// Key-switch inner products summed per output (giant steps of a product, one ModDown for their sum):
-// output u accumulates, over its jobs, sum_j digit_j(sigma_g(in)) key_j in the extended basis, plus
-// P times the top limb of its addend (2 polys, NTT form, nl limbs) on the top data row.
-struct KsSumJob {
-  const double* in;     // the rotated input poly (NTT form, nl limbs): the digits' own limbs
-  const double* ext;    // its ModUp output [D][nE][N]
-  const double* kb;
+// Key-switch inner products summed per output (giant steps of a product, one ModDown for their sum).
+// Product p has G outputs (batch elements) that share its key sequence: output (p, b) accumulates, over the
+// product's steps s, sum_j digit_j(sigma_{g_s}(in_{s,b})) key_{s,j} in the extended basis, plus P times the
+// top limb of its addend (2 polys, NTT form, nl limbs) on the top data row.  Batch element b's input,
+// ModUp output, accumulator and addend sit at fixed strides from element 0's.
+struct GsumStep {
+  uint64_t g;           // Galois element
+  const double* kb;     // its key [D][Ltot][N]
   const double* ka;
-  uint64_t g;
+  const double* in;     // batch element 0's rotated input poly (NTT form, nl limbs): the digits' own limbs
+  const double* ext;    // batch element 0's ModUp output [D][nE][N]
 };
-struct KsSumOut {
-  double* acc;          // [2][nE][N]
-  const double* top;    // the addend
-  int first, count;     // its jobs
-  int accum = 0;        // set by the launcher: add to acc (a later chunk of a long output; no top term)
+struct GsumProd {
+  int first, count;     // its steps
+  double* acc;          // batch element 0's accumulator [2][nE][N]
+  const double* top;    // batch element 0's addend
+  int accum = 0;        // set by the launcher: add to acc (a later chunk of a long product; no top term)
 };
-void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const std::vector<KsSumOut>& outs, int D,
-                         int nE, int level, size_t key_ds, double ptop);
+void launch_ks_inner_gsum(Context& c, const std::vector<GsumStep>& steps, const std::vector<GsumProd>& prods, int G,
+                          size_t in_bs, size_t ext_bs, size_t acc_bs, size_t top_bs, int D, int nE, int level,
+                          size_t key_ds, double ptop);
 // Per output u: dst_u poly 0 = f0_u + sum_t sigma_{g_t}(c0_t), poly 1 = f1_u (null f: zero), nl limbs.
 struct AutoTerm {
   const double* c0;

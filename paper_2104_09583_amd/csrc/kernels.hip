@@ -2024,7 +2024,7 @@ void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, in
       if (pk.j[k].g != 1) fail(COPSE_EINVAL, "internal: the fused inner product takes no automorphism");
     }
     hipEvent_t ev;
-    prof_begin(c, 4, &ev);
+    prof_begin(c, 15, &ev);
     hipLaunchKernelGGL(ks_inner_rows_kernel, dim3((unsigned)(c.N / 4096), nE, cnt), dim3(512), 0, c.stream, pk, D, nE,
                        level + 1, c.L, c.alpha, (int)c.log_n, (int)c.log_n - 12, key_ds, c.d_primes, ptop,
                        inv_from);
@@ -2035,146 +2035,159 @@ void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, in
       for (int k2 = 0; k2 < k; ++k2) seen |= pk.j[k2].kb == pk.j[k].kb;
       keys += !seen;
     }
-    prof_end(c, 4, ev, ks_pack_bytes(c, pk, cnt, D, nE, level + 1, keys));
+    prof_end(c, 15, ev, ks_pack_bytes(c, pk, cnt, D, nE, level + 1, keys));
   }
 }
 
-// Per-output sums of key-switch inner products (see launch_ks_inner_sum).  grid: x over coefficients,
-// y over extended rows, z over the outputs of the pack; each thread runs through its output's jobs.
-struct KsSumPack {
-  // 80 x 40 + 16 x 32 bytes: within the 4 KiB of kernel arguments with the other parameters
-  static constexpr int kJobs = 80, kOuts = 16;
-  KsSumJob j[kJobs];
-  KsSumOut o[kOuts];
+// Giant-step sums of key-switch inner products (see launch_ks_inner_gsum).  grid: x over coefficients,
+// y over extended rows, z over (product, chunk of kB batch elements).  A thread keeps the sums of its chunk's
+// kB outputs in registers and runs through the product's steps: per step the key values are loaded once and
+// serve every batch element of the chunk (all of them rotate by the same element, so the permuted index is
+// shared too), so each key is read once per chunk instead of once per output.
+struct GsumPack {
+  // 64 x 40 + 16 x 32 bytes: within the 4 KiB of kernel arguments with the other parameters
+  static constexpr int kSteps = 64, kProds = 16;
+  GsumStep s[kSteps];
+  GsumProd p[kProds];
 };
-// kD > 0: the digit count, known at compile time, so the loads of kU jobs (all their digits) are issued
-// together (one thread's chain of dependent loads a kU-th as long); the other jobs one at a time.
+constexpr int kGsumB = 8;
+// kD: the digit count when it is known at compile time, else (kD = 8) an upper bound of the runtime D_
 template <int kD>
-__global__ void ks_inner_sum_kernel(KsSumPack pk, int D, int nE, int nl, int L, int alpha, int logN,
-                                    size_t key_ds, const DevPrime* P, double ptop) {
-  constexpr int kU = 4;
+__global__ __launch_bounds__(256) void ks_inner_gsum_kernel(GsumPack pk, int G, size_t in_bs, size_t ext_bs,
+                                                            size_t acc_bs, size_t top_bs, int D_, int nE, int nl,
+                                                            int L, int alpha, int logN, size_t key_ds,
+                                                            const DevPrime* P, double ptop) {
+  const int D = kD < 8 ? kD : D_;
   const size_t N = (size_t)1 << logN;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int o = blockIdx.y;
-  const KsSumOut ou = pk.o[blockIdx.z];
+  const int bchunks = (G + kGsumB - 1) / kGsumB;
+  const GsumProd pr_ = pk.p[blockIdx.z / bchunks];
+  const int b0 = (int)(blockIdx.z % bchunks) * kGsumB;
+  const int nb = min(kGsumB, G - b0);   // uniform
   const int prime = o < nl ? o : L + 1 + (o - nl);
-  const DevPrime& pr = P[prime];
+  const DevPrime pr = cload_prime(P + prime);
   const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
-  auto row = [&](const KsSumJob& jb, int j) -> const double* {
-    return j == own ? jb.in + (size_t)o * N : jb.ext + ((size_t)j * nE + o) * N;
-  };
-  double a0 = 0.0, a1 = 0.0;
-  int t = ou.first;
-  const int tend = ou.first + ou.count;
-  if (kD > 0) {
-    constexpr int kDd = kD > 0 ? kD : 1;
-    for (; t + kU <= tend; t += kU) {
-      double e[kU][kDd], kb[kU][kDd], ka[kU][kDd];
+  double a0[kGsumB], a1[kGsumB];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const KsSumJob jb = pk.j[t + u];
-        const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
+  for (int b = 0; b < kGsumB; ++b) a0[b] = a1[b] = 0.0;
+  for (int t = pr_.first; t < pr_.first + pr_.count; ++t) {
+    const GsumStep st = pk.s[t];
+    const size_t src = st.g == 1 ? i : auto_src((uint32_t)i, st.g, logN);
+    double kb[kD], ka[kD], e[kGsumB][kD];
 #pragma unroll
-        for (int j = 0; j < kDd; ++j) {
-          const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
-          e[u][j] = row(jb, j)[src];
-          kb[u][j] = jb.kb[ko];
-          ka[u][j] = jb.ka[ko];
+    for (int j = 0; j < kD; ++j) {
+      if (j < D) {
+        const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
+        kb[j] = st.kb[ko];
+        ka[j] = st.ka[ko];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kGsumB; ++b) {
+      if (b < nb) {
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+          if (j < D) {
+            const double* row = j == own ? st.in + (size_t)(b0 + b) * in_bs + (size_t)o * N
+                                         : st.ext + (size_t)(b0 + b) * ext_bs + ((size_t)j * nE + o) * N;
+            e[b][j] = row[src];
+          }
         }
       }
+    }
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+    for (int b = 0; b < kGsumB; ++b) {
+      if (b < nb) {
 #pragma unroll
-        for (int j = 0; j < kDd; ++j) {
-          a0 += mul_lazy(e[u][j], kb[u][j], pr.q, pr.qinv);
-          a1 += mul_lazy(e[u][j], ka[u][j], pr.q, pr.qinv);
+        for (int j = 0; j < kD; ++j) {
+          if (j < D) {
+            a0[b] += mul_lazy(e[b][j], kb[j], pr.q, pr.qinv);
+            a1[b] += mul_lazy(e[b][j], ka[j], pr.q, pr.qinv);
+          }
         }
-        // D <= 8 lazy products per job: fold back after each job
-        a0 = reduce_sym(a0, pr.q, pr.qinv);
-        a1 = reduce_sym(a1, pr.q, pr.qinv);
+        // at most 8 lazy products per step: fold back after each step
+        a0[b] = reduce_sym(a0[b], pr.q, pr.qinv);
+        a1[b] = reduce_sym(a1[b], pr.q, pr.qinv);
       }
     }
   }
-  for (; t < tend; ++t) {
-    const KsSumJob jb = pk.j[t];
-    const size_t src = jb.g == 1 ? i : auto_src((uint32_t)i, jb.g, logN);
-    for (int j = 0; j < D; ++j) {
-      const double e = row(jb, j)[src];
-      const size_t ko = (size_t)j * key_ds + (size_t)prime * N + i;
-      a0 += mul_lazy(e, jb.kb[ko], pr.q, pr.qinv);
-      a1 += mul_lazy(e, jb.ka[ko], pr.q, pr.qinv);
+#pragma unroll
+  for (int b = 0; b < kGsumB; ++b) {
+    if (b < nb) {
+      double* acc = pr_.acc + (size_t)(b0 + b) * acc_bs;
+      double v0 = a0[b], v1 = a1[b];
+      if (pr_.accum) {   // a later chunk: the earlier chunks' canonical sums
+        v0 += acc[(size_t)o * N + i];
+        v1 += acc[((size_t)nE + o) * N + i];
+      } else if (o == nl - 1) {   // uniform per workgroup
+        const double* top = pr_.top + (size_t)(b0 + b) * top_bs;
+        v0 += mul_lazy(top[(size_t)o * N + i], ptop, pr.q, pr.qinv);
+        v1 += mul_lazy(top[((size_t)nl + o) * N + i], ptop, pr.q, pr.qinv);
+      }
+      acc[(size_t)o * N + i] = canon(reduce_sym(v0, pr.q, pr.qinv), pr.q);
+      acc[((size_t)nE + o) * N + i] = canon(reduce_sym(v1, pr.q, pr.qinv), pr.q);
     }
-    a0 = reduce_sym(a0, pr.q, pr.qinv);
-    a1 = reduce_sym(a1, pr.q, pr.qinv);
   }
-  if (ou.accum) {      // a later chunk: the earlier chunks' canonical sums
-    a0 += ou.acc[(size_t)o * N + i];
-    a1 += ou.acc[((size_t)nE + o) * N + i];
-  } else if (o == nl - 1) {   // uniform per workgroup
-    a0 += mul_lazy(ou.top[(size_t)o * N + i], ptop, pr.q, pr.qinv);
-    a1 += mul_lazy(ou.top[((size_t)nl + o) * N + i], ptop, pr.q, pr.qinv);
-  }
-  ou.acc[(size_t)o * N + i] = canon(reduce_sym(a0, pr.q, pr.qinv), pr.q);
-  ou.acc[((size_t)nE + o) * N + i] = canon(reduce_sym(a1, pr.q, pr.qinv), pr.q);
 }
 
-void launch_ks_inner_sum(Context& c, const std::vector<KsSumJob>& jobs, const std::vector<KsSumOut>& outs_in, int D,
-                         int nE, int level, size_t key_ds, double ptop) {
-  // outputs with more than kJobs jobs run in chunks: chunk r of every output in round r (rounds in stream
-  // order, later chunks adding to the accumulator); within a round, packs of at most kOuts chunks and kJobs
-  // jobs
-  std::vector<std::vector<KsSumOut>> rounds;
-  for (const KsSumOut& o : outs_in)
-    for (int r = 0, done = 0; done < o.count || r == 0; ++r) {
-      KsSumOut ch = o;
-      ch.first = o.first + done;
-      ch.count = std::min(KsSumPack::kJobs, o.count - done);
+void launch_ks_inner_gsum(Context& c, const std::vector<GsumStep>& steps, const std::vector<GsumProd>& prods_in, int G,
+                          size_t in_bs, size_t ext_bs, size_t acc_bs, size_t top_bs, int D, int nE, int level,
+                          size_t key_ds, double ptop) {
+  if (D < 1 || D > 8) fail(COPSE_EINVAL, "internal: digit count of the giant-step sums");
+  if (G < 1) return;
+  // products with more than kSteps steps run in chunks: chunk r of every product in round r (rounds in stream
+  // order, later chunks adding to the accumulator); within a round, packs of at most kProds chunks and kSteps
+  // steps
+  std::vector<std::vector<GsumProd>> rounds;
+  for (const GsumProd& p : prods_in)
+    for (int r = 0, done = 0; done < p.count || r == 0; ++r) {
+      GsumProd ch = p;
+      ch.first = p.first + done;
+      ch.count = std::min(GsumPack::kSteps, p.count - done);
       ch.accum = r > 0;
       if ((int)rounds.size() <= r) rounds.emplace_back();
       rounds[r].push_back(ch);
       done += ch.count;
     }
-  for (const auto& outs : rounds)
-  for (size_t u0 = 0; u0 < outs.size();) {
-    KsSumPack pk;
-    int nu = 0, nj = 0;
-    while (u0 + nu < outs.size() && nu < KsSumPack::kOuts) {
-      const KsSumOut& o = outs[u0 + nu];
-      if (nj + o.count > KsSumPack::kJobs) break;
-      pk.o[nu] = o;
-      pk.o[nu].first = nj;
-      for (int t = 0; t < o.count; ++t) pk.j[nj + t] = jobs[o.first + t];
-      nj += o.count;
-      ++nu;
+  const int bchunks = (G + kGsumB - 1) / kGsumB;
+  for (const auto& prods : rounds)
+    for (size_t u0 = 0; u0 < prods.size();) {
+      GsumPack pk;
+      int np = 0, ns = 0;
+      while (u0 + np < prods.size() && np < GsumPack::kProds) {
+        const GsumProd& p = prods[u0 + np];
+        if (ns + p.count > GsumPack::kSteps) break;
+        pk.p[np] = p;
+        pk.p[np].first = ns;
+        for (int t = 0; t < p.count; ++t) pk.s[ns + t] = steps[p.first + t];
+        ns += p.count;
+        ++np;
+      }
+      hipEvent_t ev;
+      prof_begin(c, 16, &ev);
+      const dim3 grid((unsigned)((c.N + 255) / 256), nE, (unsigned)(np * bchunks));
+#define COPSE_KSG(KD)                                                                                         \
+  hipLaunchKernelGGL(ks_inner_gsum_kernel<KD>, grid, dim3(256), 0, c.stream, pk, G, in_bs, ext_bs, acc_bs, top_bs, \
+                     D, nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes, ptop)
+      switch (D) {
+        case 1: COPSE_KSG(1); break;
+        case 2: COPSE_KSG(2); break;
+        case 3: COPSE_KSG(3); break;
+        case 4: COPSE_KSG(4); break;
+        default: COPSE_KSG(8); break;
+      }
+#undef COPSE_KSG
+      COPSE_HIP(hipGetLastError());
+      // per step and batch element: D digit rows read; per output: 2 rows written and the addend's top limb
+      // (2 rows) read, or a later chunk's accumulator (2 rows); each step's key (2 D rows) once
+      double extra = 0.0;
+      for (int u = 0; u < np; ++u) extra += G * (pk.p[u].accum ? 2.0 * nE : 2.0);
+      prof_end(c, 16, ev,
+               (((double)D * ns * G + 2.0 * np * G + 2.0 * D * ns) * nE + extra) * (double)c.N * 8.0);
+      u0 += np;
     }
-    hipEvent_t ev;
-    prof_begin(c, 4, &ev);
-    const dim3 grid((unsigned)((c.N + 255) / 256), nE, nu);
-#define COPSE_KSS(KD)                                                                                            \
-  hipLaunchKernelGGL(ks_inner_sum_kernel<KD>, grid, dim3(256), 0, c.stream, pk, D, nE, level + 1, c.L, c.alpha, \
-                     (int)c.log_n, key_ds, c.d_primes, ptop)
-    switch (D) {
-      case 1: COPSE_KSS(1); break;
-      case 2: COPSE_KSS(2); break;
-      case 3: COPSE_KSS(3); break;
-      default: COPSE_KSS(0); break;
-    }
-#undef COPSE_KSS
-    COPSE_HIP(hipGetLastError());
-    // per job: D digit rows read; per output: 2 rows written and the addend's top limb (2 rows) read, or
-    // a later chunk's accumulator (2 rows); each distinct key's 2 D rows once
-    int keys = 0;
-    for (int t = 0; t < nj; ++t) {
-      bool seen = false;
-      for (int t2 = 0; t2 < t; ++t2) seen |= pk.j[t2].kb == pk.j[t].kb;
-      keys += !seen;
-    }
-    double extra = 0.0;
-    for (int u = 0; u < nu; ++u) extra += pk.o[u].accum ? 2.0 * nE : 2.0;
-    prof_end(c, 4, ev, (((double)D * nj + 2.0 * nu + 2.0 * D * keys) * nE + extra) * (double)c.N * 8.0);
-    u0 += nu;
-  }
 }
 
 // Sums of automorphisms of c0 parts plus optional unrotated parts (see launch_auto_sum).
@@ -2204,7 +2217,7 @@ __global__ void auto_sum_kernel(AutoSumPack pk, int nl, const DevPrime* P, int l
 }
 
 void launch_auto_sum(Context& c, const std::vector<AutoTerm>& terms, const std::vector<AutoOut>& outs_in, int nl) {
-  // long outputs in chunks, chunk r in round r (see launch_ks_inner_sum)
+  // long outputs in chunks, chunk r in round r (see launch_ks_inner_gsum)
   std::vector<std::vector<AutoOut>> rounds;
   for (const AutoOut& o : outs_in)
     for (int r = 0, done = 0; done < o.count || r == 0; ++r) {
