@@ -2315,17 +2315,18 @@ struct MmPlace {
   int b;       // batch element of this wave (may be >= G)
   int s0, gm;  // the chunk's first giant group and its group count
 };
-template <int GM>
+// kW: waves per workgroup, one batch element each (the batch kernel), or 4 waves sharing one element
+template <int GM, int kW = kMmWaves>
 __device__ __forceinline__ MmPlace mm_place(int ng, int G, int wv) {
   // consecutive workgroups go to different XCDs: give each XCD a contiguous range of logical blocks
   unsigned bx = blockIdx.x;
   const unsigned nbx = gridDim.x;
   if ((nbx & 7u) == 0) bx = (bx & 7u) * (nbx >> 3) + (bx >> 3);
-  const unsigned bchunks = (unsigned)(G + kMmWaves - 1) / kMmWaves;
+  const unsigned bchunks = (unsigned)(G + kW - 1) / kW;
   const unsigned per_tile = bchunks * (unsigned)((ng + GM - 1) / GM);
   const unsigned rem = bx % per_tile;
   MmPlace m;
-  m.b = (int)(rem % bchunks) * kMmWaves + wv;
+  m.b = (int)(rem % bchunks) * kW + wv;
   m.i = (size_t)(bx / per_tile) * kMmLanes + (threadIdx.x % kMmLanes);
   m.s0 = (int)(rem / bchunks) * GM;
   m.gm = min(GM, ng - m.s0);
@@ -2441,27 +2442,28 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
   }
 }
 
-// Several batch elements: a workgroup is 64 coefficients x 4 batch elements (one per wave).  The four
-// waves need the same diagonal values, so a baby step's diagonal tile (GM groups x 1 or 2 polys x 64
-// coefficients) is fetched once per workgroup, each wave loading every fourth group, and staged in LDS,
+// Several batch elements: a workgroup is 64 coefficients x kW batch elements (one per wave; kW = 4 or 8).
+// The waves need the same diagonal values, so a baby step's diagonal tile (GM groups x 1 or 2 polys x 64
+// coefficients) is fetched once per workgroup, each wave loading every kW-th group, and staged in LDS,
 // double-buffered: the next baby step's tile and baby values are in flight while the current step's
 // products run, and one barrier per baby step hands the tile over.  Which diagonals of a step are zero
 // is a scalar bitmask.  A wave past the end of the batch still loads its share of the tiles.
-template <int GM, bool kEnc>
-__global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict__ out,
-                                                             const double* __restrict__ baby,
-                                                             const double* const* __restrict__ tab, int n_u, int ng,
-                                                             int G, int nl, size_t baby_slot, size_t baby_b,
-                                                             const DevPrime* P, int logN, Pack b0, int u0) {
+template <int GM, bool kEnc, int kW>
+__global__ __launch_bounds__(64 * kW) void mm_inner_batch_kernel(double* __restrict__ out,
+                                                                 const double* __restrict__ baby,
+                                                                 const double* const* __restrict__ tab, int n_u,
+                                                                 int ng, int G, int nl, size_t baby_slot,
+                                                                 size_t baby_b, const DevPrime* P, int logN, Pack b0,
+                                                                 int u0) {
   constexpr int kNp = kEnc ? 3 : 2, kNd = kEnc ? 2 : 1;
   constexpr int kRed = kEnc ? 3 : 7;
-  constexpr int kPer = (GM + kMmWaves - 1) / kMmWaves;   // groups of a tile one wave loads
+  constexpr int kPer = (GM + kW - 1) / kW;   // groups of a tile one wave loads
   static_assert(GM <= 32, "one bit per group");
   __shared__ double dl[2][GM][kNd][kMmLanes];
   const size_t N = (size_t)1 << logN;
   const int lane = threadIdx.x % kMmLanes;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kMmLanes));
-  const MmPlace m = mm_place<GM>(ng, G, wv);
+  const MmPlace m = mm_place<GM, kW>(ng, G, wv);
   const size_t i = m.i;
   if (i >= N) return;   // the whole workgroup (N is a multiple of 64)
   const int b = m.b;
@@ -2496,7 +2498,7 @@ __global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict_
     const double* const* row = tab + (size_t)u * ng + s0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int s = wv + kMmWaves * k;
+      const int s = wv + kW * k;
       const double* pv = cload(row + s);   // in bounds as above
       const double* dp = s < gm ? pv : nullptr;   // uniform
       if (dp != nullptr) {
@@ -2517,7 +2519,7 @@ __global__ __launch_bounds__(256) void mm_inner_batch_kernel(double* __restrict_
   auto stage = [&](int buf) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int s = wv + kMmWaves * k;
+      const int s = wv + kW * k;
       if (s < GM)
 #pragma unroll
         for (int p = 0; p < kNd; ++p) dl[buf][s][p][lane] = r[k][p];
@@ -2595,14 +2597,20 @@ template <int GM, bool kEnc>
 static void mm_inner_launch(Context& c, double* out, const double* baby, const double* const* tab, int n_u, int ng,
                             int G, int nl, size_t baby_slot, size_t baby_b, const Pack& b0, int u0) {
   const unsigned tiles = (unsigned)((c.N + kMmLanes - 1) / kMmLanes);
-  const unsigned bchunks = (unsigned)((G + kMmWaves - 1) / kMmWaves);
-  const unsigned nx = tiles * bchunks * (unsigned)((ng + GM - 1) / GM);
+  const unsigned gchunks = (unsigned)((ng + GM - 1) / GM);
   if (G == 1) {
+    const unsigned nx = tiles * gchunks;
     hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc>), dim3(nx, nl), dim3(256), 0, c.stream, out, baby, tab, n_u, ng,
                        nl, baby_slot, c.d_primes, (int)c.log_n, b0.p[0], u0);
+  } else if (G % 8 == 0) {
+    // eight batch elements per workgroup: each staged diagonal tile feeds twice the products
+    const unsigned nx = tiles * (unsigned)(G / 8) * gchunks;
+    hipLaunchKernelGGL((mm_inner_batch_kernel<GM, kEnc, 8>), dim3(nx, nl), dim3(512), 0, c.stream, out, baby, tab,
+                       n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0, u0);
   } else {
-    hipLaunchKernelGGL((mm_inner_batch_kernel<GM, kEnc>), dim3(nx, nl), dim3(256), 0, c.stream, out, baby, tab, n_u,
-                       ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0, u0);
+    const unsigned nx = tiles * (unsigned)((G + kMmWaves - 1) / kMmWaves) * gchunks;
+    hipLaunchKernelGGL((mm_inner_batch_kernel<GM, kEnc, kMmWaves>), dim3(nx, nl), dim3(256), 0, c.stream, out, baby,
+                       tab, n_u, ng, G, nl, baby_slot, baby_b, c.d_primes, (int)c.log_n, b0, u0);
   }
 }
 

@@ -473,7 +473,7 @@ def _digest(polys):
 # label_groups > batch, the remaining groups of the workload follow in calls of the same batch size and their
 # decrypted labels are checked against the plain forest (every query of the workload).
 FULL_SIZE = [("c2_forest16_d5", 1, 1), ("c5_serve_8x_d4", 1, 1), ("c5_serve_32x_d6", 1, 1),
-             ("c5_serve_64x_d8", 1, 1), ("c3_batched_32x_d6", 16, 64), ("c4_encmodel_64x_d8", 4, 64)]
+             ("c5_serve_64x_d8", 1, 1), ("c3_batched_32x_d6", 16, 64), ("c4_encmodel_64x_d8", 8, 64)]
 
 
 @pytest.mark.parametrize("name,batch,label_groups", FULL_SIZE)
@@ -585,16 +585,17 @@ def _giant_groups(A, n1, enc):
                if any(OC.generalized_diagonal(A % T, g * n1 + j).any() for j in range(n1) if g * n1 + j < n))
 
 
-@pytest.mark.parametrize("enc", [False, True])
-def test_matmul_wide_chunks_bit_exact(C, enc):
+@pytest.mark.parametrize("enc,G", [(False, 2), (True, 2), (False, 8), (True, 8)])
+def test_matmul_wide_chunks_bit_exact(C, enc, G):
     """Two query groups through the batched MatMul inner sums with the wide register tiles the full-size
     workloads run (plaintext model: 16 and 24 giant groups per thread; encrypted model: 12), on the ring
     of the fused passes (log N = 13): result ciphertexts equal the oracle's bit for bit, labels equal the
-    plain forest.  The baby-step counts are picked so that the products reach those tile widths."""
+    plain forest.  The baby-step counts are picked so that the products reach those tile widths.  With
+    8 groups the inner sums run eight batch elements per workgroup; every group then equals its evaluation
+    alone, and group 0 the oracle."""
     shape = synth.ForestShape(6, 4, 0.85, 3, 4, 3)
     text = synth.gen_forest_text(shape, 71)
     oc = OC.compile_forest(text, 3, 4)
-    G = 2
     Rext = OC.extended_reshuffle(oc)
     want_R, want_L = ((16,), (24,)) if not enc else ((12, 8), (12,))
     n1_R = next(n for n in range(2, 41) if _mm_chunk_gm(_giant_groups(Rext, n, enc), enc, G) in want_R)
@@ -618,7 +619,12 @@ def test_matmul_wide_chunks_bit_exact(C, enc):
     omodel = CI.encrypt_model(sc, okeys, pl, kseed) if enc else CI.encode_model(sc, pl)
     _, trees = F.parse_forest(text)
     for g in range(G):
-        X = CI.encrypt_queries(sc, okeys, pl, qsets[g], kseed, g)
-        same(ctx.export(batch[g])[0], CI.Evaluator(sc, okeys, pl).run(X, omodel)["result"])
+        eb = ctx.export(batch[g])[0]
+        if g < 2:
+            X = CI.encrypt_queries(sc, okeys, pl, qsets[g], kseed, g)
+            same(eb, CI.Evaluator(sc, okeys, pl).run(X, omodel)["result"])
+        else:
+            es = ctx.export(ctx.evaluate(model, ctx.export_eval(keys), groups[g]))[0]
+            assert all((a == b).all() for a, b in zip(eb["polys"], es["polys"])), f"group {g}"
         bits = ctx.decrypt_labels(keys, meta, batch[g], len(qsets[g]))
         assert (bits == np.array([F.evaluate(trees, list(x)) for x in qsets[g]])).all()
