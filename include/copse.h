@@ -131,6 +131,29 @@ int copse_ctx_sync(copse_ctx* ctx);
 /* Device bytes currently held by the context's pool (in use + cached). */
 size_t copse_ctx_device_bytes(const copse_ctx* ctx);
 
+/* Launch-shape knobs of the evaluation (chosen by an autotuner; none of them
+ * changes a result bit: they only split exact sums differently across
+ * launches, workgroups and registers).  An evaluation of G query groups on a
+ * context with ring 2^log_n and top data level L uses the first entry with
+ * that log_n and top_level, batch_lo <= G <= batch_hi and a matching model
+ * kind (model: -1 any, 0 plaintext, 1 encrypted); a knob of 0 (or no
+ * matching entry) keeps the built-in choice.  Knobs: mm_cap, giant groups per
+ * register tile of the MatMul inner sums (4..32; built in: 24 for several
+ * groups of a plaintext model, else 12); mm_waves, batch elements per MatMul
+ * workgroup when G is a multiple of 8 (4 or 8; built in 8); ks_jobs,
+ * key-switch inner products per launch (1..32; built in 32); bridge_wgs, the
+ * workgroup count under which the fused column pass of a base change splits
+ * its outputs (built in 512); gsum_b, batch elements per thread of the
+ * giant-step key-switch sums (4 or 8; built in 8). */
+typedef struct {
+  uint32_t log_n, top_level, batch_lo, batch_hi;
+  int32_t model;
+  int32_t mm_cap, mm_waves, ks_jobs, bridge_wgs, gsum_b;
+} copse_tune_entry;
+/* Replaces the context's table (entries copied; n = 0 clears it).  Errors:
+ * EINVAL (null entries with n > 0, a knob out of its range). */
+int copse_ctx_set_tuning(copse_ctx* ctx, const copse_tune_entry* entries, size_t n);
+
 /* ---------------------------------------------------------------- compile */
 /*
  * Forest compiler (model owner; Section 4.2 and Section 5, "Input

@@ -55,6 +55,27 @@ class CompileOptions(ctypes.Structure):
                 ("privacy_seed", ctypes.c_uint8 * 32), ("n_pad", ctypes.c_uint32)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("top_level", ctypes.c_uint32), ("batch_lo", ctypes.c_uint32),
+                ("batch_hi", ctypes.c_uint32), ("model", ctypes.c_int32), ("mm_cap", ctypes.c_int32),
+                ("mm_waves", ctypes.c_int32), ("ks_jobs", ctypes.c_int32), ("bridge_wgs", ctypes.c_int32),
+                ("gsum_b", ctypes.c_int32)]
+
+
+TUNE_KNOBS = ("mm_cap", "mm_waves", "ks_jobs", "bridge_wgs", "gsum_b")
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def load_tuning(path: str = TUNING_PATH) -> list:
+    """The committed autotuner choices (a list of dicts with log_n, top_level, batch [lo, hi], model and
+    knobs); [] when there is no file."""
+    import json
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return json.load(f).get("entries", [])
+
+
 class Meta(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n_features", "precision", "K", "q", "b", "m", "d", "n_trees", "block_w", "queries_per_ct",
@@ -93,6 +114,7 @@ def lib() -> ctypes.CDLL:
         "copse_ctx_primes": [P, u64p, sz, ctypes.POINTER(sz)],
         "copse_ctx_set_stream": [P, P],
         "copse_ctx_sync": [P],
+        "copse_ctx_set_tuning": [P, ctypes.POINTER(TuneEntry), sz],
         "copse_forest_compile": [ctypes.c_char_p, sz, u32, u32, u32, i32, u32, u32, PP, ctypes.POINTER(Meta)],
         "copse_compiled_rotations": [ctypes.POINTER(Meta), i32p, sz, ctypes.POINTER(sz)],
         "copse_forest_compile_private": [ctypes.c_char_p, sz, u32, u32, u32, i32, u32, u32, u8p, u32, PP,
@@ -229,15 +251,29 @@ class Context(_Handle):
     _destroy = "copse_ctx_destroy"
 
     def __init__(self, log_n: int, n_data_primes: int, q0_max: int, data_max: int, alpha: int,
-                 special_max: int, t: int = 65537, device: int = 0):
+                 special_max: int, t: int = 65537, device: int = 0, tuning: bool = True):
         p = Params(log_n, t, n_data_primes, q0_max, data_max, alpha, special_max, device)
         h = ctypes.c_void_p()
         check(lib().copse_ctx_create(ctypes.byref(p), ctypes.byref(h)))
         super().__init__(h)
         self.N = 1 << log_n
+        self.log_n = log_n
         self.t = t
         self.L = n_data_primes - 1
         self.alpha = alpha
+        if tuning:
+            # the committed autotuner choices for this ring and chain length
+            self.set_tuning([e for e in load_tuning() if e["log_n"] == log_n and e["top_level"] == self.L])
+
+    def set_tuning(self, entries: Sequence[dict]) -> None:
+        """Installs launch-shape knobs (copse_ctx_set_tuning); each entry: log_n, top_level, batch [lo, hi],
+        model (-1 any, 0 plaintext, 1 encrypted) and knobs {name: value} (missing or 0: built in)."""
+        arr = (TuneEntry * max(1, len(entries)))()
+        for i, e in enumerate(entries):
+            k = e.get("knobs", {})
+            arr[i] = TuneEntry(e["log_n"], e["top_level"], e["batch"][0], e["batch"][1], e.get("model", -1),
+                               *[int(k.get(n, 0)) for n in TUNE_KNOBS])
+        check(lib().copse_ctx_set_tuning(self.ptr, arr, len(entries)))
 
     # context
     def primes(self) -> List[int]:

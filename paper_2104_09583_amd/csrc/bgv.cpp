@@ -278,6 +278,16 @@ const MsMulti& Context::ms_multi(int level, int k) {
   return T.multi.emplace(k, M).first->second;
 }
 
+void Context::select_tuning(int batch, bool encrypted_model) {
+  tune = Tuning{};
+  for (const TuneEntry& e : tune_table)
+    if (e.log_n == log_n && e.top_level == (uint32_t)L && (uint32_t)batch >= e.batch_lo &&
+        (uint32_t)batch <= e.batch_hi && (e.model < 0 || e.model == (encrypted_model ? 1 : 0))) {
+      tune = e.t;
+      return;
+    }
+}
+
 void Context::build_level_tables() {
   for (int l = 0; l <= L; ++l) {
     kstab(l);

@@ -385,6 +385,24 @@ int copse_evaluate(copse_ctx* ctx, const copse_model* model, const copse_keys* k
   });
 }
 
+int copse_ctx_set_tuning(copse_ctx* ctx, const copse_tune_entry* entries, size_t n) {
+  return guarded([&] {
+    NEED(ctx && (entries || n == 0));
+    std::vector<TuneEntry> table;
+    for (size_t i = 0; i < n; ++i) {
+      const copse_tune_entry& e = entries[i];
+      auto in = [](int v, int lo, int hi) { return v == 0 || (v >= lo && v <= hi); };
+      if (!in(e.mm_cap, 4, 32) || !(e.mm_waves == 0 || e.mm_waves == 4 || e.mm_waves == 8) || !in(e.ks_jobs, 1, 32) ||
+          !in(e.bridge_wgs, 64, 8192) || !(e.gsum_b == 0 || e.gsum_b == 4 || e.gsum_b == 8) || e.batch_lo > e.batch_hi ||
+          e.model < -1 || e.model > 1)
+        fail(COPSE_EINVAL, "tuning entry " + std::to_string(i) + " out of range");
+      table.push_back(TuneEntry{e.log_n, e.top_level, e.batch_lo, e.batch_hi, e.model,
+                                Tuning{e.mm_cap, e.mm_waves, e.ks_jobs, e.bridge_wgs, e.gsum_b}});
+    }
+    ctx->c->tune_table = std::move(table);
+  });
+}
+
 int copse_evaluate_noalloc(copse_ctx* ctx, const copse_model* model, const copse_keys* keys, const copse_cts* query,
                            copse_cts* result) {
   return guarded([&] {

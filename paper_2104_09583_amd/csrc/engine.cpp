@@ -800,6 +800,7 @@ std::vector<CtPtr> evaluate_groups(Context& c, const Model& M, const Keys& k,
   const int p = (int)M.meta.precision;
   const size_t N = c.N;
   check_evaluation(c, M, k, groups);
+  c.select_tuning(G, M.encrypted);
   auto view = [](const Ct* x) { return SCt(const_cast<Ct*>(x), [](Ct*) {}); };
   // stage timings for the profiler (comparison, reshuffle, levels, aggregation; Section 8's breakdown)
   hipEvent_t stage_ev = nullptr;

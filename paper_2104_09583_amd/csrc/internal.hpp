@@ -155,6 +155,22 @@ struct ProfSlot {
 
 struct KSTables;  // per-level base-conversion constants (device)
 
+// Launch-shape knobs that change no result bit (how exact sums are split across launches, workgroups and
+// registers); 0 means the built-in choice.  The active values are picked per evaluation from the context's
+// table by (log N, top data level, query groups per call) (copse_ctx_set_tuning).
+struct Tuning {
+  int mm_cap = 0;       // giant groups per register tile of the MatMul inner sums (4..32)
+  int mm_waves = 0;     // batch elements per MatMul workgroup when the batch is a multiple of 8 (4 or 8)
+  int ks_jobs = 0;      // key-switch inner products per launch (1..32)
+  int bridge_wgs = 0;   // workgroup count under which the fused column pass splits its outputs (64..8192)
+  int gsum_b = 0;       // batch elements per thread of the giant-step sums (4 or 8)
+};
+struct TuneEntry {
+  uint32_t log_n, top_level, batch_lo, batch_hi;
+  int model;   // -1 any, 0 plaintext, 1 encrypted
+  Tuning t;
+};
+
 struct Context {
   int device = 0;
   hipStream_t own_stream = nullptr;
@@ -180,6 +196,11 @@ struct Context {
   std::map<std::string, int2*> call_rows;
   std::vector<std::vector<int2>> call_rows_host;
   std::vector<DBuf> call_row_bufs;
+  Tuning tune;                    // active for the evaluation being issued
+  std::vector<TuneEntry> tune_table;
+  // the table's entry for an evaluation of `batch` query groups of a plaintext or encrypted model (defaults
+  // when none matches)
+  void select_tuning(int batch, bool encrypted_model);
   bool profiling = false;
   ProfSlot prof[kProfKinds];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kProfKinds];

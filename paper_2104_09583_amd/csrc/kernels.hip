@@ -1086,7 +1086,8 @@ void launch_bridge_set(Context& c, int mode, double* out_base, const double* in_
       // at least ~512 workgroups (2048 waves) when the batch is small, by splitting the outputs into chunks
       // of at least 4 (one per wave)
       int chunks = 1;
-      while (chunks * 8 <= d.n_out && (size_t)xb * d.nz * chunks * set.n < 512) chunks *= 2;
+      const size_t target = c.tune.bridge_wgs > 0 ? (size_t)c.tune.bridge_wgs : 512;
+      while (chunks * 8 <= d.n_out && (size_t)xb * d.nz * chunks * set.n < target) chunks *= 2;
       d.ochunk = (d.n_out + chunks - 1) / chunks;
       chunks = (d.n_out + d.ochunk - 1) / d.ochunk;
       d.chunk0 = rows_y;
@@ -1882,8 +1883,9 @@ static double ks_pack_bytes(const Context& c, const KsPack& pk, int cnt, int D, 
 
 void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE, int level, size_t key_ds,
                       double ptop) {
-  for (size_t first = 0; first < jobs.size(); first += KsPack::kMax) {
-    int cnt = (int)std::min<size_t>(KsPack::kMax, jobs.size() - first);
+  const size_t per = c.tune.ks_jobs > 0 ? (size_t)std::min(c.tune.ks_jobs, KsPack::kMax) : KsPack::kMax;
+  for (size_t first = 0; first < jobs.size(); first += per) {
+    int cnt = (int)std::min<size_t>(per, jobs.size() - first);
     KsPack pk;
     for (int k = 0; k < cnt; ++k) pk.j[k] = jobs[first + k];
     hipEvent_t ev;
@@ -2016,8 +2018,9 @@ void launch_ks_inner_rows(Context& c, const std::vector<KsJob2>& jobs, int D, in
                           double ptop, int inv_from) {
   if (c.log_n < 13) fail(COPSE_EINVAL, "internal: split transform needs N >= 8192");
   if (D > 8) fail(COPSE_EINVAL, "internal: too many digits for the fused inner product");
-  for (size_t first = 0; first < jobs.size(); first += KsPack::kMax) {
-    const int cnt = (int)std::min<size_t>(KsPack::kMax, jobs.size() - first);
+  const size_t per = c.tune.ks_jobs > 0 ? (size_t)std::min(c.tune.ks_jobs, KsPack::kMax) : KsPack::kMax;
+  for (size_t first = 0; first < jobs.size(); first += per) {
+    const int cnt = (int)std::min<size_t>(per, jobs.size() - first);
     KsPack pk;
     for (int k = 0; k < cnt; ++k) {
       pk.j[k] = jobs[first + k];
@@ -2050,9 +2053,9 @@ struct GsumPack {
   GsumStep s[kSteps];
   GsumProd p[kProds];
 };
-constexpr int kGsumB = 8;
-// kD: the digit count when it is known at compile time, else (kD = 8) an upper bound of the runtime D_
-template <int kD>
+// kD: the digit count when it is known at compile time, else (kD = 8) an upper bound of the runtime D_;
+// kGsumB: batch elements per thread
+template <int kD, int kGsumB>
 __global__ __launch_bounds__(256) void ks_inner_gsum_kernel(GsumPack pk, int G, size_t in_bs, size_t ext_bs,
                                                             size_t acc_bs, size_t top_bs, int D_, int nE, int nl,
                                                             int L, int alpha, int logN, size_t key_ds,
@@ -2151,7 +2154,8 @@ void launch_ks_inner_gsum(Context& c, const std::vector<GsumStep>& steps, const 
       rounds[r].push_back(ch);
       done += ch.count;
     }
-  const int bchunks = (G + kGsumB - 1) / kGsumB;
+  const int kB = c.tune.gsum_b == 4 ? 4 : 8;
+  const int bchunks = (G + kB - 1) / kB;
   for (const auto& prods : rounds)
     for (size_t u0 = 0; u0 < prods.size();) {
       GsumPack pk;
@@ -2168,16 +2172,23 @@ void launch_ks_inner_gsum(Context& c, const std::vector<GsumStep>& steps, const 
       hipEvent_t ev;
       prof_begin(c, 16, &ev);
       const dim3 grid((unsigned)((c.N + 255) / 256), nE, (unsigned)(np * bchunks));
-#define COPSE_KSG(KD)                                                                                         \
-  hipLaunchKernelGGL(ks_inner_gsum_kernel<KD>, grid, dim3(256), 0, c.stream, pk, G, in_bs, ext_bs, acc_bs, top_bs, \
-                     D, nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes, ptop)
-      switch (D) {
-        case 1: COPSE_KSG(1); break;
-        case 2: COPSE_KSG(2); break;
-        case 3: COPSE_KSG(3); break;
-        case 4: COPSE_KSG(4); break;
-        default: COPSE_KSG(8); break;
+#define COPSE_KSG(KD, KB)                                                                                       \
+  hipLaunchKernelGGL((ks_inner_gsum_kernel<KD, KB>), grid, dim3(256), 0, c.stream, pk, G, in_bs, ext_bs, acc_bs,     \
+                     top_bs, D, nE, level + 1, c.L, c.alpha, (int)c.log_n, key_ds, c.d_primes, ptop)
+#define COPSE_KSG_D(KB)             \
+  switch (D) {                      \
+    case 1: COPSE_KSG(1, KB); break; \
+    case 2: COPSE_KSG(2, KB); break; \
+    case 3: COPSE_KSG(3, KB); break; \
+    case 4: COPSE_KSG(4, KB); break; \
+    default: COPSE_KSG(8, KB); break; \
+  }
+      if (kB == 4) {
+        COPSE_KSG_D(4)
+      } else {
+        COPSE_KSG_D(8)
       }
+#undef COPSE_KSG_D
 #undef COPSE_KSG
       COPSE_HIP(hipGetLastError());
       // per step and batch element: D digit rows read; per output: 2 rows written and the addend's top limb
@@ -2602,7 +2613,7 @@ static void mm_inner_launch(Context& c, double* out, const double* baby, const d
     const unsigned nx = tiles * gchunks;
     hipLaunchKernelGGL((mm_inner_kernel<GM, kEnc>), dim3(nx, nl), dim3(256), 0, c.stream, out, baby, tab, n_u, ng,
                        nl, baby_slot, c.d_primes, (int)c.log_n, b0.p[0], u0);
-  } else if (G % 8 == 0) {
+  } else if (G % 8 == 0 && c.tune.mm_waves != 4) {
     // eight batch elements per workgroup: each staged diagonal tile feeds twice the products
     const unsigned nx = tiles * (unsigned)(G / 8) * gchunks;
     hipLaunchKernelGGL((mm_inner_batch_kernel<GM, kEnc, 8>), dim3(nx, nl), dim3(512), 0, c.stream, out, baby, tab,
@@ -2630,7 +2641,7 @@ void launch_mm_inner(Context& c, double* out, const double* baby, const double* 
   // giant groups in chunks of at most 24 (12 with three accumulators each, or for one batch element, whose
   // kernel holds a step's loads for every group: more, smaller chunks at higher occupancy measured faster),
   // split evenly
-  const int cap = enc || G == 1 ? 12 : 24;
+  const int cap = c.tune.mm_cap > 0 ? std::min(32, std::max(4, c.tune.mm_cap)) : (enc || G == 1 ? 12 : 24);
   const int chunks = (ng + cap - 1) / cap;
   const int per = (ng + chunks - 1) / chunks;
   auto run = [&](auto gm_tag) {

@@ -134,6 +134,7 @@ struct Plain1 {
 
   CtPtr run(const std::vector<const Ct*>& X) {
     check_evaluation(c, M, k, {X});
+    c.select_tuning(1, M.encrypted);
     std::vector<SCt> rep;
     std::vector<const Ct*> planes = X;
     if (M.meta.server_rep) {
