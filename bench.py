@@ -5,7 +5,7 @@ features, 16-bit values, 10 classes, with the thresholds, the reshuffle and
 level diagonals and the masks encrypted under the data owner's key (45 GiB of
 ciphertexts resident in HBM), ring N = 32768 with 11 data primes and 4 special
 primes; all 256 encrypted queries of the workload (64 query groups of 4) per
-step, in batched calls of 8 groups.  A step is the complete Algorithm 1 on
+step, in batched calls of 16 groups.  A step is the complete Algorithm 1 on
 every query: comparison, reshuffle, level products with masks, product tree,
 switch to q_0.  Encrypted queries are resident in device memory before the
 timed region starts.  Inputs are synthetic (the pinned generator).

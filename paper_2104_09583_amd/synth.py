@@ -125,7 +125,7 @@ WORKLOADS = {
     "c4_encmodel_64x_d8": Workload(
         "c4_encmodel_64x_d8", ForestShape(64, 8, 0.7, 32, 16, 10), 256, 15, True, 4,
         "encrypted model and queries, 64 trees max depth 8, 16-bit, N=32768", CHAIN_32K_P16, n1=(0, 128),
-        batch=8),
+        batch=16),
     "c5_serve_8x_d4": Workload(
         "c5_serve_8x_d4", ForestShape(8, 4, 0.7, 16, 8, 4), 1, 15, False, 5,
         "serving mix member: 8 trees of depth 4", CHAIN_32K_P16),

@@ -473,7 +473,7 @@ def _digest(polys):
 # label_groups > batch, the remaining groups of the workload follow in calls of the same batch size and their
 # decrypted labels are checked against the plain forest (every query of the workload).
 FULL_SIZE = [("c2_forest16_d5", 1, 1), ("c5_serve_8x_d4", 1, 1), ("c5_serve_32x_d6", 1, 1),
-             ("c5_serve_64x_d8", 1, 1), ("c3_batched_32x_d6", 16, 64), ("c4_encmodel_64x_d8", 8, 64)]
+             ("c5_serve_64x_d8", 1, 1), ("c3_batched_32x_d6", 16, 64), ("c4_encmodel_64x_d8", 16, 64)]
 
 
 @pytest.mark.parametrize("name,batch,label_groups", FULL_SIZE)
