@@ -1918,9 +1918,12 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
 // them after the column stages; a digit's own limbs come from the input in NTT form, a product's formed
 // from both operands) and accumulates digit x key in registers, so the extended rows are never written in
 // NTT form.  Rows o >= inv_from (the rows the ModDown transforms back) leave after the inverse row pass.
-__global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha,
-                                                            int logN, int S1, size_t key_ds, const DevPrime* P,
-                                                            double ptop, int inv_from) {
+// At most 128 registers (four waves per SIMD), so that two workgroups share a compute unit and one
+// transforms while the other waits on memory: hence the keys are read after each transform, one
+// polynomial at a time.
+__global__ __launch_bounds__(512, 4) void ks_inner_rows_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha,
+                                                               int logN, int S1, size_t key_ds, const DevPrime* P,
+                                                               double ptop, int inv_from) {
   __shared__ double sh[kLdsTile4];
   const size_t N = (size_t)1 << logN;
   const int o = blockIdx.y;
@@ -1931,38 +1934,43 @@ __global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, 
   const int t = threadIdx.x;
   const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
   double a0[8], a1[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
-  for (int j = 0; j < D; ++j) {   // uniform per workgroup
-    // the digit's key values first: their loads are in flight while the tile is transformed
-    const size_t ko = (size_t)j * key_ds + (size_t)prime * N + t0 + t;
-    double kb[8], ka[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      kb[k] = gload(jb.kb + ko + 512 * k);
-      ka[k] = gload(jb.ka + ko + 512 * k);
-    }
+  // the digit whose own limb this row is first (its values are the input's, not transformed), so that
+  // its loads do not overlap live accumulators; the sums are exact, so the digit order changes no bit
+  if (own >= 0 && own < D) {
+    const size_t ko = (size_t)own * key_ds + (size_t)prime * N + t0 + t;
     double x[8];
-    if (j == own) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) x[k] = gload(jb.in + (size_t)o * N + t0 + t + 512 * k);
-      if (jb.in_b != nullptr) {
-        double xb[8];
+    for (int k = 0; k < 8; ++k) x[k] = gload(jb.in + (size_t)o * N + t0 + t + 512 * k);
+    if (jb.in_b != nullptr) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) xb[k] = gload(jb.in_b + (size_t)o * N + t0 + t + 512 * k);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = mod_mul(x[k], xb[k], pr.q, pr.qinv);
-      }
-    } else {
-      row4_fwd_tile(jb.ext + ((size_t)j * nE + o) * N + t0, t0, S1, pr, sh, x);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) x[k] = reduce_sym(x[k], pr.q, pr.qinv);
+      for (int k = 0; k < 8; ++k)
+        x[k] = mod_mul(x[k], gload(jb.in_b + (size_t)o * N + t0 + t + 512 * k), pr.q, pr.qinv);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      a0[k] += mul_lazy(x[k], kb[k], pr.q, pr.qinv);
-      a1[k] += mul_lazy(x[k], ka[k], pr.q, pr.qinv);
+      a0[k] = mul_lazy(x[k], gload(jb.kb + ko + 512 * k), pr.q, pr.qinv);
+      a1[k] = mul_lazy(x[k], gload(jb.ka + ko + 512 * k), pr.q, pr.qinv);
     }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
+  }
+  for (int j = 0; j < D; ++j) {   // uniform per workgroup
+    if (j == own) continue;
+    double x[8];
+    row4_fwd_tile(jb.ext + ((size_t)j * nE + o) * N + t0, t0, S1, pr, sh, x);
+    const size_t ko = (size_t)j * key_ds + (size_t)prime * N + t0 + t;
+    double kv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) kv[k] = gload(jb.kb + ko + 512 * k);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = reduce_sym(x[k], pr.q, pr.qinv);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a0[k] += mul_lazy(x[k], kv[k], pr.q, pr.qinv);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) kv[k] = gload(jb.ka + ko + 512 * k);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a1[k] += mul_lazy(x[k], kv[k], pr.q, pr.qinv);
   }
   if (jb.top != nullptr && o == nl - 1) {   // uniform: the addend's top limb, all loads issued together
     double u0[8], u1[8];
@@ -1998,13 +2006,14 @@ __global__ __launch_bounds__(512) void ks_inner_rows_kernel(KsPack jobs, int D, 
     // rows the ModDown transforms back (the special rows, and the top data row of a ModDown merged with
     // the switch): the inverse row pass of the tile here, as the separate row pass would run it
     double x[8];
+    lds_barrier();   // the tile buffer's previous use is over in every wave
+    row4_inv_tile(jb.acc + (size_t)o * N + t0, t0, S1, pr, sh, x, a0);   // src unread
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      lds_barrier();   // the tile buffer's previous use is over in every wave
-      row4_inv_tile(jb.acc + (size_t)o * N + t0, t0, S1, pr, sh, x, h == 0 ? a0 : a1);   // src unread
+    for (int k = 0; k < 8; ++k) a0[k] = reduce_sym(x[k], pr.q, pr.qinv);
+    lds_barrier();
+    row4_inv_tile(jb.acc + (size_t)o * N + t0, t0, S1, pr, sh, x, a1);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) (h == 0 ? a0 : a1)[k] = reduce_sym(x[k], pr.q, pr.qinv);
-    }
+    for (int k = 0; k < 8; ++k) a1[k] = reduce_sym(x[k], pr.q, pr.qinv);
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -2317,9 +2326,19 @@ void launch_md_finish2(Context& c, const std::vector<double*>& out, const std::v
 // are skipped by uniform branches.  The workgroups of one coefficient tile (all batch chunks and all
 // giant-group chunks) run back to back on one XCD, so a baby-step tile is fetched from HBM once and the
 // other chunks find it in that XCD's L2.  Sums are lazy (|term| < 0.91 q) and folded back with
-// reduce_sym every kRed baby steps.
+// reduce_sym every mm_fold_every(q) baby steps.
 // grid: x = (N / 64) x giant-group chunks of GM x ceil(G / 4) (XCD-aware, the batch chunk fastest), y = limbs.
 constexpr int kMmLanes = 64, kMmWaves = 4;
+
+// How many lazy terms a partial sum takes before it is folded back with reduce_sym, for the limb's prime q:
+// a folded sum is below q and every term below c q (c = 1.25 for an encrypted model's operands below 2q,
+// 0.91 for a plaintext model's below q), so after K terms a sum is below (1 + c K) q, kept below 2^52:
+// exact, and reduce_sym's quotient estimate is off by less than one.  Primes near 2^49 fold every 5 or 7
+// terms, primes below 2^42 every 64.
+__device__ __forceinline__ int mm_fold_every(double q, bool enc) {
+  const double k = (4503599627370496.0 / q - 1.0) / (enc ? 1.25 : 0.91);
+  return __builtin_amdgcn_readfirstlane(k >= 64.0 ? 64 : (k < 1.0 ? 1 : (int)k));
+}
 
 struct MmPlace {
   size_t i;    // coefficient
@@ -2346,8 +2365,7 @@ __device__ __forceinline__ MmPlace mm_place(int ng, int G, int wv) {
 
 // Encrypted diagonals (Karatsuba): acc = {sum x0 d0, sum (x0 + x1)(d0 + d1), sum x1 d1}; the middle sum
 // becomes sum (x0 d1 + x1 d0) = acc[1] - acc[0] - acc[2].  Every term is a lazy product of operands below 2q,
-// |term| < 1.25 q (the quotient estimate is off by at most 0.75 for products below 4 q^2 < 2^100); sums are
-// folded back with reduce_sym every kRed = 3 terms, so every partial sum stays far below 2^53 (exact).
+// |term| < 1.25 q (the quotient estimate is off by at most 0.75 for products below 4 q^2 < 2^100).
 __device__ __forceinline__ void mm_karatsuba_mid(double (&a)[3], double q, double qinv) {
   const double lo = reduce_sym(a[0], q, qinv), hi = reduce_sym(a[2], q, qinv);
   a[1] = reduce_sym(a[1], q, qinv) - lo - hi;
@@ -2365,7 +2383,6 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
                                                        int nl, size_t baby_slot, const DevPrime* P, int logN,
                                                        const double* b0, int u0) {
   constexpr int kNp = kEnc ? 3 : 2;
-  constexpr int kRed = kEnc ? 3 : 7;
   const size_t N = (size_t)1 << logN;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kMmLanes));
   const MmPlace m = mm_place<GM>(ng, 1, 0);
@@ -2375,6 +2392,7 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
   const int l = blockIdx.y;
   const int s0 = m.s0, gm = m.gm;
   const DevPrime& pr = P[l];
+  const int fold = mm_fold_every(pr.q, kEnc);
   const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
   double acc[GM][kNp];
 #pragma unroll
@@ -2417,7 +2435,7 @@ __global__ __launch_bounds__(256) void mm_inner_kernel(double* __restrict__ out,
         }
       }
     }
-    if (++cnt == kRed) {
+    if (++cnt == fold) {
       cnt = 0;
 #pragma unroll
       for (int s = 0; s < GM; ++s)
@@ -2467,7 +2485,6 @@ __global__ __launch_bounds__(64 * kW) void mm_inner_batch_kernel(double* __restr
                                                                  size_t baby_b, const DevPrime* P, int logN, Pack b0,
                                                                  int u0) {
   constexpr int kNp = kEnc ? 3 : 2, kNd = kEnc ? 2 : 1;
-  constexpr int kRed = kEnc ? 3 : 7;
   constexpr int kPer = (GM + kW - 1) / kW;   // groups of a tile one wave loads
   static_assert(GM <= 32, "one bit per group");
   __shared__ double dl[2][GM][kNd][kMmLanes];
@@ -2484,6 +2501,7 @@ __global__ __launch_bounds__(64 * kW) void mm_inner_batch_kernel(double* __restr
   // the prime and the table entries as scalar loads: a vector load's wait inside the products would
   // also wait for the next tile
   const DevPrime pr = cload_prime(P + l);
+  const int fold = mm_fold_every(pr.q, kEnc);
   const size_t o = (size_t)l * N + i, ps = (size_t)nl * N;
   // the first baby step at or after u with a term in the chunk (n_u if none) and its bitmask of groups
   auto scan = [&](int u, uint32_t& mask) -> int {
@@ -2575,7 +2593,7 @@ __global__ __launch_bounds__(64 * kW) void mm_inner_batch_kernel(double* __restr
           }
         }
       }
-      if (++cnt == kRed) {
+      if (++cnt == fold) {
         cnt = 0;
 #pragma unroll
         for (int s = 0; s < GM; ++s)
