@@ -1926,11 +1926,17 @@ __global__ __launch_bounds__(512, 4) void ks_inner_rows_kernel(KsPack jobs, int 
                                                                double ptop, int inv_from) {
   __shared__ double sh[kLdsTile4];
   const size_t N = (size_t)1 << logN;
-  const int o = blockIdx.y;
-  const KsJob2 jb = jobs.j[blockIdx.z];
+  // block order: the hardware deals consecutive workgroups to the eight XCDs in turn, so with the tile
+  // index fastest (N / 4096 tiles, a multiple of 8 from N = 32768) each XCD keeps to its tiles, and with
+  // the job next the jobs of one (tile, row), which read the same key tile, run together on one XCD and
+  // find it in its L2
+  const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned rest = lin / gridDim.x;
+  const int o = (int)(rest / gridDim.z);
+  const KsJob2 jb = jobs.j[rest % gridDim.z];
   const int prime = o < nl ? o : L + 1 + (o - nl);
   const DevPrime pr = P[prime];
-  const size_t t0 = (size_t)blockIdx.x * 4096;
+  const size_t t0 = (size_t)(lin % gridDim.x) * 4096;
   const int t = threadIdx.x;
   const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
   double a0[8], a1[8];
