@@ -20,7 +20,7 @@ workload (batched / plain), the CPU oracle's throughput on a bounded sample
 32-tree workload (1024 queries per step) and the one-query 16-tree workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--batch G] [--groups N] [--no-cpu-baseline] [--no-extras]
+                    [--batch G] [--groups N] [--no-cpu-baseline] [--no-extras] [--no-plain]
 """
 from __future__ import annotations
 
@@ -740,6 +740,9 @@ def main():
                     help="the unbatched path: each group alone, one homomorphic operation per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the c3 and c2 lines of the default run")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the unbatched comparison leg of the default run (counter runs: the timed steps' "
+                         "launches are then the run's last)")
     ap.add_argument("--graph", action="store_true",
                     help="replay the captured evaluation (HIP graph) instead of launching eagerly; on this "
                          "ROCm stack a replay costs about 1 us more per kernel than the eager launches")
@@ -780,7 +783,7 @@ def main():
     headline_default = args.workload == "c4_encmodel_64x_d8" and not (args.plain or args.graph)
     check = not args.no_cpu_baseline
     r = run_workload(w, args, args.steps, args.warmup, args.batch, args.groups,
-                     plain_groups=1 if headline_default else 0, check_labels=check)
+                     plain_groups=1 if headline_default and not args.no_plain else 0, check_labels=check)
     meta, prof, per_step = r["meta"], r["prof"], r["per_step"]
     n_groups, batch = r["n_groups"], r["batch"]
     steps = args.steps

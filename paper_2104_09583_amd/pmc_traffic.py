@@ -6,7 +6,8 @@ reference copy), scales each counter by what it reads for the reference copy
 of known size (bench.py ends with one copy of 256 MiB, read and written once),
 and writes, per kernel, the mean HBM bytes per dispatch over the dispatches of
 the timed steps (the last launches_per_step * steps dispatches, from the
-bench JSON line of the same run) beside the algorithmic bytes per dispatch
+bench JSON line of the same run; for the default workload bench.py runs with
+--no-plain, so that no other launches follow them) beside the algorithmic bytes per dispatch
 that bench.py measured, keyed by the sha256 of the kernel source so that a
 stale summary is not used.
 
