@@ -93,6 +93,9 @@ __device__ __forceinline__ DevPrime cload_prime(const DevPrime* p) {
 // before it (the next round's twiddles, an epilogue's operands) stay in flight across it.  The memory
 // clobber keeps the compiler from moving LDS accesses across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// An LDS exchange among the lanes of one wave: its writes are complete before its next reads are issued
+// (no other wave takes part, so no workgroup barrier)
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // ------------------------------------------------------------------ automorphism (evaluation domain)
 // Slot k holds a(psi^e) with e = 2 bitrev(k) + 1.  sigma_g(a)(psi^e) = a(psi^(g e)), so the
@@ -505,7 +508,7 @@ __device__ __forceinline__ void row4_fwd_tile(const double* __restrict__ src, si
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jB + 64 * k)] = x[k];
-  lds_barrier();
+  lds_wave_sync();   // rounds B and C touch the same 512 elements of this wave's block
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
   if (pre != nullptr) {
@@ -516,7 +519,7 @@ __device__ __forceinline__ void row4_fwd_tile(const double* __restrict__ src, si
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
-  lds_barrier();
+  lds_wave_sync();   // and so do rounds C and D
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jD + k)];
   radix8_ct_w(x, wd, pr);
@@ -546,7 +549,7 @@ __device__ __forceinline__ void row4_inv_tile(const double* __restrict__ src, si
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jD + k)] = x[k];
-  lds_barrier();
+  lds_wave_sync();   // rounds D and C touch the same 512 elements of this wave's block
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jC + 8 * k)];
   radix8_gs_w(x, wc, pr);
@@ -554,7 +557,7 @@ __device__ __forceinline__ void row4_inv_tile(const double* __restrict__ src, si
   red8(x, pr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) sh[lds_idx(jC + 8 * k)] = x[k];
-  lds_barrier();
+  lds_wave_sync();   // and so do rounds C and B
 #pragma unroll
   for (int k = 0; k < 8; ++k) x[k] = sh[lds_idx(jB + 64 * k)];
   radix8_gs_w(x, wb, pr);
