@@ -1932,10 +1932,11 @@ __global__ __launch_bounds__(512, 4) void ks_inner_rows_kernel(KsPack jobs, int 
   // block order: the hardware deals consecutive workgroups to the eight XCDs in turn, so with the tile
   // index fastest (N / 4096 tiles, a multiple of 8 from N = 32768) each XCD keeps to its tiles, and with
   // the job next the jobs of one (tile, row), which read the same key tile, run together on one XCD and
-  // find it in its L2
+  // find it in its L2; rows from the last, so that the special rows (three transforms and two inverse
+  // ones against two) start first instead of forming the launch's tail
   const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const unsigned rest = lin / gridDim.x;
-  const int o = (int)(rest / gridDim.z);
+  const int o = (int)gridDim.y - 1 - (int)(rest / gridDim.z);
   const KsJob2 jb = jobs.j[rest % gridDim.z];
   const int prime = o < nl ? o : L + 1 + (o - nl);
   const DevPrime pr = P[prime];
