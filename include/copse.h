@@ -401,8 +401,8 @@ int copse_poly_mul(copse_ctx* ctx, int prime, const uint64_t* a, const uint64_t*
 /* When on, the library brackets each launch of the named kernel class with
  * HIP events on the launching stream and accumulates the launch count, the
  * durations and the algorithmic bytes (every input and output row of the
- * operation read or written once; key rows counted per key-switch job;
- * twiddle tables not counted).  kind: 0 = forward NTT row pass, 1 = forward
+ * operation read or written once; each distinct key's rows counted once per
+ * launch; twiddle tables not counted).  kind: 0 = forward NTT row pass, 1 = forward
  * NTT column pass (unfused path), 2 = inverse NTT row pass, 3 = inverse NTT
  * column pass (unfused path), 4 = key-switch inner product, 5 = base
  * conversion (fused with the column passes where available), 6 = other
