@@ -570,6 +570,156 @@ __device__ __forceinline__ void row4_inv_tile(const double* __restrict__ src, si
   radix8_gs_w(x, wa, pr);
 }
 
+// Two tiles of one row pass at once (the same prime and tile position, so the same twiddles): the rounds of
+// both run between the same exchanges, so a workgroup waits at half the barriers per tile and has twice the
+// independent work between them.  sh and sh2: one tile buffer each.  The forward pair reads srcA[t + 512 k]
+// and srcB[t + 512 k]; the inverse pair takes the tiles' values at t + 512 k in va and vb.  Results as for
+// one tile, in x and y.
+__device__ __forceinline__ void row4_fwd_tile2(const double* __restrict__ srcA, const double* __restrict__ srcB,
+                                               size_t gb0, int S1, const DevPrime& pr, double* sh, double* sh2,
+                                               double x[8], double y[8]) {
+  const int t = threadIdx.x;
+  const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
+  const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
+  const Tw8 wa = tw8_load(pr.fwd, gb0 + jA, 512, mA);
+  const Tw8 wb = tw8_load(pr.fwd, gb0 + jB, 64, mB);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = gload(srcA + jA + 512 * k);
+    y[k] = gload(srcB + jA + 512 * k);
+  }
+  radix8_ct_w(x, wa, pr);
+  radix8_ct_w(y, wa, pr);
+  const Tw8 wc = tw8_load(pr.fwd, gb0 + jC, 8, mC);
+  red8(x, pr);
+  red8(y, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jA + 512 * k)] = x[k];
+    sh2[lds_idx(jA + 512 * k)] = y[k];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jB + 64 * k)];
+    y[k] = sh2[lds_idx(jB + 64 * k)];
+  }
+  radix8_ct_w(x, wb, pr);
+  radix8_ct_w(y, wb, pr);
+  const Tw8 wd = tw8_load(pr.fwd, gb0 + jD, 1, mD);
+  red8(x, pr);
+  red8(y, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jB + 64 * k)] = x[k];
+    sh2[lds_idx(jB + 64 * k)] = y[k];
+  }
+  lds_wave_sync();   // rounds B and C touch the same 512 elements of this wave's block
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jC + 8 * k)];
+    y[k] = sh2[lds_idx(jC + 8 * k)];
+  }
+  radix8_ct_w(x, wc, pr);
+  radix8_ct_w(y, wc, pr);
+  red8(x, pr);
+  red8(y, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jC + 8 * k)] = x[k];
+    sh2[lds_idx(jC + 8 * k)] = y[k];
+  }
+  lds_wave_sync();   // and so do rounds C and D
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jD + k)];
+    y[k] = sh2[lds_idx(jD + k)];
+  }
+  radix8_ct_w(x, wd, pr);
+  radix8_ct_w(y, wd, pr);
+  // each thread overwrites only the LDS words it just read
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jD + k)] = x[k];
+    sh2[lds_idx(jD + k)] = y[k];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jA + 512 * k)];
+    y[k] = sh2[lds_idx(jA + 512 * k)];
+  }
+}
+
+__device__ __forceinline__ void row4_inv_tile2(size_t gb0, int S1, const DevPrime& pr, double* sh, double* sh2,
+                                               const double va[8], const double vb[8], double x[8], double y[8]) {
+  const int t = threadIdx.x;
+  const size_t mA = (size_t)1 << S1, mB = mA << 3, mC = mA << 6, mD = mA << 9;
+  const int jA = t, jB = (t >> 6) * 512 + (t & 63), jC = (t >> 3) * 64 + (t & 7), jD = 8 * t;
+  const Tw8 wd = tw8_load(pr.inv, gb0 + jD, 1, mD);
+  const Tw8 wc = tw8_load(pr.inv, gb0 + jC, 8, mC);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jA + 512 * k)] = va[k];
+    sh2[lds_idx(jA + 512 * k)] = vb[k];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jD + k)];
+    y[k] = sh2[lds_idx(jD + k)];
+  }
+  radix8_gs_w(x, wd, pr);
+  radix8_gs_w(y, wd, pr);
+  const Tw8 wb = tw8_load(pr.inv, gb0 + jB, 64, mB);
+  red8(x, pr);
+  red8(y, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jD + k)] = x[k];
+    sh2[lds_idx(jD + k)] = y[k];
+  }
+  lds_wave_sync();   // rounds D and C touch the same 512 elements of this wave's block
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jC + 8 * k)];
+    y[k] = sh2[lds_idx(jC + 8 * k)];
+  }
+  radix8_gs_w(x, wc, pr);
+  radix8_gs_w(y, wc, pr);
+  const Tw8 wa = tw8_load(pr.inv, gb0 + jA, 512, mA);
+  red8(x, pr);
+  red8(y, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jC + 8 * k)] = x[k];
+    sh2[lds_idx(jC + 8 * k)] = y[k];
+  }
+  lds_wave_sync();   // and so do rounds C and B
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jB + 64 * k)];
+    y[k] = sh2[lds_idx(jB + 64 * k)];
+  }
+  radix8_gs_w(x, wb, pr);
+  radix8_gs_w(y, wb, pr);
+  red8(x, pr);
+  red8(y, pr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sh[lds_idx(jB + 64 * k)] = x[k];
+    sh2[lds_idx(jB + 64 * k)] = y[k];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = sh[lds_idx(jA + 512 * k)];
+    y[k] = sh2[lds_idx(jA + 512 * k)];
+  }
+  radix8_gs_w(x, wa, pr);
+  radix8_gs_w(y, wa, pr);
+}
+
 template <bool kInverse>
 __global__ __launch_bounds__(512) void ntt_rowreg4_kernel(double* __restrict__ base, const int2* __restrict__ rows,
                                                          const DevPrime* __restrict__ P, int logN, int S1, int scale) {
@@ -1921,13 +2071,15 @@ void launch_ks_inner2(Context& c, const std::vector<KsJob2>& jobs, int D, int nE
 // them after the column stages; a digit's own limbs come from the input in NTT form, a product's formed
 // from both operands) and accumulates digit x key in registers, so the extended rows are never written in
 // NTT form.  Rows o >= inv_from (the rows the ModDown transforms back) leave after the inverse row pass.
-// At most 128 registers (four waves per SIMD), so that two workgroups share a compute unit and one
-// transforms while the other waits on memory: hence the keys are read after each transform, one
-// polynomial at a time.
+// At most 128 registers (four waves per SIMD) and two tile buffers (68 KiB), so that two workgroups share a
+// compute unit and one transforms while the other waits on memory: the first two digits to transform run
+// as one pair (row4_fwd_tile2) before any sum is live, further digits one at a time, the row's own digit
+// last; the keys are read after each transform, one polynomial at a time; the two sums' inverse row passes
+// run as one pair.
 __global__ __launch_bounds__(512, 4) void ks_inner_rows_kernel(KsPack jobs, int D, int nE, int nl, int L, int alpha,
                                                                int logN, int S1, size_t key_ds, const DevPrime* P,
                                                                double ptop, int inv_from) {
-  __shared__ double sh[kLdsTile4];
+  __shared__ double sh[kLdsTile4], sh2[kLdsTile4];
   const size_t N = (size_t)1 << logN;
   // block order: the hardware deals consecutive workgroups to the eight XCDs in turn, so with the tile
   // index fastest (N / 4096 tiles, a multiple of 8 from N = 32768) each XCD keeps to its tiles, and with
@@ -1944,31 +2096,9 @@ __global__ __launch_bounds__(512, 4) void ks_inner_rows_kernel(KsPack jobs, int 
   const int t = threadIdx.x;
   const int own = o < nl ? o / alpha : -1;   // digit whose own limb this row is
   double a0[8], a1[8];
-  // the digit whose own limb this row is first (its values are the input's, not transformed), so that
-  // its loads do not overlap live accumulators; the sums are exact, so the digit order changes no bit
-  if (own >= 0 && own < D) {
-    const size_t ko = (size_t)own * key_ds + (size_t)prime * N + t0 + t;
-    double x[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = gload(jb.in + (size_t)o * N + t0 + t + 512 * k);
-    if (jb.in_b != nullptr) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        x[k] = mod_mul(x[k], gload(jb.in_b + (size_t)o * N + t0 + t + 512 * k), pr.q, pr.qinv);
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      a0[k] = mul_lazy(x[k], gload(jb.kb + ko + 512 * k), pr.q, pr.qinv);
-      a1[k] = mul_lazy(x[k], gload(jb.ka + ko + 512 * k), pr.q, pr.qinv);
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
-  }
-  for (int j = 0; j < D; ++j) {   // uniform per workgroup
-    if (j == own) continue;
-    double x[8];
-    row4_fwd_tile(jb.ext + ((size_t)j * nE + o) * N + t0, t0, S1, pr, sh, x);
+  // digit j's tile x times its key values, added to the sums (the keys read after x is ready, one
+  // polynomial at a time)
+  auto mac = [&](int j, double(&x)[8]) {
     const size_t ko = (size_t)j * key_ds + (size_t)prime * N + t0 + t;
     double kv[8];
 #pragma unroll
@@ -1981,6 +2111,51 @@ __global__ __launch_bounds__(512, 4) void ks_inner_rows_kernel(KsPack jobs, int 
     for (int k = 0; k < 8; ++k) kv[k] = gload(jb.ka + ko + 512 * k);
 #pragma unroll
     for (int k = 0; k < 8; ++k) a1[k] += mul_lazy(x[k], kv[k], pr.q, pr.qinv);
+  };
+  auto ext = [&](int j) { return jb.ext + ((size_t)j * nE + o) * N + t0; };
+  // the first two digits to transform (not the row's own) as one pair, before any sum is live; the sums
+  // are exact, so the digit order changes no bit
+  int j = own == 0 ? 1 : 0, jn = D;   // jn: the first digit left after the pair
+  if (j < D) {
+    int j2 = j + 1;
+    if (j2 == own) ++j2;
+    if (j2 < D) {
+      double x[8], y[8];
+      row4_fwd_tile2(ext(j), ext(j2), t0, S1, pr, sh, sh2, x, y);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
+      mac(j, x);
+      mac(j2, y);
+      jn = j2 + 1;
+    } else {
+      double x[8];
+      row4_fwd_tile(ext(j), t0, S1, pr, sh, x);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
+      mac(j, x);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a0[k] = a1[k] = 0.0;
+  }
+  for (int jj = jn; jj < D; ++jj) {   // any further digit one at a time (uniform per workgroup)
+    if (jj == own) continue;
+    double x[8];
+    row4_fwd_tile(ext(jj), t0, S1, pr, sh, x);
+    mac(jj, x);
+  }
+  // the digit whose own limb this row is: its values are the input's in NTT form (a product's: formed
+  // from both operands), not transformed
+  if (own >= 0) {
+    double x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = gload(jb.in + (size_t)o * N + t0 + t + 512 * k);
+    if (jb.in_b != nullptr) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        x[k] = mod_mul(x[k], gload(jb.in_b + (size_t)o * N + t0 + t + 512 * k), pr.q, pr.qinv);
+    }
+    mac(own, x);
   }
   if (jb.top != nullptr && o == nl - 1) {   // uniform: the addend's top limb, all loads issued together
     double u0[8], u1[8];
@@ -2014,16 +2189,15 @@ __global__ __launch_bounds__(512, 4) void ks_inner_rows_kernel(KsPack jobs, int 
   }
   if (o >= inv_from) {
     // rows the ModDown transforms back (the special rows, and the top data row of a ModDown merged with
-    // the switch): the inverse row pass of the tile here, as the separate row pass would run it
-    double x[8];
-    lds_barrier();   // the tile buffer's previous use is over in every wave
-    row4_inv_tile(jb.acc + (size_t)o * N + t0, t0, S1, pr, sh, x, a0);   // src unread
+    // the switch): the inverse row pass of both sums' tiles here, as the separate row pass would run it
+    double x[8], y[8];
+    lds_barrier();   // the tile buffers' previous use is over in every wave
+    row4_inv_tile2(t0, S1, pr, sh, sh2, a0, a1, x, y);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a0[k] = reduce_sym(x[k], pr.q, pr.qinv);
-    lds_barrier();
-    row4_inv_tile(jb.acc + (size_t)o * N + t0, t0, S1, pr, sh, x, a1);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a1[k] = reduce_sym(x[k], pr.q, pr.qinv);
+    for (int k = 0; k < 8; ++k) {
+      a0[k] = reduce_sym(x[k], pr.q, pr.qinv);
+      a1[k] = reduce_sym(y[k], pr.q, pr.qinv);
+    }
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
