@@ -332,6 +332,15 @@ def cpu_baseline(w, text, queries, seed, all_cores: bool = True):
                             "sample": f"the same sample in {P} processes at once ({wall:.1f}s wall); rate = sum of "
                                       "the processes' extrapolated rates",
                             "seconds_per_group_mean": round(sum(s for s, _ in res) / P, 2)}
+    # for context: the plaintext forest walk on the same queries (no encryption), one thread
+    from oracle import forest as F
+    _, trees = F.parse_forest(text)
+    t0 = time.perf_counter()
+    for x in queries:
+        F.evaluate(trees, list(x))
+    walk = time.perf_counter() - t0
+    out["plain_forest"] = {"value": len(queries) / walk, "unit": "queries/s", "cores": 1,
+                           "sample": f"the oracle's plaintext tree walk over the workload's {len(queries)} queries"}
     return out
 
 
