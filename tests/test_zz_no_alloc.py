@@ -72,6 +72,34 @@ def test_noalloc_equals_evaluate_two_calls():
     assert all((a == b).all() for a, b in zip(got[1], want[1]))
 
 
+def test_noalloc_encrypted_model_equals_evaluate():
+    """An encrypted model (thresholds, diagonals and masks encrypted: the Karatsuba MatMul and the
+    comparison's products) through the no-allocation entry point: bit-identical to copse_evaluate, twice."""
+    from paper_2104_09583_amd import copse as C
+    shape = synth.ForestShape(4, 4, 0.8, 3, 4, 3)
+    log_n = 13
+    oc = OC.compile_forest(synth.gen_forest_text(shape, 63), 3, 4)
+    need = CI.seccomp_depth(4) + 2 + math.ceil(math.log2(max(2, oc.d)))
+    ctx = C.Context(log_n, need + 1, 1 << 49, 1 << 42, 3, 1 << 49)
+    kseed = b"\x53" * 32
+    text, comp, meta, keys = _setup(C, ctx, shape, 63, kseed, log_n)
+    evk = ctx.export_eval(keys)
+    model = ctx.model_encode(comp, keys, encrypt=True, seed=kseed)
+    q = synth.gen_queries(meta.queries_per_ct, shape.n_features, shape.precision, 803)
+    qct = ctx.query_encrypt(keys, meta, q, kseed, group=0)
+    want = _bits(ctx, ctx.evaluate(model, evk, qct))
+    result = ctx.evaluate(model, evk, qct)
+    for rep in range(2):
+        say("no-alloc encrypted model, call", rep)
+        ctx.evaluate_noalloc(model, evk, qct, result)
+        got = _bits(ctx, result)
+        assert got[0] == want[0] == 0
+        assert all((a == b).all() for a, b in zip(got[1], want[1])), f"call {rep}"
+    _, trees = F.parse_forest(text)
+    bits = ctx.decrypt_labels(keys, meta, result, len(q))
+    assert (bits == np.array([F.evaluate(trees, list(x)) for x in q])).all()
+
+
 def test_noalloc_rejects_wrong_result_handle():
     from paper_2104_09583_amd import copse as C
     shape = synth.ForestShape(2, 3, 0.7, 3, 4, 2)
